@@ -1,0 +1,265 @@
+/*
+ * CPU ORACLE for block-partitioned triangle counting -- TEST INFRASTRUCTURE.
+ *
+ * This file is the parity checker for the GPU library, not part of it.  Only
+ * the tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header or table with the HIP sources.
+ *
+ * What it computes (PGAbB, Section 3.6, "An example: triangle counting"):
+ * the number of sets of three vertices of an undirected graph that are
+ * pairwise adjacent.  The input is made undirected and deduplicated first
+ * (Section 5.1, Dataset); self-loops are dropped as well.
+ *
+ * The count is the plain definition evaluated with the standard oriented
+ * formulation the paper uses for TC (Section 5.4: degree-based vertex
+ * ordering, and only half of the edges are needed):
+ *   1. keep every undirected pair {a, b}, a != b, once;
+ *   2. deg[v] = number of kept pairs containing v;
+ *   3. rank vertices by ascending (deg, id) (or by id in the second mode);
+ *   4. orient each pair from lower to higher rank: N+(x) = out-neighbours;
+ *   5. T = sum over x, over y in N+(x), of |N+(x) & N+(y)|, by two-pointer
+ *      merge of the sorted lists.
+ * Each triangle with ranks r(a) < r(b) < r(c) is counted once, at edge (a, b)
+ * with common neighbour c, so T is the triangle count.
+ *
+ * Block mode (Section 3.6, block-list composition and kernel development;
+ * Section 4.3, symmetric 2-D partitioning): with cut vector
+ * c_0 = 0 <= c_1 <= ... <= c_p = n applied to the ranked ids on both axes,
+ * T_ijk counts the triangles whose three ranked vertices fall in stripes
+ * i <= j <= k.  That is exactly what the triple (A_ij, A_ik, A_jk) finds:
+ * for every edge (u, v) of block A_ij, the common out-neighbours of u and v
+ * that lie in stripe k.  Here it is computed by the definition: merge the full
+ * lists and bin every common neighbour by its stripe.
+ *
+ * Precision: all integer; counts in uint64.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- helpers */
+
+static int cmp_u64(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return (a > b) - (a < b);
+}
+
+static int cmp_i32(const void *pa, const void *pb)
+{
+    int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Step 1: canonical undirected pairs.  keys_out must hold m entries; returns
+ * the number of distinct pairs m' (written sorted, key = min << 32 | max), or
+ * -1 if an id lies outside [0, n). */
+int64_t oracle_clean(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     uint64_t *keys_out)
+{
+    int64_t k = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t a = src[e], b = dst[e];
+        if (a < 0 || b < 0 || a >= n || b >= n) return -1;
+        if (a == b) continue; /* self-loop */
+        uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+        keys_out[k++] = ((uint64_t)lo << 32) | hi;
+    }
+    qsort(keys_out, (size_t)k, sizeof(uint64_t), cmp_u64);
+    int64_t u = 0;
+    for (int64_t e = 0; e < k; ++e)
+        if (u == 0 || keys_out[u - 1] != keys_out[e]) keys_out[u++] = keys_out[e];
+    return u;
+}
+
+/* Step 2: degree of every vertex in the simple undirected graph. */
+void oracle_degrees(int32_t n, const uint64_t *keys, int64_t mu, int32_t *deg)
+{
+    memset(deg, 0, sizeof(int32_t) * (size_t)n);
+    for (int64_t e = 0; e < mu; ++e) {
+        deg[keys[e] >> 32]++;
+        deg[keys[e] & 0xffffffffu]++;
+    }
+}
+
+/* Step 3: rank[v] = position of v in the order.  mode 0: ascending
+ * (deg, id); mode 1: ascending id (rank = id). */
+static const int32_t *g_sort_deg;
+static int cmp_by_deg_then_id(const void *pa, const void *pb)
+{
+    int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+    if (g_sort_deg[a] != g_sort_deg[b]) return g_sort_deg[a] < g_sort_deg[b] ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+void oracle_rank(int32_t n, const int32_t *deg, int mode, int32_t *rank)
+{
+    if (mode == 1) {
+        for (int32_t v = 0; v < n; ++v) rank[v] = v;
+        return;
+    }
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t v = 0; v < n; ++v) order[v] = v;
+    g_sort_deg = deg;
+    qsort(order, (size_t)n, sizeof(int32_t), cmp_by_deg_then_id);
+    for (int32_t r = 0; r < n; ++r) rank[order[r]] = r;
+    free(order);
+}
+
+/* Step 4: oriented CSR over ranked ids.  Row x (a rank) lists, in increasing
+ * order, the ranks of its neighbours that have a higher rank.  row_off has
+ * n + 1 entries, col has mu entries. */
+void oracle_orient(int32_t n, const uint64_t *keys, int64_t mu, const int32_t *rank,
+                   int64_t *row_off, int32_t *col)
+{
+    memset(row_off, 0, sizeof(int64_t) * ((size_t)n + 1));
+    for (int64_t e = 0; e < mu; ++e) {
+        int32_t ra = rank[keys[e] >> 32], rb = rank[keys[e] & 0xffffffffu];
+        int32_t lo = ra < rb ? ra : rb;
+        row_off[lo + 1]++;
+    }
+    for (int32_t x = 0; x < n; ++x) row_off[x + 1] += row_off[x];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    memcpy(fill, row_off, sizeof(int64_t) * (size_t)n);
+    for (int64_t e = 0; e < mu; ++e) {
+        int32_t ra = rank[keys[e] >> 32], rb = rank[keys[e] & 0xffffffffu];
+        int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        col[fill[lo]++] = hi;
+    }
+    free(fill);
+    for (int32_t x = 0; x < n; ++x)
+        qsort(col + row_off[x], (size_t)(row_off[x + 1] - row_off[x]), sizeof(int32_t), cmp_i32);
+}
+
+/* |A & B| of two increasing lists by two-pointer merge. */
+static uint64_t merge_count(const int32_t *a, int64_t na, const int32_t *b, int64_t nb)
+{
+    uint64_t c = 0;
+    int64_t i = 0, j = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else { ++c; ++i; ++j; }
+    }
+    return c;
+}
+
+/* Step 5: T = sum over oriented edges (x, y) of |N+(x) & N+(y)|.  Rows are
+ * independent, so an OpenMP build may split them across threads (the sum of
+ * integers does not depend on the order). */
+uint64_t oracle_count(int32_t n, const int64_t *row_off, const int32_t *col)
+{
+    uint64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t *nx = col + row_off[x];
+        int64_t dx = row_off[x + 1] - row_off[x];
+        for (int64_t t = 0; t < dx; ++t) {
+            int32_t y = nx[t];
+            total += merge_count(nx, dx, col + row_off[y], row_off[y + 1] - row_off[y]);
+        }
+    }
+    return total;
+}
+
+/* Number of oracle threads an OpenMP build uses (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
+#else
+int oracle_threads(void) { return 1; }
+void oracle_set_threads(int t) { (void)t; }
+#endif
+
+/* Stripe of ranked vertex x under cut vector cuts[0..p] (the largest s with
+ * cuts[s] <= x, restricted to s < p). */
+static int32_t stripe_of(int32_t x, int32_t p, const int32_t *cuts)
+{
+    int32_t lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) / 2;
+        if (cuts[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* Block mode: out[(i * p + j) * p + k] = T_ijk (zero unless i <= j <= k).
+ * cuts must be non-decreasing with cuts[0] = 0 and cuts[p] = n.  Returns -1
+ * on a bad cut vector. */
+int oracle_block_counts(int32_t n, const int64_t *row_off, const int32_t *col,
+                        int32_t p, const int32_t *cuts, uint64_t *out)
+{
+    if (p < 1 || cuts[0] != 0 || cuts[p] != n) return -1;
+    for (int32_t s = 0; s < p; ++s)
+        if (cuts[s] > cuts[s + 1]) return -1;
+    memset(out, 0, sizeof(uint64_t) * (size_t)p * p * p);
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t *nu = col + row_off[u];
+        int64_t du = row_off[u + 1] - row_off[u];
+        int32_t si = stripe_of(u, p, cuts);
+        for (int64_t t = 0; t < du; ++t) {
+            int32_t v = nu[t];
+            int32_t sj = stripe_of(v, p, cuts);
+            const int32_t *nv = col + row_off[v];
+            int64_t dv = row_off[v + 1] - row_off[v];
+            int64_t a = 0, b = 0;
+            while (a < du && b < dv) {
+                if (nu[a] < nv[b]) ++a;
+                else if (nu[a] > nv[b]) ++b;
+                else {
+                    int32_t sk = stripe_of(nu[a], p, cuts);
+                    out[((size_t)si * p + sj) * p + sk]++;
+                    ++a; ++b;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* Whole pipeline: clean, degree, rank (mode), orient, count.  Returns
+ * UINT64_MAX on an out-of-range id or allocation failure.  If mu_out is not
+ * NULL it receives m'. */
+uint64_t oracle_tc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int mode,
+                   int64_t *mu_out)
+{
+    if (n < 0 || m < 0) return UINT64_MAX;
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *row_off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!keys || !deg || !rank || !row_off) {
+        free(keys); free(deg); free(rank); free(row_off);
+        return UINT64_MAX;
+    }
+    int64_t mu = oracle_clean(n, m, src, dst, keys);
+    uint64_t t = UINT64_MAX;
+    if (mu >= 0) {
+        int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(mu > 0 ? mu : 1));
+        if (col) {
+            oracle_degrees(n, keys, mu, deg);
+            oracle_rank(n, deg, mode, rank);
+            oracle_orient(n, keys, mu, rank, row_off, col);
+            t = oracle_count(n, row_off, col);
+            free(col);
+        }
+        if (mu_out) *mu_out = mu;
+    }
+    free(keys); free(deg); free(rank); free(row_off);
+    return t;
+}
+
+/* Probe work of the oriented formulation: W = sum over oriented edges (x, y)
+ * of |N+(y)|, the number of list elements a merge streams from the second
+ * list.  Used to state the algorithmic bytes of a count, not the count. */
+uint64_t oracle_probe_work(int32_t n, const int64_t *row_off, const int32_t *col)
+{
+    uint64_t w = 0;
+    for (int32_t x = 0; x < n; ++x)
+        for (int64_t t = row_off[x]; t < row_off[x + 1]; ++t) {
+            int32_t y = col[t];
+            w += (uint64_t)(row_off[y + 1] - row_off[y]);
+        }
+    return w;
+}

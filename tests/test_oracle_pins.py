@@ -1,0 +1,255 @@
+"""Pins of the CPU oracle against results fixed by mathematics or computed by
+independent software: brute force on tiny graphs, closed forms, networkx,
+the sparse and dense matrix identities T = sum(A o A^2) / 6, and invariances.
+
+The oracle follows PGAbB Section 3.6 (problem and per-edge common-neighbour
+count over a block-list), Section 5.1 (undirected, deduplicated inputs) and
+Section 5.4 (degree ordering, oriented half of the edges).
+"""
+import itertools
+import json
+import math
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_2209_04541_amd import gen
+from tests import graphs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def nx_count(n, src, dst):
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from((int(a), int(b)) for a, b in zip(src, dst) if a != b)
+    return sum(nx.triangles(G).values()) // 3
+
+
+def sparse_identity(n, src, dst):
+    """T = sum(A o (A @ A)) / 6 with scipy sparse integer matrices."""
+    keep = src != dst
+    s = np.concatenate([src[keep], dst[keep]]).astype(np.int64)
+    d = np.concatenate([dst[keep], src[keep]]).astype(np.int64)
+    A = sp.coo_matrix((np.ones(len(s), np.int64), (s, d)), shape=(n, n)).tocsr()
+    A.data[:] = 1  # duplicates summed above; make it 0/1
+    A.sum_duplicates()
+    A.data[:] = 1
+    return int((A.multiply(A @ A)).sum()) // 6
+
+
+# ------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("name,g,expected", graphs.closed_forms(), ids=lambda x: x if isinstance(x, str) else "")
+def test_closed_forms(name, g, expected):
+    n, s, d = g
+    assert oracle.tc(n, s, d) == expected
+    assert oracle.tc(n, s, d, mode=1) == expected
+    n2, s2, d2 = graphs.messy(n, s, d, seed=len(name))
+    assert oracle.tc(n2, s2, d2) == expected
+
+
+def test_closed_form_helpers_are_right():
+    # the helper graphs themselves, checked by brute force where small
+    for name, (n, s, d), expected in graphs.closed_forms():
+        if n <= 40:
+            assert graphs.brute_force(n, s, d) == expected, name
+
+
+# ------------------------------------------------------------- brute force
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(0, 40), st.floats(0.0, 1.0), st.integers(0, 2**31 - 1))
+def test_brute_force_random(n, density, seed):
+    rng = np.random.default_rng(seed)
+    m = int(density * n * n)
+    s = rng.integers(0, max(n, 1), size=m).astype(np.int32) if n else np.zeros(0, np.int32)
+    d = rng.integers(0, max(n, 1), size=m).astype(np.int32) if n else np.zeros(0, np.int32)
+    want = graphs.brute_force(n, s, d)
+    assert oracle.tc(n, s, d) == want
+    assert oracle.tc(n, s, d, mode=1) == want
+
+
+# ----------------------------------------------------------- library pins
+
+@pytest.mark.parametrize("kind", ["er", "rgg", "rmat"])
+def test_networkx_and_sparse(kind):
+    if kind == "er":
+        n, s, d = gen.er(700, 9000, gen.seed(90, 1))
+    elif kind == "rgg":
+        n, s, d = gen.rgg(900, 30, gen.seed(90, 2))
+    else:
+        n, s, d = gen.rmat(11, 16, gen.seed(90, 3))
+    t = oracle.tc(n, s, d)
+    assert t == nx_count(n, s, d)
+    assert t == sparse_identity(n, s, d)
+
+
+def test_plain_workload_dense_identity():
+    """ER G(4096, 32768): dense A @ A in float32 is exact (entries <= 4096 <
+    2^24), so sum(A o A^2) / 6 is the exact count."""
+    n, s, d = gen.plain_graph()
+    A = np.zeros((n, n), dtype=np.float32)
+    A[s, d] = 1
+    A[d, s] = 1
+    np.fill_diagonal(A, 0)
+    A2 = A @ A
+    t_dense = int(np.rint((A.astype(np.float64) * A2).sum())) // 6
+    t = oracle.tc(n, s, d)
+    assert t == t_dense
+    assert t == nx_count(n, s, d)
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        gold = json.load(f)
+    assert gold["plain"]["triangles"] == t
+
+
+# ---------------------------------------------------------- the steps
+
+def test_clean_degrees_rank_against_numpy():
+    n, s, d = graphs.messy(*gen.rmat(10, 8, gen.seed(91, 0)), seed=3)
+    keys = oracle.clean(n, s, d)
+    lo = np.minimum(s, d).astype(np.uint64)
+    hi = np.maximum(s, d).astype(np.uint64)
+    keep = s != d
+    want = np.unique((lo[keep] << np.uint64(32)) | hi[keep])
+    assert np.array_equal(keys, want)
+    deg = oracle.degrees(n, keys)
+    ends = np.concatenate([(want >> np.uint64(32)).astype(np.int64), (want & np.uint64(0xFFFFFFFF)).astype(np.int64)])
+    assert np.array_equal(deg, np.bincount(ends, minlength=n))
+    rk = oracle.rank(n, deg, 0)
+    order = np.lexsort((np.arange(n), deg))  # ascending degree, then id
+    want_rank = np.empty(n, np.int64)
+    want_rank[order] = np.arange(n)
+    assert np.array_equal(rk, want_rank)
+    assert np.array_equal(oracle.rank(n, deg, 1), np.arange(n))
+
+
+def test_orient_properties():
+    n, s, d = gen.rmat(12, 16, gen.seed(91, 1))
+    keys, deg, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    assert row_off[0] == 0 and row_off[-1] == len(keys) == len(col)
+    rows = np.repeat(np.arange(n), np.diff(row_off))
+    assert np.all(col > rows)  # oriented low rank -> high rank
+    for x in range(n):  # each row strictly increasing
+        seg = col[row_off[x]:row_off[x + 1]]
+        assert np.all(np.diff(seg) > 0)
+    # same undirected edge set, in rank space
+    inv = np.empty(n, np.int64)
+    inv[rk] = np.arange(n)
+    a, b = inv[rows], inv[col]
+    got = np.sort((np.minimum(a, b).astype(np.uint64) << np.uint64(32)) | np.maximum(a, b).astype(np.uint64))
+    assert np.array_equal(got, keys)
+    # degree ordering bounds every out-degree by sqrt(2 m')
+    assert np.diff(row_off).max() <= math.isqrt(2 * len(keys)) + 1
+
+
+def test_probe_work_against_numpy():
+    n, s, d = gen.rmat(11, 8, gen.seed(91, 2))
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    od = np.diff(row_off)
+    assert oracle.probe_work(n, row_off, col) == int(od[col].sum())
+
+
+def _triangles_by_stripe(n, s, d, rk, cuts):
+    """Enumerate triangles with networkx and bin them by the stripes of their
+    ranked vertices."""
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from((int(a), int(b)) for a, b in zip(s, d) if a != b)
+    p = len(cuts) - 1
+    out = np.zeros((p, p, p), np.uint64)
+    stripe = np.searchsorted(np.asarray(cuts), np.arange(n), side="right") - 1
+    stripe = np.minimum(stripe, p - 1)
+    for clique in nx.enumerate_all_cliques(G):
+        if len(clique) < 3:
+            continue
+        if len(clique) > 3:
+            break
+        r = sorted(rk[v] for v in clique)
+        out[stripe[r[0]], stripe[r[1]], stripe[r[2]]] += 1
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 8])
+def test_block_counts(p):
+    n, s, d = gen.rmat(9, 12, gen.seed(92, p))
+    keys, deg, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    T = oracle.count_csr(n, row_off, col)
+    rng = np.random.default_rng(p)
+    inner = np.sort(rng.integers(0, n + 1, size=p - 1))
+    cuts = np.concatenate([[0], inner, [n]]).astype(np.int32)
+    B = oracle.block_counts(n, row_off, col, cuts)
+    assert int(B.sum()) == T
+    i, j, k = np.nonzero(B)
+    assert np.all(i <= j) and np.all(j <= k)
+    assert np.array_equal(B, _triangles_by_stripe(n, s, d, rk, cuts))
+
+
+def test_block_counts_rejects_bad_cuts():
+    n, s, d = graphs.complete(6)[0]
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    with pytest.raises(ValueError):
+        oracle.block_counts(n, row_off, col, [0, 4, 3, 6])
+    with pytest.raises(ValueError):
+        oracle.block_counts(n, row_off, col, [1, 3, 6])
+
+
+def test_out_of_range_ids():
+    with pytest.raises(ValueError):
+        oracle.tc(4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(ValueError):
+        oracle.tc(4, np.array([-1], np.int32), np.array([1], np.int32))
+
+
+def test_invariances():
+    n, s, d = gen.rmat(10, 16, gen.seed(93, 0))
+    t = oracle.tc(n, s, d)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(n).astype(np.int32)
+    assert oracle.tc(n, perm[s], perm[d]) == t  # vertex relabelling
+    o = rng.permutation(len(s))
+    assert oracle.tc(n, d[o], s[o]) == t  # pair order and direction
+    assert oracle.tc(n + 100, s, d) == t  # isolated vertices
+    assert oracle.tc(n, s, d, mode=1) == t  # id order instead of degree order
+
+
+def test_statistical_sanity_plain_workload():
+    """ER G(4096, 32768): E[T] = C(n,3) p^3 with p = m / C(n,2), about 683."""
+    n, s, d = gen.plain_graph()
+    t = oracle.tc(n, s, d)
+    pr = 32768 / math.comb(4096, 2)
+    mean = math.comb(4096, 3) * pr ** 3
+    assert abs(t - mean) < 6 * math.sqrt(mean) + 10
+
+
+def test_block_workload_sparse_identity():
+    """R-MAT scale 20 (the p = 8 workload): the stored oracle count equals
+    sum((U[r] @ U) o U[r]) over row chunks of the degree-oriented upper
+    matrix U, built here with numpy and multiplied with scipy."""
+    n, s, d = gen.block_graph()
+    keep = s != d
+    lo = np.minimum(s, d)[keep].astype(np.int64)
+    hi = np.maximum(s, d)[keep].astype(np.int64)
+    k = np.unique(lo * n + hi)
+    a, b = k // n, k % n
+    deg = np.bincount(np.concatenate([a, b]), minlength=n)
+    order = np.lexsort((np.arange(n), deg))
+    rk = np.empty(n, np.int64)
+    rk[order] = np.arange(n)
+    r0 = np.minimum(rk[a], rk[b])
+    r1 = np.maximum(rk[a], rk[b])
+    U = sp.csr_matrix((np.ones(len(r0), np.int64), (r0, r1)), shape=(n, n))
+    t = 0
+    for r in range(0, n, 1 << 16):
+        Ur = U[r:r + (1 << 16)]
+        t += int((Ur @ U).multiply(Ur).sum())
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        gold = json.load(f)["block"]
+    assert t == gold["triangles"]
+    assert len(k) == gold["m"]
+    assert int((deg == 0).sum()) == gold["isolated"]
