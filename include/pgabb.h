@@ -1,0 +1,281 @@
+/*
+ * pgabb.h -- C ABI of a block-partitioned triangle-counting library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the triangle-counting example of PGAbB (Yasar,
+ * Rajamanickam, Berry, Catalyurek, "PGAbB: A Block-Based Graph Processing
+ * Framework for Heterogeneous Platforms"): count the sets of three mutually
+ * adjacent vertices of an undirected graph (Section 3.6).  The graph is made
+ * undirected and deduplicated (Section 5.1), its vertices are ordered by
+ * degree and each edge is kept once, oriented from lower to higher rank
+ * (Section 5.4).  The oriented adjacency matrix is cut by one cut vector on
+ * both axes into a p x p grid of blocks (symmetric rectilinear partitioning,
+ * Section 4.3), and every block-list (A_ij, A_ik, A_jk), i <= j <= k, is a
+ * task: for each edge (u, v) of A_ij it counts the common entries of row u of
+ * A_ik and row v of A_jk (Section 3.6, block-list composition and kernel
+ * development).  Tasks are weighted by their edge count and run heaviest
+ * first (Section 4.1, Section 4.4).
+ *
+ * Conventions for every entry point:
+ *  - Vertex ids are int32 in [0, n); counts are uint64.
+ *  - Pointers are host pointers unless a flag or argument name says device.
+ *  - Input arrays are borrowed for the duration of the call and copied; the
+ *    caller keeps ownership.  Objects returned through an out-parameter are
+ *    owned by the caller and released with the matching *_destroy call.
+ *  - Every call returns a pgabb_status (pgabb_tc_count returns the count or
+ *    PGABB_COUNT_ERROR).  On failure the reason is available from
+ *    pgabb_last_error() on the same thread.  Argument errors are detected
+ *    before any device work starts.
+ *  - Self-loops, repeated pairs and reciprocal pairs are not errors: they
+ *    are removed, as the paper's inputs were made undirected and
+ *    deduplicated.  Isolated vertices are kept (n is never reduced).
+ *  - Calls on one object must not overlap in time; distinct objects may be
+ *    used from different threads.
+ */
+#ifndef PGABB_H
+#define PGABB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pgabb_status {
+    PGABB_OK = 0,
+    PGABB_EINVAL = -1,  /* bad argument: NULL, id out of range, bad p or cuts */
+    PGABB_ENOMEM = -2,  /* device or pinned host allocation failed */
+    PGABB_EDEVICE = -3, /* a HIP runtime call failed */
+    PGABB_ESTATE = -4,  /* call not valid in the object's current state */
+    PGABB_EBUDGET = -5  /* request does not fit a server's device budget */
+} pgabb_status;
+
+/* Returned by pgabb_tc_count on failure.  No real count reaches it: a graph
+ * with m' edges has at most (2 m')^{3/2} / 6 triangles, below 2^50 for any
+ * m' < 2^32. */
+#define PGABB_COUNT_ERROR UINT64_MAX
+
+/* Flags of pgabb_graph_from_edges. */
+#define PGABB_EDGES_ON_DEVICE 0x1u /* src/dst are device pointers */
+#define PGABB_ORDER_BY_ID     0x2u /* rank vertices by id instead of degree */
+
+/* Cut modes (pgabb_tc_options.cut_mode, pgabb_partition_ex). */
+#define PGABB_CUT_NNZ     0 /* stripes hold equal shares of oriented edges */
+#define PGABB_CUT_UNIFORM 1 /* stripes hold equal shares of vertex ids */
+
+/* Intersection kernels (pgabb_tc_options.kernel). */
+#define PGABB_KERNEL_AUTO   0 /* chosen per task from list lengths and widths */
+#define PGABB_KERNEL_HASH   1 /* staged row in an LDS hash table */
+#define PGABB_KERNEL_BITMAP 2 /* staged row in an LDS bitmap over the stripe */
+#define PGABB_KERNEL_SEARCH 3 /* binary search in the staged row (no staging) */
+
+/* Option flags. */
+#define PGABB_OPT_STREAM    0x1u /* force the host block store + streamer path */
+#define PGABB_OPT_PER_GRAPH 0x2u /* batch only: one plain launch per graph, in
+                                    order on one stream (the baseline that the
+                                    single persistent launch is measured
+                                    against) */
+#define PGABB_SERVER_BORROW 0x4u /* server only: submitted arrays are borrowed
+                                    until the request finishes, not copied */
+
+typedef struct pgabb_tc_options {
+    int32_t kernel;            /* PGABB_KERNEL_* */
+    int32_t num_streams;       /* compute streams of the streamer (0 = 4) */
+    uint64_t device_cap_bytes; /* 0 = no cap; otherwise block cache bound */
+    uint32_t flags;            /* PGABB_OPT_* */
+    int32_t waves_per_block;   /* 0 = library default */
+    int32_t rows_per_grab;     /* 0 = library default */
+} pgabb_tc_options;
+
+typedef struct pgabb_graph pgabb_graph;
+
+typedef struct pgabb_graph_info {
+    int64_t n;              /* vertices (as given) */
+    int64_t m_input;        /* input pairs */
+    int64_t m;              /* undirected distinct non-loop edges m' */
+    int64_t isolated;       /* vertices of degree 0 */
+    int32_t max_out_degree; /* largest oriented row */
+    int32_t p;              /* grid size (0 before partitioning) */
+    int64_t num_blocks;     /* non-empty blocks */
+    int64_t num_tasks;      /* block-lists with three non-empty blocks */
+    uint64_t probe_work;    /* sum over oriented edges (u,v) of |N+(v)| */
+    uint64_t block_bytes;   /* bytes of all block storage */
+    uint64_t h2d_bytes;     /* bytes copied host->device by the last count */
+    double t_build_ms;      /* device time of the last build phase */
+    double t_partition_ms;  /* device time of the last partition */
+    double t_count_ms;      /* time of the last count (incl. transfers) */
+    double t_kernel_ms;     /* device time of the last count's kernels */
+    int64_t kernel_launches; /* counting launches of the last count */
+} pgabb_graph_info;
+
+/*
+ * Build a graph from m pairs (src[e], dst[e]), 0 <= id < n.  Cleans the pairs
+ * (drops self-loops, merges repeated and reciprocal pairs), ranks vertices by
+ * ascending (degree, id) -- or by id with PGABB_ORDER_BY_ID -- and stores the
+ * oriented graph in CSR over ranks on the device.
+ *   n, m        : n >= 0, m >= 0 (m = 0 gives an edgeless graph)
+ *   src, dst    : m ids each; host pointers, or device pointers with
+ *                 PGABB_EDGES_ON_DEVICE (read before the call returns)
+ *   hip_stream  : hipStream_t for all work on this graph (NULL = the
+ *                 library's own stream)
+ *   out         : receives the graph (caller-owned)
+ * Errors: EINVAL (NULL pointer, n < 0, m < 0, id outside [0, n)),
+ * ENOMEM, EDEVICE.
+ */
+pgabb_status pgabb_graph_from_edges(int32_t n, int64_t m, const int32_t *src,
+                                    const int32_t *dst, uint32_t flags, void *hip_stream,
+                                    pgabb_graph **out);
+
+/*
+ * Cut the oriented graph into a p x p grid with nnz-balanced cuts (stripe s
+ * starts at the first row whose CSR offset reaches s * m' / p), then build
+ * the blocks and the task list.  1 <= p <= 64.  Replaces an earlier
+ * partition.  Errors: EINVAL (NULL, p out of range), ENOMEM, EDEVICE.
+ */
+pgabb_status pgabb_partition(pgabb_graph *g, int32_t p);
+
+/*
+ * As pgabb_partition with a cut mode, or with an explicit host cut vector
+ * (cuts != NULL: p + 1 non-decreasing values, cuts[0] = 0, cuts[p] = n,
+ * applied to ranks on both axes; empty stripes are allowed).
+ */
+pgabb_status pgabb_partition_ex(pgabb_graph *g, int32_t p, int32_t cut_mode,
+                                const int32_t *cuts);
+
+/*
+ * Triangle count with default options.  Partitions with p = 1 first if the
+ * graph was not partitioned.  Returns PGABB_COUNT_ERROR on failure.
+ */
+uint64_t pgabb_tc_count(pgabb_graph *g);
+
+/* Triangle count with options (NULL = defaults); result in *count. */
+pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
+
+/* Sizes and timings of the graph. */
+pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info);
+
+/*
+ * Copy the oriented CSR to host buffers: row_off[n + 1] (int64), col[m']
+ * (ranks, increasing within a row), rank[n] (rank of each input id).  Any of
+ * the three may be NULL to skip it.
+ */
+pgabb_status pgabb_graph_export_csr(const pgabb_graph *g, int64_t *row_off, int32_t *col,
+                                    int32_t *rank);
+
+/* Copy the cut vector (p + 1 values) of the current partition. */
+pgabb_status pgabb_graph_cuts(const pgabb_graph *g, int32_t *cuts);
+
+/*
+ * Per-task results of the last count: ijk[3 t .. 3 t + 2] = (i, j, k) and
+ * counts[t] = triangles found by task t, for t < num_tasks, in execution
+ * order.  Either pointer may be NULL.
+ */
+pgabb_status pgabb_graph_task_counts(const pgabb_graph *g, int32_t *ijk, uint64_t *counts);
+
+/* Release a graph and its device and host memory.  NULL is ignored. */
+void pgabb_graph_destroy(pgabb_graph *g);
+
+/* Status and message of the last failing call on this thread. */
+pgabb_status pgabb_last_status(void);
+const char *pgabb_last_error(void);
+
+/* ------------------------------------------------------------------ batch */
+
+/*
+ * Batched counting of many independent graphs in one persistent launch
+ * (PGAbB's task-parallel execution, Section 4.4, applied to a set of graphs).
+ * The graphs are packed into one arena as a disjoint union; each is cleaned,
+ * ranked by (degree, id) within itself and oriented; one persistent kernel
+ * then consumes a device work queue of rows and adds each row's triangles to
+ * its graph's uint64 slot.  The launch sequence is captured once into a HIP
+ * graph and replayed.
+ *   num_graphs       : G >= 0
+ *   n                : G vertex counts (host)
+ *   edge_off         : G + 1 non-decreasing offsets into src/dst (host)
+ *   src, dst         : edge_off[G] ids; host, or device with
+ *                      PGABB_EDGES_ON_DEVICE
+ */
+typedef struct pgabb_batch pgabb_batch;
+
+pgabb_status pgabb_batch_create(int64_t num_graphs, const int32_t *n, const int64_t *edge_off,
+                                const int32_t *src, const int32_t *dst, uint32_t flags,
+                                void *hip_stream, pgabb_batch **out);
+
+/*
+ * Count every graph of the batch: counts[g] for g < num_graphs (host).
+ * opts == NULL selects the autotuned launch shape (searched on first use,
+ * then cached by the batch's shape features); otherwise opts->kernel,
+ * waves_per_block and rows_per_grab are used as given.
+ */
+pgabb_status pgabb_batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uint64_t *counts);
+
+/* Milliseconds of the last batch count (one replay) and of the build. */
+pgabb_status pgabb_batch_times(const pgabb_batch *b, double *t_build_ms, double *t_count_ms);
+
+void pgabb_batch_destroy(pgabb_batch *b);
+
+/* ----------------------------------------------------------------- server */
+
+/*
+ * A request server with continuous batching: requests (one graph each) are
+ * admitted while their estimated device bytes fit the budget, are built on a
+ * build stream while earlier requests are being counted, and join the next
+ * counting launch as soon as they are built.  Finished requests release
+ * their memory and let queued ones in.
+ *   device_budget_bytes : bound on the device bytes held by admitted requests
+ *   opts                : counting options (NULL = defaults)
+ */
+typedef struct pgabb_server pgabb_server;
+
+pgabb_status pgabb_server_create(uint64_t device_budget_bytes, const pgabb_tc_options *opts,
+                                 pgabb_server **out);
+
+/*
+ * Queue one request; host arrays are copied before the call returns (or
+ * borrowed until it finishes, with PGABB_SERVER_BORROW in the server's
+ * options).  *ticket receives an id for pgabb_server_poll.  EINVAL for an id
+ * outside [0, n); EBUDGET if the request can never fit the budget.
+ */
+pgabb_status pgabb_server_submit(pgabb_server *s, int32_t n, int64_t m, const int32_t *src,
+                                 const int32_t *dst, uint64_t *ticket);
+
+/*
+ * *done = 1 and *count = triangles once the request finished, else *done = 0.
+ * Timestamps (seconds on the server's monotonic clock) of submission and
+ * completion are written when the pointers are not NULL.
+ */
+pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count,
+                               double *t_submit, double *t_done);
+
+/* Block until every submitted request has finished. */
+pgabb_status pgabb_server_drain(pgabb_server *s);
+
+/* Server clock (seconds). */
+double pgabb_server_now(const pgabb_server *s);
+
+/* Counting launches issued so far. */
+pgabb_status pgabb_server_stats(const pgabb_server *s, uint64_t *launches);
+
+void pgabb_server_destroy(pgabb_server *s);
+
+/* ------------------------------------------------------------- allocator */
+
+/*
+ * Route the library's device allocations through caller functions (NULL,
+ * NULL restores the default stream-ordered HIP allocator).  alloc returns
+ * NULL on failure, which the library reports as ENOMEM.  Applies to
+ * allocations made after the call.
+ */
+typedef void *(*pgabb_alloc_fn)(size_t bytes, void *hip_stream, void *ctx);
+typedef void (*pgabb_free_fn)(void *ptr, void *hip_stream, void *ctx);
+pgabb_status pgabb_set_allocator(pgabb_alloc_fn alloc, pgabb_free_fn free_fn, void *ctx);
+
+/* Library version string. */
+const char *pgabb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGABB_H */

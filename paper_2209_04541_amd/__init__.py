@@ -1,0 +1,394 @@
+"""Python binding of libpgabb.so, the MI355X block-partitioned triangle
+counter (PGAbB's triangle-counting example: Section 3.6 for the block-list
+kernel, Section 4.3 for the symmetric 2-D partition, Section 4.4 for the
+scheduler).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Edge arrays may be numpy arrays (host) or torch CUDA tensors (device); for
+device tensors the current torch stream is handed to the library.  If the
+library has not been built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpgabb.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pgabb.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET = 0, -1, -2, -3, -4, -5
+COUNT_ERROR = 2**64 - 1
+EDGES_ON_DEVICE = 0x1
+ORDER_BY_ID = 0x2
+CUT_NNZ, CUT_UNIFORM = 0, 1
+KERNEL_AUTO, KERNEL_HASH, KERNEL_BITMAP, KERNEL_SEARCH = 0, 1, 2, 3
+OPT_STREAM = 0x1
+
+
+class PgabbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("pgabb status %d: %s" % (status, message))
+        self.status = status
+
+
+class TcOptions(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("num_streams", ctypes.c_int32),
+                ("device_cap_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m_input", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("isolated", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("num_blocks", ctypes.c_int64),
+                ("num_tasks", ctypes.c_int64), ("probe_work", ctypes.c_uint64),
+                ("block_bytes", ctypes.c_uint64), ("h2d_bytes", ctypes.c_uint64),
+                ("t_build_ms", ctypes.c_double), ("t_partition_ms", ctypes.c_double),
+                ("t_count_ms", ctypes.c_double), ("t_kernel_ms", ctypes.c_double),
+                ("kernel_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/pgabb.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pgabb_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpgabb.so is not built: run paper_2209_04541_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_uint64)
+        st = ctypes.c_int
+        sig = {
+            "pgabb_graph_from_edges": (st, [i32, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]),
+            "pgabb_partition": (st, [vp, i32]),
+            "pgabb_partition_ex": (st, [vp, i32, i32, vp]),
+            "pgabb_tc_count": (u64, [vp]),
+            "pgabb_tc_count_ex": (st, [vp, vp, ctypes.POINTER(u64)]),
+            "pgabb_graph_info_get": (st, [vp, ctypes.POINTER(GraphInfo)]),
+            "pgabb_graph_export_csr": (st, [vp, vp, vp, vp]),
+            "pgabb_graph_cuts": (st, [vp, vp]),
+            "pgabb_graph_task_counts": (st, [vp, vp, vp]),
+            "pgabb_graph_destroy": (None, [vp]),
+            "pgabb_last_status": (st, []),
+            "pgabb_last_error": (ctypes.c_char_p, []),
+            "pgabb_batch_create": (st, [i64, vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]),
+            "pgabb_batch_count": (st, [vp, vp, vp]),
+            "pgabb_batch_times": (st, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+            "pgabb_batch_destroy": (None, [vp]),
+            "pgabb_server_create": (st, [u64, vp, ctypes.POINTER(vp)]),
+            "pgabb_server_submit": (st, [vp, i32, i64, vp, vp, ctypes.POINTER(u64)]),
+            "pgabb_server_poll": (st, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(u64),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+            "pgabb_server_drain": (st, [vp]),
+            "pgabb_server_now": (ctypes.c_double, [vp]),
+            "pgabb_server_stats": (st, [vp, ctypes.POINTER(u64)]),
+            "pgabb_server_destroy": (None, [vp]),
+            "pgabb_set_allocator": (st, [vp, vp, vp]),
+            "pgabb_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        msg = lib().pgabb_last_error()
+        raise PgabbError(status, msg.decode() if msg else "")
+
+
+def _is_torch_cuda(a):
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+def _torch_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _edges(src, dst):
+    """(ptr_src, ptr_dst, m, flags, keepalive, stream) for host or device arrays."""
+    if _is_torch_cuda(src) or _is_torch_cuda(dst):
+        import torch
+        if not (_is_torch_cuda(src) and _is_torch_cuda(dst)):
+            raise ValueError("src and dst must both be device tensors or both host arrays")
+        s = src.to(torch.int32).contiguous()
+        d = dst.to(torch.int32).contiguous()
+        if s.numel() != d.numel():
+            raise ValueError("src and dst differ in length")
+        return (ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(d.data_ptr()), s.numel(),
+                EDGES_ON_DEVICE, (s, d), _torch_stream())
+    s = np.ascontiguousarray(np.asarray(src), dtype=np.int32)
+    d = np.ascontiguousarray(np.asarray(dst), dtype=np.int32)
+    if s.shape != d.shape:
+        raise ValueError("src and dst differ in length")
+    stream = None
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            stream = _torch_stream()
+    except ImportError:
+        pass
+    return (ctypes.c_void_p(s.ctypes.data if s.size else 0), ctypes.c_void_p(d.ctypes.data if d.size else 0),
+            s.size, 0, (s, d), stream)
+
+
+def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
+            waves_per_block=0, rows_per_grab=0):
+    o = TcOptions()
+    o.kernel = kernel
+    o.num_streams = num_streams
+    o.device_cap_bytes = device_cap_bytes
+    o.flags = OPT_STREAM if stream_blocks else 0
+    o.waves_per_block = waves_per_block
+    o.rows_per_grab = rows_per_grab
+    return o
+
+
+class Graph:
+    """A cleaned, degree-oriented graph resident on the device."""
+
+    def __init__(self, n, src, dst, order_by_id=False, stream=None):
+        ps, pd, m, flags, keep, st = _edges(src, dst)
+        if order_by_id:
+            flags |= ORDER_BY_ID
+        if stream is not None:
+            st = ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(lib().pgabb_graph_from_edges(int(n), int(m), ps, pd, flags, st, ctypes.byref(h)))
+        self._h = h
+        self._keep = keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pgabb_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def partition(self, p, cut_mode=CUT_NNZ, cuts=None):
+        if cuts is not None:
+            c = np.ascontiguousarray(cuts, dtype=np.int32)
+            if len(c) != p + 1:
+                raise ValueError("cuts must hold p + 1 values")
+            _check(lib().pgabb_partition_ex(self._h, int(p), cut_mode, ctypes.c_void_p(c.ctypes.data)))
+        else:
+            _check(lib().pgabb_partition_ex(self._h, int(p), cut_mode, None))
+        return self
+
+    def count(self, opts=None, **kw):
+        if opts is None and kw:
+            opts = options(**kw)
+        c = ctypes.c_uint64()
+        _check(lib().pgabb_tc_count_ex(self._h, ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(c)))
+        return int(c.value)
+
+    def info(self):
+        i = GraphInfo()
+        _check(lib().pgabb_graph_info_get(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def export_csr(self):
+        inf = self.info()
+        n, m = inf["n"], inf["m"]
+        row_off = np.empty(n + 1, np.int64)
+        col = np.empty(max(m, 1), np.int32)
+        rank = np.empty(max(n, 1), np.int32)
+        _check(lib().pgabb_graph_export_csr(self._h, ctypes.c_void_p(row_off.ctypes.data),
+                                            ctypes.c_void_p(col.ctypes.data),
+                                            ctypes.c_void_p(rank.ctypes.data)))
+        return row_off, col[:m], rank[:n]
+
+    def cuts(self):
+        p = self.info()["p"]
+        c = np.empty(p + 1, np.int32)
+        _check(lib().pgabb_graph_cuts(self._h, ctypes.c_void_p(c.ctypes.data)))
+        return c
+
+    def task_counts(self):
+        t = self.info()["num_tasks"]
+        ijk = np.empty((max(t, 1), 3), np.int32)
+        cnt = np.empty(max(t, 1), np.uint64)
+        _check(lib().pgabb_graph_task_counts(self._h, ctypes.c_void_p(ijk.ctypes.data),
+                                             ctypes.c_void_p(cnt.ctypes.data)))
+        return ijk[:t], cnt[:t]
+
+
+def tc_count(n, src, dst, p=1, **kw):
+    """Build, partition and count in one call."""
+    with Graph(n, src, dst) as g:
+        g.partition(p)
+        return g.count(**kw) if kw else g.count()
+
+
+def version():
+    return lib().pgabb_version().decode()
+
+
+OPT_PER_GRAPH = 0x2
+SERVER_BORROW = 0x4
+
+
+class Batch:
+    """Many independent graphs packed into one device arena and counted by
+    one persistent, graph-captured launch."""
+
+    def __init__(self, graphs_or_arrays, stream=None):
+        """graphs_or_arrays: list of (n, src, dst) host arrays, or a tuple
+        (n_array, edge_off, src, dst) already packed."""
+        if isinstance(graphs_or_arrays, tuple) and len(graphs_or_arrays) == 4:
+            nv, eoff, src, dst = graphs_or_arrays
+            nv = np.ascontiguousarray(nv, np.int32)
+            eoff = np.ascontiguousarray(eoff, np.int64)
+        else:
+            gl = list(graphs_or_arrays)
+            nv = np.array([g[0] for g in gl], np.int32)
+            eoff = np.zeros(len(gl) + 1, np.int64)
+            eoff[1:] = np.cumsum([len(g[1]) for g in gl])
+            src = np.concatenate([np.asarray(g[1], np.int32) for g in gl]) if gl else np.zeros(0, np.int32)
+            dst = np.concatenate([np.asarray(g[2], np.int32) for g in gl]) if gl else np.zeros(0, np.int32)
+        ps, pd, m, flags, keep, st = _edges(src, dst)
+        if m != int(eoff[-1] if len(eoff) else 0):
+            raise ValueError("edge_off[-1] must equal the number of pairs")
+        if stream is not None:
+            st = ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(lib().pgabb_batch_create(len(nv), ctypes.c_void_p(nv.ctypes.data),
+                                        ctypes.c_void_p(eoff.ctypes.data), ps, pd, flags, st,
+                                        ctypes.byref(h)))
+        self._h = h
+        self.num_graphs = len(nv)
+        self._keep = (nv, eoff, keep)
+
+    def count(self, opts=None, per_graph=False, **kw):
+        if per_graph:
+            opts = options(**kw)
+            opts.flags |= OPT_PER_GRAPH
+        elif opts is None and kw:
+            opts = options(**kw)
+        out = np.zeros(max(self.num_graphs, 1), np.uint64)
+        _check(lib().pgabb_batch_count(self._h, ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.c_void_p(out.ctypes.data)))
+        return out[:self.num_graphs]
+
+    def times(self):
+        b, c = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pgabb_batch_times(self._h, ctypes.byref(b), ctypes.byref(c)))
+        return b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pgabb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous-batching triangle-count server (host threads inside the
+    library; this class only forwards calls)."""
+
+    def __init__(self, budget_bytes, borrow=False, **kw):
+        o = options(**kw)
+        if borrow:
+            o.flags |= SERVER_BORROW
+        h = ctypes.c_void_p()
+        _check(lib().pgabb_server_create(int(budget_bytes), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._borrowed = {}
+        self.borrow = borrow
+
+    def submit(self, n, src, dst):
+        s = np.ascontiguousarray(src, np.int32)
+        d = np.ascontiguousarray(dst, np.int32)
+        t = ctypes.c_uint64()
+        _check(lib().pgabb_server_submit(self._h, int(n), len(s), ctypes.c_void_p(s.ctypes.data if s.size else 0),
+                                         ctypes.c_void_p(d.ctypes.data if d.size else 0), ctypes.byref(t)))
+        if self.borrow:
+            self._borrowed[t.value] = (s, d)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        cnt = ctypes.c_uint64()
+        ts, td = ctypes.c_double(), ctypes.c_double()
+        st = lib().pgabb_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(cnt),
+                                     ctypes.byref(ts), ctypes.byref(td))
+        if done.value and self.borrow:
+            self._borrowed.pop(ticket, None)
+        _check(st)
+        return bool(done.value), int(cnt.value), ts.value, td.value
+
+    def drain(self):
+        _check(lib().pgabb_server_drain(self._h))
+
+    def now(self):
+        return lib().pgabb_server_now(self._h)
+
+    def launches(self):
+        v = ctypes.c_uint64()
+        _check(lib().pgabb_server_stats(self._h, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pgabb_server_destroy(self._h)
+            self._h = None
+            self._borrowed.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

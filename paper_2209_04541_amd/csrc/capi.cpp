@@ -1,0 +1,315 @@
+// C ABI entry points: argument checks, error capture, object lifetime.
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "common.hpp"
+#include "graph.hpp"
+
+namespace pgabb {
+
+namespace {
+
+thread_local pgabb_status t_status = PGABB_OK;
+thread_local std::string t_message;
+
+std::mutex g_alloc_mu;
+pgabb_alloc_fn g_alloc = nullptr;
+pgabb_free_fn g_free = nullptr;
+void *g_alloc_ctx = nullptr;
+
+pgabb_status set_ok() {
+    t_status = PGABB_OK;
+    t_message.clear();
+    return PGABB_OK;
+}
+
+pgabb_status set_err(pgabb_status st, const std::string &msg) {
+    t_status = st;
+    t_message = msg;
+    return st;
+}
+
+}  // namespace
+
+void fail(pgabb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{st, buf};
+}
+
+void *dalloc(size_t bytes, hipStream_t s) {
+    if (!bytes) return nullptr;
+    pgabb_alloc_fn fa;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        fa = g_alloc;
+        ctx = g_alloc_ctx;
+    }
+    void *p = nullptr;
+    if (fa) {
+        p = fa(bytes, s, ctx);
+        if (!p) fail(PGABB_ENOMEM, "allocator hook failed for %zu bytes", bytes);
+        return p;
+    }
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(PGABB_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
+    return p;
+}
+
+void dfree(void *p, hipStream_t s) {
+    if (!p) return;
+    pgabb_free_fn ff;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        ff = g_free;
+        ctx = g_alloc_ctx;
+    }
+    if (ff) ff(p, s, ctx);
+    else (void)hipFreeAsync(p, s);
+}
+
+StreamTimer::StreamTimer() {
+    PGABB_HIP(hipEventCreate(&a_));
+    PGABB_HIP(hipEventCreate(&b_));
+}
+StreamTimer::~StreamTimer() {
+    if (a_) (void)hipEventDestroy(a_);
+    if (b_) (void)hipEventDestroy(b_);
+}
+void StreamTimer::start(hipStream_t s) { PGABB_HIP(hipEventRecord(a_, s)); }
+void StreamTimer::stop(hipStream_t s) { PGABB_HIP(hipEventRecord(b_, s)); }
+double StreamTimer::ms() {
+    PGABB_HIP(hipEventSynchronize(b_));
+    float t = 0;
+    PGABB_HIP(hipEventElapsedTime(&t, a_, b_));
+    return t;
+}
+
+hipStream_t library_stream() {
+    static hipStream_t s = [] {
+        hipStream_t x = nullptr;
+        PGABB_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        return x;
+    }();
+    return s;
+}
+
+pgabb_status capture_status(const Error &e) { return set_err(e.status, e.message); }
+
+}  // namespace pgabb
+
+using namespace pgabb;
+
+#define PGABB_API extern "C" __attribute__((visibility("default")))
+
+#define PGABB_TRY try {
+#define PGABB_CATCH                                                      \
+    }                                                                    \
+    catch (const Error &e) {                                             \
+        return set_err(e.status, e.message);                             \
+    }                                                                    \
+    catch (const std::bad_alloc &) {                                     \
+        return set_err(PGABB_ENOMEM, "host allocation failed");          \
+    }                                                                    \
+    catch (...) {                                                        \
+        return set_err(PGABB_EDEVICE, "unexpected internal error");      \
+    }
+
+PGABB_API pgabb_status pgabb_last_status(void) { return t_status; }
+PGABB_API const char *pgabb_last_error(void) { return t_message.c_str(); }
+PGABB_API const char *pgabb_version(void) { return "pgabb-mi355x 0.1 (gfx950)"; }
+
+PGABB_API pgabb_status pgabb_set_allocator(pgabb_alloc_fn alloc, pgabb_free_fn free_fn, void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return set_err(PGABB_EINVAL, "alloc and free must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = alloc ? ctx : nullptr;
+    return set_ok();
+}
+
+PGABB_API pgabb_status pgabb_graph_from_edges(int32_t n, int64_t m, const int32_t *src,
+                                              const int32_t *dst, uint32_t flags, void *hip_stream,
+                                              pgabb_graph **out) {
+    if (!out) return set_err(PGABB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 0) return set_err(PGABB_EINVAL, "n < 0");
+    if (m < 0) return set_err(PGABB_EINVAL, "m < 0");
+    if (m > 0 && (!src || !dst)) return set_err(PGABB_EINVAL, "src or dst is NULL");
+    if (flags & ~(PGABB_EDGES_ON_DEVICE | PGABB_ORDER_BY_ID)) return set_err(PGABB_EINVAL, "unknown flag bits");
+    if (m >= (int64_t(1) << 32)) return set_err(PGABB_EINVAL, "more than 2^32 - 1 pairs");
+    // host input: check ids before any device work
+    if (m > 0 && !(flags & PGABB_EDGES_ON_DEVICE)) {
+        for (int64_t e = 0; e < m; ++e) {
+            if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) {
+                char buf[160];
+                snprintf(buf, sizeof buf, "pair %lld = (%d, %d) has an id outside [0, %d)",
+                         static_cast<long long>(e), src[e], dst[e], n);
+                return set_err(PGABB_EINVAL, buf);
+            }
+        }
+    }
+    pgabb_graph *g = nullptr;
+    PGABB_TRY
+    g = new pgabb_graph();
+    g->flags = flags;
+    g->n = n;
+    g->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : library_stream();
+    hipStream_t s = g->stream;
+    StreamTimer tm;
+    tm.start(s);
+    if (m > 0 && !(flags & PGABB_EDGES_ON_DEVICE)) {
+        DArray<int32_t> ds(static_cast<size_t>(m), s), dd(static_cast<size_t>(m), s);
+        PGABB_HIP(hipMemcpyAsync(ds.get(), src, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        PGABB_HIP(hipMemcpyAsync(dd.get(), dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        build_graph(g, ds.get(), dd.get(), m);
+    } else {
+        build_graph(g, src, dst, m);
+    }
+    tm.stop(s);
+    g->t_build_ms = tm.ms();
+    *out = g;
+    return set_ok();
+    }
+    catch (const Error &e) {
+        delete g;
+        return set_err(e.status, e.message);
+    }
+    catch (const std::bad_alloc &) {
+        delete g;
+        return set_err(PGABB_ENOMEM, "host allocation failed");
+    }
+    catch (...) {
+        delete g;
+        return set_err(PGABB_EDEVICE, "unexpected internal error");
+    }
+}
+
+PGABB_API pgabb_status pgabb_partition_ex(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t *cuts) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (p < 1 || p > 64) return set_err(PGABB_EINVAL, "p must lie in [1, 64]");
+    if (cut_mode != PGABB_CUT_NNZ && cut_mode != PGABB_CUT_UNIFORM)
+        return set_err(PGABB_EINVAL, "unknown cut mode");
+    if (cuts) {
+        if (cuts[0] != 0 || cuts[p] != g->n) return set_err(PGABB_EINVAL, "cuts must start at 0 and end at n");
+        for (int32_t s = 0; s < p; ++s)
+            if (cuts[s] > cuts[s + 1]) return set_err(PGABB_EINVAL, "cuts must be non-decreasing");
+    }
+    PGABB_TRY
+    partition_graph(g, p, cut_mode, cuts);
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_partition(pgabb_graph *g, int32_t p) {
+    return pgabb_partition_ex(g, p, PGABB_CUT_NNZ, nullptr);
+}
+
+static pgabb_tc_options default_options() {
+    pgabb_tc_options o;
+    std::memset(&o, 0, sizeof o);
+    return o;
+}
+
+PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!count) return set_err(PGABB_EINVAL, "count is NULL");
+    *count = PGABB_COUNT_ERROR;
+    pgabb_tc_options o = opts ? *opts : default_options();
+    if (o.kernel < PGABB_KERNEL_AUTO || o.kernel > PGABB_KERNEL_SEARCH)
+        return set_err(PGABB_EINVAL, "unknown kernel");
+    if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0)
+        return set_err(PGABB_EINVAL, "negative option");
+    if (o.waves_per_block && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
+        return set_err(PGABB_EINVAL, "waves_per_block must be 2, 4 or 8");
+    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW))
+        return set_err(PGABB_EINVAL, "unknown option flag bits");
+    PGABB_TRY
+    *count = count_graph(g, o);
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API uint64_t pgabb_tc_count(pgabb_graph *g) {
+    uint64_t c = PGABB_COUNT_ERROR;
+    if (pgabb_tc_count_ex(g, nullptr, &c) != PGABB_OK) return PGABB_COUNT_ERROR;
+    return c;
+}
+
+PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info) {
+    if (!g || !info) return set_err(PGABB_EINVAL, "NULL argument");
+    info->n = g->n;
+    info->m_input = g->m_input;
+    info->m = g->m;
+    info->isolated = g->isolated;
+    info->max_out_degree = g->max_out;
+    info->p = g->p;
+    info->num_blocks = static_cast<int64_t>(g->blocks.size());
+    info->num_tasks = static_cast<int64_t>(g->tasks.size());
+    info->probe_work = g->probe_work;
+    info->block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
+    info->h2d_bytes = g->h2d_bytes;
+    info->t_build_ms = g->t_build_ms;
+    info->t_partition_ms = g->t_partition_ms;
+    info->t_count_ms = g->t_count_ms;
+    info->t_kernel_ms = g->t_kernel_ms;
+    info->kernel_launches = g->kernel_launches;
+    return set_ok();
+}
+
+PGABB_API pgabb_status pgabb_graph_export_csr(const pgabb_graph *g, int64_t *row_off, int32_t *col, int32_t *rank) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    PGABB_TRY
+    hipStream_t s = g->stream;
+    if (row_off)
+        PGABB_HIP(hipMemcpyAsync(row_off, g->row_off.get(), sizeof(int64_t) * (static_cast<size_t>(g->n) + 1),
+                                 hipMemcpyDeviceToHost, s));
+    if (col && g->m)
+        PGABB_HIP(hipMemcpyAsync(col, g->col.get(), sizeof(int32_t) * g->m, hipMemcpyDeviceToHost, s));
+    if (rank && g->n)
+        PGABB_HIP(hipMemcpyAsync(rank, g->rank.get(), sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, s));
+    PGABB_HIP(hipStreamSynchronize(s));
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_graph_cuts(const pgabb_graph *g, int32_t *cuts) {
+    if (!g || !cuts) return set_err(PGABB_EINVAL, "NULL argument");
+    if (g->p == 0) return set_err(PGABB_ESTATE, "graph is not partitioned");
+    std::memcpy(cuts, g->cuts.data(), sizeof(int32_t) * g->cuts.size());
+    return set_ok();
+}
+
+PGABB_API pgabb_status pgabb_graph_task_counts(const pgabb_graph *g, int32_t *ijk, uint64_t *counts) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (g->p == 0) return set_err(PGABB_ESTATE, "graph is not partitioned");
+    for (size_t t = 0; t < g->tasks.size(); ++t) {
+        if (ijk) {
+            ijk[3 * t] = g->tasks[t].i;
+            ijk[3 * t + 1] = g->tasks[t].j;
+            ijk[3 * t + 2] = g->tasks[t].k;
+        }
+        if (counts) counts[t] = t < g->task_counts.size() ? g->task_counts[t] : 0;
+    }
+    return set_ok();
+}
+
+PGABB_API void pgabb_graph_destroy(pgabb_graph *g) {
+    if (!g) return;
+    try {
+        (void)hipStreamSynchronize(g->stream);
+        delete g;
+    } catch (...) {
+    }
+}

@@ -1,0 +1,219 @@
+// Count phase: run every task (block-list) of a partitioned graph.
+//
+// In-core path: all blocks live in one device arena.  One persistent launch
+// covers every task: the work items are the rows of each task's A_ij, laid
+// out task after task in the heaviest-first order of the task table, and
+// each wave repeatedly grabs a few consecutive items from a global counter
+// (dynamic load balance over skewed rows, PGAbB Section 4.4's "heavy tasks
+// first").  A wave accumulates its hits in registers and adds them to the
+// task's uint64 counter when it leaves a task.
+//
+// Streamed path (graph blocks held in pinned host memory): see streamer.hip.
+#include <algorithm>
+#include <chrono>
+
+#include "common.hpp"
+#include "count.hpp"
+#include "graph.hpp"
+#include "tc_device.hpp"
+#include "wave.hpp"
+
+namespace pgabb {
+
+namespace {
+
+template <int MODE, int LDS_WORDS, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
+    __shared__ int32_t lds_all[WAVES][LDS_WORDS];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    int32_t *lds = lds_all[w];
+    if (MODE == kModeBitmap) {
+        for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
+        wave_lds_sync();
+    }
+    for (;;) {
+        unsigned long long g0 = 0;
+        if (lane == 0) g0 = atomicAdd(a.next, static_cast<unsigned long long>(a.grab));
+        g0 = shfl_t(g0, 0);
+        if (static_cast<int64_t>(g0) >= a.total) break;
+        const int64_t g1 = min(static_cast<int64_t>(g0) + a.grab, a.total);
+        int32_t lo = 0, hi = a.ntasks - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (a.item_pre[mid] <= static_cast<int64_t>(g0)) lo = mid;
+            else hi = mid - 1;
+        }
+        int32_t t = __builtin_amdgcn_readfirstlane(lo);
+        int64_t t_end = a.item_pre[t + 1];
+        uint32_t cnt = 0;
+        for (int64_t g = static_cast<int64_t>(g0); g < g1; ++g) {
+            while (g >= t_end) {
+                const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
+                if (lane == 0 && s) atomicAdd(&a.counts[a.tasks[t].slot], s);
+                cnt = 0;
+                ++t;
+                t_end = a.item_pre[t + 1];
+            }
+            const TaskDesc &T = a.tasks[t];
+            cnt += tc_row<MODE, LDS_WORDS>(T.ij, T.ik, T.jk, T.width_k,
+                                           static_cast<int32_t>(g - a.item_pre[t]), lds);
+        }
+        const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
+        if (lane == 0 && s) atomicAdd(&a.counts[a.tasks[t].slot], s);
+    }
+}
+
+template <int MODE, int LDS_WORDS, int WAVES>
+void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
+    auto kern = k_tc_tasks<MODE, LDS_WORDS, WAVES>;
+    int per_cu = 0;
+    PGABB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, 0));
+    if (per_cu < 1) per_cu = 1;
+    int dev = 0, cus = 0;
+    PGABB_HIP(hipGetDevice(&dev));
+    PGABB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t grid = static_cast<int64_t>(cus) * per_cu;
+    if (grid_override > 0) grid = grid_override;
+    const int64_t waves_needed = (a.total + a.grab - 1) / a.grab;
+    const int64_t blocks_needed = (waves_needed + WAVES - 1) / WAVES;
+    if (grid > blocks_needed) grid = blocks_needed;
+    if (grid < 1) grid = 1;
+    kern<<<static_cast<unsigned>(grid), WAVES * 64, 0, s>>>(a);
+    PGABB_HIP(hipGetLastError());
+}
+
+template <int MODE, int WAVES>
+void launch_words(const CountArgs &a, int lds_words, hipStream_t s, int grid_override) {
+    if (lds_words <= 256) launch_one<MODE, 256, WAVES>(a, s, grid_override);
+    else if (lds_words <= 512) launch_one<MODE, 512, WAVES>(a, s, grid_override);
+    else if (lds_words <= 1024) launch_one<MODE, 1024, WAVES>(a, s, grid_override);
+    else if (lds_words <= 2048) launch_one<MODE, 2048, WAVES>(a, s, grid_override);
+    else launch_one<MODE, 4096, WAVES>(a, s, grid_override);
+}
+
+}  // namespace
+
+int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
+    int need = 256;
+    if (mode == kModeBitmap) {
+        const int64_t w = (static_cast<int64_t>(max_width_k) + 31) / 32;
+        while (need < w && need < 4096) need <<= 1;
+    } else if (mode == kModeHash) {
+        while (need < 2 * static_cast<int64_t>(max_stage_len) && need < 4096) need <<= 1;
+    }
+    return need;
+}
+
+void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
+                     int grid_override) {
+    if (a.total <= 0) return;
+    if (waves == 2) {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 2>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 2>(a, s, grid_override);
+        else launch_words<kModeHash, 2>(a, lds_words, s, grid_override);
+    } else if (waves == 8) {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 8>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 8>(a, s, grid_override);
+        else launch_words<kModeHash, 8>(a, lds_words, s, grid_override);
+    } else {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 4>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 4>(a, s, grid_override);
+        else launch_words<kModeHash, 4>(a, lds_words, s, grid_override);
+    }
+}
+
+int mode_of_option(int32_t kernel) {
+    switch (kernel) {
+        case PGABB_KERNEL_BITMAP: return kModeBitmap;
+        case PGABB_KERNEL_SEARCH: return kModeSearch;
+        default: return kModeHash;
+    }
+}
+
+TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
+                   const int64_t *chunk_dev_off) {
+    auto ref = [&](int32_t b) {
+        const BlockInfo &bi = g->blocks[b];
+        const int32_t *c = arena_base + (chunk_dev_off ? chunk_dev_off[b] : bi.chunk_off);
+        BlockRef r;
+        r.rptr = c;
+        r.rid = c + bi.width + 1;
+        r.col = r.rid + bi.nrows;
+        r.nrows = bi.nrows;
+        r.width = bi.width;
+        return r;
+    };
+    TaskDesc d;
+    d.ij = ref(t.bij);
+    d.ik = ref(t.bik);
+    d.jk = ref(t.bjk);
+    d.width_k = g->cuts[t.k + 1] - g->base[t.k];
+    d.slot = slot;
+    return d;
+}
+
+static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
+    hipStream_t s = g->stream;
+    const int32_t T = static_cast<int32_t>(g->tasks.size());
+    std::vector<TaskDesc> td(T);
+    std::vector<int64_t> pre(static_cast<size_t>(T) + 1, 0);
+    int32_t max_wk = 0;
+    for (int32_t t = 0; t < T; ++t) {
+        td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
+        pre[t + 1] = pre[t] + g->blocks[g->tasks[t].bij].nrows;
+        max_wk = std::max(max_wk, td[t].width_k);
+    }
+    DArray<TaskDesc> dtd(T, s);
+    DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
+    DArray<unsigned long long> dcnt(static_cast<size_t>(T) + 1, s);  // last slot: work counter
+    PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, s));
+    PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + 1), s));
+
+    CountArgs a;
+    a.tasks = dtd.get();
+    a.item_pre = dpre.get();
+    a.ntasks = T;
+    a.total = pre[T];
+    a.counts = dcnt.get();
+    a.next = dcnt.get() + T;
+    a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : 8;
+    const int mode = mode_of_option(opt.kernel);
+    const int words = choose_lds_words(mode, g->max_out, max_wk);
+    const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
+    StreamTimer tm;
+    tm.start(s);
+    launch_tc_tasks(a, mode, words, waves, s, 0);
+    tm.stop(s);
+
+    g->task_counts.assign(T, 0);
+    PGABB_HIP(hipMemcpyAsync(g->task_counts.data(), dcnt.get(), sizeof(uint64_t) * T, hipMemcpyDeviceToHost, s));
+    PGABB_HIP(hipStreamSynchronize(s));
+    g->t_kernel_ms = tm.ms();
+    g->kernel_launches = 1;
+    uint64_t total = 0;
+    for (uint64_t c : g->task_counts) total += c;
+    return total;
+}
+
+uint64_t count_graph(pgabb_graph *g, const pgabb_tc_options &opt) {
+    if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    auto t0 = std::chrono::steady_clock::now();
+    g->h2d_bytes = 0;
+    g->t_kernel_ms = 0;
+    g->kernel_launches = 0;
+    uint64_t total = 0;
+    if (!g->tasks.empty()) {
+        const uint64_t block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
+        const bool stream = g->blocks_on_host || (opt.flags & PGABB_OPT_STREAM) ||
+                            (opt.device_cap_bytes && block_bytes > opt.device_cap_bytes);
+        total = stream ? count_streamed(g, opt) : count_in_core(g, opt);
+    } else {
+        g->task_counts.clear();
+    }
+    g->t_count_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return total;
+}
+
+}  // namespace pgabb

@@ -1,0 +1,26 @@
+// Host-side interface of the counting kernels.
+#pragma once
+
+#include "graph.hpp"
+
+namespace pgabb {
+
+struct CountArgs {
+    const TaskDesc *tasks;     // device
+    const int64_t *item_pre;   // device, ntasks + 1 prefix of rows per task
+    int32_t ntasks;
+    int32_t grab;              // rows taken per counter increment
+    int64_t total;             // item_pre[ntasks]
+    unsigned long long *counts;  // device, indexed by TaskDesc::slot
+    unsigned long long *next;    // device work counter (zero before launch)
+};
+
+int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
+int mode_of_option(int32_t kernel);
+void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
+                     int grid_override);
+TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
+                   const int64_t *chunk_dev_off);
+uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt);
+
+}  // namespace pgabb

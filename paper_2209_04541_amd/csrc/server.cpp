@@ -1,0 +1,354 @@
+// Request server with continuous batching.
+//
+// Two host threads drive two HIP streams:
+//  - the builder admits queued requests in arrival order while their
+//    estimated device bytes fit the budget, and builds each one (clean, rank,
+//    orient, partition) on the build stream;
+//  - the counter takes every request built so far, runs all their tasks in
+//    one counting launch on the count stream, returns each request's uint64
+//    count, frees its device memory and wakes the builder.
+// So requests that arrive while others are being counted are admitted as
+// memory frees up, are built while the previous launch runs, and join the
+// next launch: their device work overlaps, and each result is the same as
+// when counted alone (integer sums do not depend on the batch).
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "common.hpp"
+#include "count.hpp"
+#include "graph.hpp"
+#include "tc_device.hpp"
+
+namespace pgabb {
+pgabb_status capture_status(const Error &e);
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    std::vector<int32_t> src, dst;      // owned copies
+    const int32_t *bsrc = nullptr;      // borrowed arrays (PGABB_SERVER_BORROW)
+    const int32_t *bdst = nullptr;
+    uint64_t est = 0;
+    double t_submit = 0, t_done = 0;
+    pgabb_graph *g = nullptr;
+    uint64_t count = PGABB_COUNT_ERROR;
+    pgabb_status status = PGABB_OK;
+    bool done = false;
+};
+
+}  // namespace
+
+struct pgabb_server {
+    uint64_t budget = 0;
+    pgabb_tc_options opt{};
+    std::mutex mu;
+    std::condition_variable cv_build, cv_count, cv_done;
+    std::deque<Request *> queue;  // submitted, not yet admitted
+    std::deque<Request *> ready;  // built, waiting for a launch
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
+    uint64_t reserved = 0;
+    uint64_t next_ticket = 1;
+    int64_t in_flight = 0;  // admitted, not finished
+    bool stop = false;
+    bool builder_done = false;
+    std::thread builder, counter;
+    hipStream_t build_stream = nullptr, count_stream = nullptr;
+    int device = 0;
+    Clock::time_point t0 = Clock::now();
+    uint64_t launches = 0;
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace pgabb {
+
+// Device bytes a request may hold at its peak: the build's sort buffers
+// (two 8-byte keys per pair plus flags), the CSR and the blocks.
+uint64_t request_bytes(int32_t n, int64_t m) {
+    return static_cast<uint64_t>(m) * 40 + static_cast<uint64_t>(n) * 48 + (4ull << 20);
+}
+
+static void builder_loop(pgabb_server *s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_build.wait(lk, [&] {
+                return s->stop || (!s->queue.empty() && s->reserved + s->queue.front()->est <= s->budget);
+            });
+            if (s->stop && s->queue.empty()) break;
+            if (s->queue.empty() || s->reserved + s->queue.front()->est > s->budget) {
+                if (s->stop) {
+                    // cannot admit more while stopping: fail what is left
+                    for (Request *q : s->queue) {
+                        q->status = PGABB_ESTATE;
+                        q->done = true;
+                    }
+                    s->queue.clear();
+                    s->cv_done.notify_all();
+                    break;
+                }
+                continue;
+            }
+            r = s->queue.front();
+            s->queue.pop_front();
+            s->reserved += r->est;
+        }
+        try {
+            pgabb_graph *g = new pgabb_graph();
+            r->g = g;
+            g->n = r->n;
+            g->stream = s->build_stream;
+            const int32_t *hs = r->bsrc ? r->bsrc : r->src.data();
+            const int32_t *hd = r->bdst ? r->bdst : r->dst.data();
+            if (r->m > 0) {
+                DArray<int32_t> ds(static_cast<size_t>(r->m), g->stream), dd(static_cast<size_t>(r->m), g->stream);
+                PGABB_HIP(hipMemcpyAsync(ds.get(), hs, sizeof(int32_t) * r->m, hipMemcpyHostToDevice, g->stream));
+                PGABB_HIP(hipMemcpyAsync(dd.get(), hd, sizeof(int32_t) * r->m, hipMemcpyHostToDevice, g->stream));
+                build_graph(g, ds.get(), dd.get(), r->m);
+            } else {
+                build_graph(g, nullptr, nullptr, 0);
+            }
+            partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+            PGABB_HIP(hipStreamSynchronize(g->stream));
+            std::vector<int32_t>().swap(r->src);
+            std::vector<int32_t>().swap(r->dst);
+        } catch (const Error &e) {
+            r->status = e.status;
+        } catch (...) {
+            r->status = PGABB_EDEVICE;
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->ready.push_back(r);
+        }
+        s->cv_count.notify_one();
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->builder_done = true;
+    }
+    s->cv_count.notify_one();
+}
+
+static void finish(pgabb_server *s, Request *r) {
+    if (r->g) {
+        (void)hipStreamSynchronize(r->g->stream);
+        delete r->g;
+        r->g = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->t_done = s->now();
+    r->done = true;
+    s->reserved -= r->est;
+    --s->in_flight;
+}
+
+static void counter_loop(pgabb_server *s) {
+    (void)hipSetDevice(s->device);
+    DArray<TaskDesc> dtd;
+    DArray<int64_t> dpre;
+    DArray<unsigned long long> dcnt;
+    PinnedArray<unsigned long long> hcnt;
+    for (;;) {
+        std::vector<Request *> batch;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_count.wait(lk, [&] { return !s->ready.empty() || s->builder_done; });
+            if (s->ready.empty() && s->builder_done) break;
+            batch.assign(s->ready.begin(), s->ready.end());
+            s->ready.clear();
+        }
+        // one launch over every task of every built request in the batch
+        std::vector<TaskDesc> td;
+        std::vector<int64_t> pre(1, 0);
+        std::vector<Request *> live;
+        int32_t max_out = 0, max_wk = 0;
+        for (Request *r : batch) {
+            if (r->status != PGABB_OK || !r->g) {
+                finish(s, r);
+                continue;
+            }
+            const int32_t slot = static_cast<int32_t>(live.size());
+            live.push_back(r);
+            pgabb_graph *g = r->g;
+            for (const Task &t : g->tasks) {
+                td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
+                pre.push_back(pre.back() + g->blocks[t.bij].nrows);
+                max_wk = std::max(max_wk, td.back().width_k);
+            }
+            max_out = std::max(max_out, g->max_out);
+        }
+        if (live.empty()) {
+            s->cv_build.notify_all();
+            s->cv_done.notify_all();
+            continue;
+        }
+        try {
+            hipStream_t cs = s->count_stream;
+            const int32_t T = static_cast<int32_t>(td.size());
+            const size_t L = live.size();
+            if (dcnt.size() < L + 1) {
+                dcnt.reset(std::max<size_t>(2 * (L + 1), 64), cs);
+                hcnt.reset(dcnt.size());
+            }
+            if (T > 0) {
+                if (dtd.size() < static_cast<size_t>(T)) dtd.reset(std::max<size_t>(2 * T, 256), cs);
+                if (dpre.size() < static_cast<size_t>(T) + 1) dpre.reset(std::max<size_t>(2 * T + 2, 256), cs);
+                PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, cs));
+                PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, cs));
+            }
+            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + 1), cs));
+            if (T > 0) {
+                CountArgs a;
+                a.tasks = dtd.get();
+                a.item_pre = dpre.get();
+                a.ntasks = T;
+                a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : 8;
+                a.total = pre.back();
+                a.counts = dcnt.get();
+                a.next = dcnt.get() + L;
+                const int mode = mode_of_option(s->opt.kernel);
+                launch_tc_tasks(a, mode, choose_lds_words(mode, max_out, max_wk),
+                                s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0);
+            }
+            PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, cs));
+            PGABB_HIP(hipStreamSynchronize(cs));
+            for (size_t q = 0; q < L; ++q) live[q]->count = hcnt[q];
+            ++s->launches;
+        } catch (const Error &e) {
+            for (Request *r : live) r->status = e.status;
+        } catch (...) {
+            for (Request *r : live) r->status = PGABB_EDEVICE;
+        }
+        for (Request *r : live) finish(s, r);
+        s->cv_build.notify_all();
+        s->cv_done.notify_all();
+    }
+}
+
+}  // namespace pgabb
+
+using namespace pgabb;
+
+#define PGABB_API extern "C" __attribute__((visibility("default")))
+
+PGABB_API pgabb_status pgabb_server_create(uint64_t device_budget_bytes, const pgabb_tc_options *opts,
+                                           pgabb_server **out) {
+    if (!out) return capture_status(Error{PGABB_EINVAL, "out is NULL"});
+    *out = nullptr;
+    if (device_budget_bytes == 0) return capture_status(Error{PGABB_EINVAL, "budget is 0"});
+    pgabb_server *s = nullptr;
+    try {
+        s = new pgabb_server();
+        s->budget = device_budget_bytes;
+        if (opts) s->opt = *opts;
+        PGABB_HIP(hipGetDevice(&s->device));
+        PGABB_HIP(hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking));
+        PGABB_HIP(hipStreamCreateWithFlags(&s->count_stream, hipStreamNonBlocking));
+        s->builder = std::thread(builder_loop, s);
+        s->counter = std::thread(counter_loop, s);
+        *out = s;
+        return capture_status(Error{PGABB_OK, ""});
+    } catch (const Error &e) {
+        if (s) {
+            if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+            if (s->count_stream) (void)hipStreamDestroy(s->count_stream);
+            delete s;
+        }
+        return capture_status(e);
+    }
+}
+
+PGABB_API pgabb_status pgabb_server_submit(pgabb_server *s, int32_t n, int64_t m, const int32_t *src,
+                                           const int32_t *dst, uint64_t *ticket) {
+    if (!s || !ticket) return capture_status(Error{PGABB_EINVAL, "NULL argument"});
+    if (n < 0 || m < 0) return capture_status(Error{PGABB_EINVAL, "n < 0 or m < 0"});
+    if (m > 0 && (!src || !dst)) return capture_status(Error{PGABB_EINVAL, "src or dst is NULL"});
+    for (int64_t e = 0; e < m; ++e)
+        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n)
+            return capture_status(Error{PGABB_EINVAL, "an edge endpoint lies outside [0, n)"});
+    const uint64_t est = request_bytes(n, m);
+    if (est > s->budget) return capture_status(Error{PGABB_EBUDGET, "request exceeds the device budget"});
+    auto r = std::make_unique<Request>();
+    r->n = n;
+    r->m = m;
+    r->est = est;
+    if (s->opt.flags & PGABB_SERVER_BORROW) {
+        r->bsrc = src;
+        r->bdst = dst;
+    } else if (m > 0) {
+        r->src.assign(src, src + m);
+        r->dst.assign(dst, dst + m);
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return capture_status(Error{PGABB_ESTATE, "server is stopping"});
+        r->ticket = s->next_ticket++;
+        r->t_submit = s->now();
+        *ticket = r->ticket;
+        s->queue.push_back(r.get());
+        ++s->in_flight;
+        s->all.emplace(r->ticket, std::move(r));
+    }
+    s->cv_build.notify_one();
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count,
+                                         double *t_submit, double *t_done) {
+    if (!s || !done) return capture_status(Error{PGABB_EINVAL, "NULL argument"});
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return capture_status(Error{PGABB_EINVAL, "unknown ticket"});
+    Request *r = it->second.get();
+    *done = r->done ? 1 : 0;
+    if (count) *count = r->done ? r->count : PGABB_COUNT_ERROR;
+    if (t_submit) *t_submit = r->t_submit;
+    if (t_done) *t_done = r->t_done;
+    if (r->done && r->status != PGABB_OK)
+        return capture_status(Error{r->status, "request failed"});
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_server_drain(pgabb_server *s) {
+    if (!s) return capture_status(Error{PGABB_EINVAL, "server is NULL"});
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->in_flight == 0; });
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API double pgabb_server_now(const pgabb_server *s) { return s ? s->now() : 0.0; }
+
+PGABB_API pgabb_status pgabb_server_stats(const pgabb_server *s, uint64_t *launches) {
+    if (!s) return capture_status(Error{PGABB_EINVAL, "server is NULL"});
+    if (launches) *launches = s->launches;
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API void pgabb_server_destroy(pgabb_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_build.notify_all();
+    s->cv_count.notify_all();
+    if (s->builder.joinable()) s->builder.join();
+    if (s->counter.joinable()) s->counter.join();
+    (void)hipStreamDestroy(s->build_stream);
+    (void)hipStreamDestroy(s->count_stream);
+    delete s;
+}

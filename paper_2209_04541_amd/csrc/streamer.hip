@@ -1,0 +1,308 @@
+// Streamed count: blocks live in a pinned host store and move to the device
+// on demand, under a byte cap.
+//
+// PGAbB Section 4.4: the graph is stored in host memory; the blocks of a task
+// assigned to the GPU are copied with asynchronous host-to-device copies, and
+// several streams let the copy of the next assignment overlap the current
+// computation.  Instead of waiting for all tasks and clearing the device
+// when memory runs low, this keeps a block cache: a device pool of at most
+// `device_cap_bytes` managed first-fit, with least-recently-used eviction of
+// blocks that no in-flight task still reads.
+//
+// Tasks are taken in the heaviest-first order and grouped into windows of a
+// few tasks whose blocks are resident together.  For each window the missing
+// blocks are copied on a copy stream; the window's counting launch runs on
+// one of several compute streams once its copies are done; windows on
+// different streams overlap, and the copies of later windows overlap earlier
+// launches.
+#include <algorithm>
+#include <list>
+#include <map>
+
+#include "common.hpp"
+#include "count.hpp"
+#include "graph.hpp"
+#include "tc_device.hpp"
+
+namespace pgabb {
+
+namespace {
+
+// First-fit allocator over [0, cap) with coalescing of free ranges.
+class RangePool {
+  public:
+    explicit RangePool(uint64_t cap) { free_[0] = cap; }
+    // Returns offset or UINT64_MAX.
+    uint64_t alloc(uint64_t bytes) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const uint64_t off = it->first;
+                const uint64_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return off;
+            }
+        }
+        return UINT64_MAX;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+};
+
+constexpr uint64_t kAlign = 256;
+
+uint64_t chunk_bytes(const BlockInfo &b) {
+    const uint64_t raw = static_cast<uint64_t>(b.chunk_len) * sizeof(int32_t);
+    return (raw + kAlign - 1) / kAlign * kAlign;
+}
+
+}  // namespace
+
+// Moves the device arena to a pinned host store (once per partition).
+static void move_blocks_to_host(pgabb_graph *g) {
+    if (g->blocks_on_host) return;
+    hipStream_t s = g->stream;
+    g->host_arena.reset(static_cast<size_t>(g->arena_words));
+    if (g->arena_words)
+        PGABB_HIP(hipMemcpyAsync(g->host_arena.get(), g->arena.get(), sizeof(int32_t) * g->arena_words,
+                                 hipMemcpyDeviceToHost, s));
+    PGABB_HIP(hipStreamSynchronize(s));
+    g->arena.release();
+    g->blocks_on_host = true;
+}
+
+uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
+    move_blocks_to_host(g);
+    hipStream_t s = g->stream;
+    const int32_t T = static_cast<int32_t>(g->tasks.size());
+    const int32_t nblk = static_cast<int32_t>(g->blocks.size());
+
+    uint64_t total_bytes = 0;
+    for (const BlockInfo &b : g->blocks) total_bytes += chunk_bytes(b);
+    uint64_t cap = opt.device_cap_bytes ? opt.device_cap_bytes : total_bytes;
+    cap = std::min(cap, total_bytes);
+    cap = cap / kAlign * kAlign;
+    for (const Task &t : g->tasks) {
+        uint64_t need = chunk_bytes(g->blocks[t.bij]);
+        if (t.bik != t.bij) need += chunk_bytes(g->blocks[t.bik]);
+        if (t.bjk != t.bij && t.bjk != t.bik) need += chunk_bytes(g->blocks[t.bjk]);
+        PGABB_REQUIRE(need <= cap, PGABB_ENOMEM,
+                      "device cap of %llu bytes cannot hold the %llu bytes of task (%d, %d, %d)",
+                      static_cast<unsigned long long>(cap), static_cast<unsigned long long>(need),
+                      t.i, t.j, t.k);
+    }
+
+    const int nstreams = opt.num_streams > 0 ? std::min(opt.num_streams, 16) : 4;
+    std::vector<hipStream_t> cs(nstreams);
+    hipStream_t copy_s = nullptr;
+    PGABB_HIP(hipStreamCreateWithFlags(&copy_s, hipStreamNonBlocking));
+    for (auto &x : cs) PGABB_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+
+    // device pool and per-run arrays
+    DArray<uint8_t> pool(static_cast<size_t>(cap), s);
+    DArray<TaskDesc> ddesc(static_cast<size_t>(T), s);
+    DArray<int64_t> dpre(static_cast<size_t>(2 * T + 1), s);
+    DArray<unsigned long long> dcnt(static_cast<size_t>(2 * T), s);  // counts then window counters
+    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * 2 * T, s));
+    PinnedArray<TaskDesc> hdesc;
+    hdesc.reset(static_cast<size_t>(T));
+    PinnedArray<int64_t> hpre;
+    hpre.reset(static_cast<size_t>(2 * T + 1));
+    PGABB_HIP(hipStreamSynchronize(s));
+
+    RangePool rp(cap);
+    std::vector<uint64_t> where(nblk, UINT64_MAX);   // pool offset of resident blocks
+    std::vector<int32_t> last_window(nblk, -1);      // last window that reads the block
+    std::list<int32_t> lru;                           // resident blocks, least recent first
+    std::vector<std::list<int32_t>::iterator> lru_pos(nblk);
+    std::vector<hipEvent_t> done;                     // per window
+    std::vector<hipEvent_t> copied;
+
+    int32_t max_wk = 0;
+    for (int32_t t = 0; t < T; ++t) max_wk = std::max(max_wk, g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k]);
+    const int mode = mode_of_option(opt.kernel);
+    const int words = choose_lds_words(mode, g->max_out, max_wk);
+    const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
+    const int grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : 8;
+    const int window_tasks = 64;
+    const uint64_t window_new_bytes = std::max<uint64_t>(cap / 4, 64ull << 20);
+
+    std::vector<int64_t> chunk_dev(nblk, 0);  // in int32 words from pool start
+    uint64_t h2d = 0;
+    int32_t next_task = 0;
+    int32_t win = 0;
+    int64_t pre_at = 0;
+
+    auto touch = [&](int32_t b) {
+        lru.erase(lru_pos[b]);
+        lru.push_back(b);
+        lru_pos[b] = std::prev(lru.end());
+    };
+
+    try {
+        while (next_task < T) {
+            // ---- form a window: tasks whose blocks fit together
+            std::vector<int32_t> wtasks;
+            std::vector<char> in_window(nblk, 0);
+            uint64_t pinned_bytes = 0, new_bytes = 0;
+            while (next_task < T && static_cast<int>(wtasks.size()) < window_tasks) {
+                const Task &t = g->tasks[next_task];
+                // bytes this task adds to the window (its block ids may repeat)
+                uint64_t add = 0, add_new = 0;
+                int32_t seen[3] = {-1, -1, -1};
+                int ns = 0;
+                for (int32_t b : {t.bij, t.bik, t.bjk}) {
+                    bool rep = in_window[b] != 0;
+                    for (int q = 0; q < ns; ++q) rep = rep || seen[q] == b;
+                    if (rep) continue;
+                    seen[ns++] = b;
+                    add += chunk_bytes(g->blocks[b]);
+                    if (where[b] == UINT64_MAX) add_new += chunk_bytes(g->blocks[b]);
+                }
+                if (!wtasks.empty() && (pinned_bytes + add > cap || new_bytes + add_new > window_new_bytes))
+                    break;
+                for (int32_t b : {t.bij, t.bik, t.bjk}) in_window[b] = 1;
+                pinned_bytes += add;
+                new_bytes += add_new;
+                wtasks.push_back(next_task++);
+            }
+
+            // ---- make the window's blocks resident.  If first-fit cannot place
+            // a block even with every block outside the window evicted (the pool
+            // is fragmented), wait for all in-flight work, empty the cache and
+            // place the window again into the empty pool, where it fits.
+            std::vector<int32_t> loads;
+            bool placed = false;
+            for (int attempt = 0; attempt < 2 && !placed; ++attempt) {
+                loads.clear();
+                placed = true;
+                for (int32_t ti : wtasks) {
+                    for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) {
+                        if (where[b] != UINT64_MAX) {
+                            touch(b);
+                            continue;
+                        }
+                        const uint64_t need = chunk_bytes(g->blocks[b]);
+                        uint64_t off = rp.alloc(need);
+                        while (off == UINT64_MAX) {
+                            auto it = lru.begin();
+                            while (it != lru.end() && in_window[*it]) ++it;
+                            if (it == lru.end()) break;
+                            const int32_t v = *it;
+                            if (last_window[v] >= 0) PGABB_HIP(hipEventSynchronize(done[last_window[v]]));
+                            rp.release(where[v], chunk_bytes(g->blocks[v]));
+                            where[v] = UINT64_MAX;
+                            lru.erase(it);
+                            off = rp.alloc(need);
+                        }
+                        if (off == UINT64_MAX) {
+                            placed = false;
+                            break;
+                        }
+                        where[b] = off;
+                        chunk_dev[b] = static_cast<int64_t>(off / sizeof(int32_t));
+                        lru.push_back(b);
+                        lru_pos[b] = std::prev(lru.end());
+                        loads.push_back(b);
+                    }
+                    if (!placed) break;
+                }
+                if (!placed) {
+                    for (auto x : cs) PGABB_HIP(hipStreamSynchronize(x));
+                    PGABB_HIP(hipStreamSynchronize(copy_s));
+                    for (int32_t v : lru) where[v] = UINT64_MAX;
+                    lru.clear();
+                    rp = RangePool(cap);
+                }
+            }
+            PGABB_REQUIRE(placed, PGABB_ENOMEM, "device cap of %llu bytes cannot hold a window",
+                          static_cast<unsigned long long>(cap));
+            for (int32_t b : loads) {
+                const BlockInfo &bi = g->blocks[b];
+                const size_t bytes = static_cast<size_t>(bi.chunk_len) * sizeof(int32_t);
+                PGABB_HIP(hipMemcpyAsync(pool.get() + where[b], g->host_arena.get() + bi.chunk_off, bytes,
+                                         hipMemcpyHostToDevice, copy_s));
+                h2d += bytes;
+            }
+            hipEvent_t ce = nullptr, de = nullptr;
+            PGABB_HIP(hipEventCreateWithFlags(&ce, hipEventDisableTiming));
+            PGABB_HIP(hipEventCreateWithFlags(&de, hipEventDisableTiming));
+            copied.push_back(ce);
+            done.push_back(de);
+            PGABB_HIP(hipEventRecord(ce, copy_s));
+
+            // ---- descriptors and launch
+            const int32_t w0 = wtasks.front();
+            const int32_t W = static_cast<int32_t>(wtasks.size());
+            int64_t items = 0;
+            hpre[pre_at] = 0;
+            for (int32_t q = 0; q < W; ++q) {
+                const int32_t ti = wtasks[q];
+                hdesc[ti] = make_desc(g, reinterpret_cast<const int32_t *>(pool.get()), g->tasks[ti], ti,
+                                      chunk_dev.data());
+                items += g->blocks[g->tasks[ti].bij].nrows;
+                hpre[pre_at + q + 1] = items;
+            }
+            hipStream_t st = cs[win % nstreams];
+            PGABB_HIP(hipStreamWaitEvent(st, ce, 0));
+            PGABB_HIP(hipMemcpyAsync(ddesc.get() + w0, hdesc.get() + w0, sizeof(TaskDesc) * W,
+                                     hipMemcpyHostToDevice, st));
+            PGABB_HIP(hipMemcpyAsync(dpre.get() + pre_at, hpre.get() + pre_at, sizeof(int64_t) * (W + 1),
+                                     hipMemcpyHostToDevice, st));
+            CountArgs a;
+            a.tasks = ddesc.get() + w0;
+            a.item_pre = dpre.get() + pre_at;
+            a.ntasks = W;
+            a.grab = grab;
+            a.total = items;
+            a.counts = dcnt.get();
+            a.next = dcnt.get() + T + win;
+            launch_tc_tasks(a, mode, words, waves, st, 0);
+            PGABB_HIP(hipEventRecord(de, st));
+            for (int32_t ti : wtasks)
+                for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) last_window[b] = win;
+            pre_at += W + 1;
+            ++win;
+        }
+        for (auto x : cs) PGABB_HIP(hipStreamSynchronize(x));
+        PGABB_HIP(hipStreamSynchronize(copy_s));
+        g->task_counts.assign(T, 0);
+        PGABB_HIP(hipMemcpyAsync(g->task_counts.data(), dcnt.get(), sizeof(uint64_t) * T, hipMemcpyDeviceToHost, s));
+        PGABB_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        for (auto x : cs) (void)hipStreamSynchronize(x);
+        (void)hipStreamSynchronize(copy_s);
+        for (auto e : copied) (void)hipEventDestroy(e);
+        for (auto e : done) (void)hipEventDestroy(e);
+        for (auto x : cs) (void)hipStreamDestroy(x);
+        (void)hipStreamDestroy(copy_s);
+        throw;
+    }
+    for (auto e : copied) (void)hipEventDestroy(e);
+    for (auto e : done) (void)hipEventDestroy(e);
+    for (auto x : cs) (void)hipStreamDestroy(x);
+    (void)hipStreamDestroy(copy_s);
+    g->h2d_bytes = h2d;
+    g->kernel_launches = win;
+    uint64_t total = 0;
+    for (uint64_t c : g->task_counts) total += c;
+    return total;
+}
+
+}  // namespace pgabb

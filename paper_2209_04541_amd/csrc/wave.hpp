@@ -1,0 +1,80 @@
+// Wave64 helpers (CDNA: 64 lanes per wavefront).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace pgabb {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & (kWave - 1); }
+
+// Shuffles of 32- and 64-bit integers built from 32-bit lane moves.
+template <class T>
+__device__ __forceinline__ T shfl_up_t(T v, int d) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = static_cast<uint64_t>(v);
+        const uint32_t lo = __shfl_up(static_cast<uint32_t>(u), d);
+        const uint32_t hi = __shfl_up(static_cast<uint32_t>(u >> 32), d);
+        return static_cast<T>((static_cast<uint64_t>(hi) << 32) | lo);
+    } else {
+        return static_cast<T>(__shfl_up(static_cast<uint32_t>(v), d));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_xor_t(T v, int m) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = static_cast<uint64_t>(v);
+        const uint32_t lo = __shfl_xor(static_cast<uint32_t>(u), m);
+        const uint32_t hi = __shfl_xor(static_cast<uint32_t>(u >> 32), m);
+        return static_cast<T>((static_cast<uint64_t>(hi) << 32) | lo);
+    } else {
+        return static_cast<T>(__shfl_xor(static_cast<uint32_t>(v), m));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_t(T v, int src) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = static_cast<uint64_t>(v);
+        const uint32_t lo = __shfl(static_cast<uint32_t>(u), src);
+        const uint32_t hi = __shfl(static_cast<uint32_t>(u >> 32), src);
+        return static_cast<T>((static_cast<uint64_t>(hi) << 32) | lo);
+    } else {
+        return static_cast<T>(__shfl(static_cast<uint32_t>(v), src));
+    }
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (all lanes active).
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const T y = shfl_up_t(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Sum across the wave, returned to every lane.
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) x += shfl_xor_t(x, m);
+    return x;
+}
+
+// Order LDS accesses of the lanes of one wave: what a lane wrote before the
+// call is visible to every lane of the wave after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace pgabb

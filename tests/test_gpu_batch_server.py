@@ -1,0 +1,129 @@
+"""GPU parity of the batched form (one persistent, graph-captured launch over
+many graphs) and of the continuous-batching server, against the CPU oracle.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_04541_amd as P
+from paper_2209_04541_amd import gen
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_batch(count, n_range=(64, 1500), d_range=(8, 64)):
+    return [gen.batch_graph(g, n_range, d_range) for g in range(count)]
+
+
+def test_batch_matches_oracle_all_shapes():
+    gl = small_batch(160)
+    gl += [graphs.complete(40)[0], graphs.wheel(77)[0], (0, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+           (5, np.zeros(0, np.int32), np.zeros(0, np.int32)), graphs.messy(*graphs.cocktail_party(9)[0])]
+    want = np.array([oracle.tc(*g) for g in gl], np.uint64)
+    say("batch graphs", len(gl), "triangles", int(want.sum()))
+    with P.Batch(gl) as b:
+        auto = b.count()  # autotuned + captured
+        assert np.array_equal(auto, want)
+        for kernel in (P.KERNEL_HASH, P.KERNEL_BITMAP):
+            for waves in (2, 4, 8):
+                for grab in (1, 5):
+                    got = b.count(kernel=kernel, waves_per_block=waves, rows_per_grab=grab)
+                    assert np.array_equal(got, want), (kernel, waves, grab)
+        assert np.array_equal(b.count(per_graph=True), want)
+        # replays of the captured launch, with eager work in between
+        for rep in range(4):
+            assert np.array_equal(b.count(), want), rep
+            b.count(kernel=P.KERNEL_HASH, waves_per_block=2, rows_per_grab=3)
+
+
+def test_batch_degenerate():
+    with P.Batch([]) as b:
+        assert len(b.count()) == 0
+    z = np.zeros(0, np.int32)
+    with P.Batch([(0, z, z), (3, z, z)]) as b:
+        assert list(b.count()) == [0, 0]
+    loops = np.arange(4, dtype=np.int32)
+    with P.Batch([(4, loops, loops)]) as b:
+        assert list(b.count()) == [0]
+    with pytest.raises(P.PgabbError) as ei:
+        P.Batch([(3, np.array([0, 1], np.int32), np.array([1, 3], np.int32))])
+    assert ei.value.status == P.EINVAL
+
+
+def test_batch_workload_sample():
+    """Graphs of the 10,000-graph recipe at their real sizes (n up to 8192,
+    degree up to 64), a sample of 48."""
+    gl = [gen.batch_graph(g) for g in range(0, 480, 10)]
+    want = np.array([oracle.tc(*g) for g in gl], np.uint64)
+    with P.Batch(gl) as b:
+        assert np.array_equal(b.count(), want)
+        assert np.array_equal(b.count(per_graph=True), want)
+
+
+def _rmat_requests(k, seed0=500):
+    out = []
+    for r in range(k):
+        sc = 8 + (r * 7) % 7
+        ef = 8 + (r * 5) % 25
+        out.append(gen.rmat(sc, ef, gen.seed(seed0, r)))
+    return out
+
+
+def _wait(srv, tickets, timeout=60):
+    t0 = time.time()
+    res = {}
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t in res:
+                continue
+            done, cnt, ts, td = srv.poll(t)
+            if done:
+                res[t] = cnt
+        if time.time() - t0 > timeout:
+            raise TimeoutError("server did not finish")
+        time.sleep(0.001)
+    return [res[t] for t in tickets]
+
+
+@pytest.mark.parametrize("borrow", [False, True])
+def test_server_alone_equals_mix(borrow):
+    reqs = _rmat_requests(24)
+    want = [oracle.tc(*g) for g in reqs]
+    say("server requests", len(reqs), "borrow", borrow)
+    with P.Server(8 << 30, borrow=borrow) as srv:
+        alone = []
+        for g in reqs[:8]:
+            t = srv.submit(*g)
+            alone += _wait(srv, [t])
+        tickets = [srv.submit(*g) for g in reqs]
+        mix = _wait(srv, tickets)
+        srv.drain()
+        assert srv.launches() >= 2
+    assert alone == want[:8]
+    assert mix == want
+
+
+def test_server_small_budget_and_rejection():
+    reqs = _rmat_requests(10, seed0=600)
+    want = [oracle.tc(*g) for g in reqs]
+    biggest = max(len(g[1]) for g in reqs)
+    budget = biggest * 40 + 64 * (1 << 20)  # admits about one request at a time
+    with P.Server(budget) as srv:
+        tickets = [srv.submit(*g) for g in reqs]
+        assert _wait(srv, tickets) == want
+        n, s, d = gen.rmat(16, 32, gen.seed(601, 0))
+        with pytest.raises(P.PgabbError) as ei:
+            srv.submit(n, s, d)
+        assert ei.value.status == P.EBUDGET
+        with pytest.raises(P.PgabbError) as ei:
+            srv.submit(4, np.array([0], np.int32), np.array([7], np.int32))
+        assert ei.value.status == P.EINVAL

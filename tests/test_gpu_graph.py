@@ -1,0 +1,213 @@
+"""GPU parity of the graph path (build, partition, count) against the CPU
+oracle, through the C ABI.  Counts are integers: the bar is exact equality.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2209_04541_amd as P
+from paper_2209_04541_amd import gen
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_count(n, s, d, p=1, **kw):
+    with P.Graph(n, s, d) as g:
+        g.partition(p, cut_mode=kw.pop("cut_mode", P.CUT_NNZ), cuts=kw.pop("cuts", None))
+        return g.count(**kw) if kw else g.count()
+
+
+@pytest.mark.parametrize("name,g,expected", graphs.closed_forms(), ids=lambda x: x if isinstance(x, str) else "")
+def test_closed_forms(name, g, expected):
+    n, s, d = g
+    say("closed form", name, n, len(s))
+    for p in (1, 2, 3):
+        if p > max(n, 1):
+            continue
+        assert gpu_count(n, s, d, p) == expected, (name, p)
+    n2, s2, d2 = graphs.messy(n, s, d, seed=7)
+    assert gpu_count(n2, s2, d2, 2) == expected
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_vs_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 70))
+    m = int(rng.integers(0, 4 * n * n // 3 + 1))
+    s = rng.integers(0, n, size=m).astype(np.int32)
+    d = rng.integers(0, n, size=m).astype(np.int32)
+    want = graphs.brute_force(n, s, d)
+    say("random", seed, n, m, want)
+    for p in (1, 2, 5):
+        if p <= n:
+            assert gpu_count(n, s, d, p) == want
+    assert gpu_count(n, s, d, min(4, n), cut_mode=P.CUT_UNIFORM) == want
+
+
+@pytest.mark.parametrize("order_by_id", [False, True])
+def test_csr_bit_identical_to_oracle(order_by_id):
+    n, s, d = graphs.messy(*gen.rmat(13, 16, gen.seed(94, 0)), seed=5)
+    say("csr", n, len(s), order_by_id)
+    keys, deg, rk, row_off, col = oracle.oriented_csr(n, s, d, mode=1 if order_by_id else 0)
+    with P.Graph(n, s, d, order_by_id=order_by_id) as g:
+        r2, c2, k2 = g.export_csr()
+        info = g.info()
+    assert np.array_equal(r2, row_off)
+    assert np.array_equal(c2, col)
+    assert np.array_equal(k2, rk)
+    assert info["m"] == len(keys)
+    assert info["isolated"] == int((deg == 0).sum())
+    assert info["max_out_degree"] == int(np.diff(row_off).max())
+    assert info["probe_work"] == oracle.probe_work(n, row_off, col)
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 8, 13])
+def test_task_counts_equal_oracle_blocks(p):
+    n, s, d = gen.rmat(12, 12, gen.seed(95, p))
+    _, _, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    say("tasks", p, n, len(s))
+    for mode in (P.CUT_NNZ, P.CUT_UNIFORM):
+        with P.Graph(n, s, d) as g:
+            g.partition(p, cut_mode=mode)
+            total = g.count()
+            cuts = g.cuts()
+            ijk, cnt = g.task_counts()
+        B = oracle.block_counts(n, row_off, col, cuts)
+        got = np.zeros_like(B)
+        for (i, j, k), c in zip(ijk, cnt):
+            got[i, j, k] += c
+        assert np.array_equal(got, B), (p, mode)
+        assert total == int(B.sum())
+
+
+def test_explicit_cuts_with_empty_stripes():
+    n, s, d = gen.rmat(11, 16, gen.seed(96, 0))
+    want = oracle.tc(n, s, d)
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    cuts = np.array([0, 0, 700, 700, 1500, n, n], np.int32)
+    with P.Graph(n, s, d) as g:
+        g.partition(len(cuts) - 1, cuts=cuts)
+        assert g.count() == want
+        ijk, cnt = g.task_counts()
+    B = oracle.block_counts(n, row_off, col, cuts)
+    got = np.zeros_like(B)
+    for (i, j, k), c in zip(ijk, cnt):
+        got[i, j, k] += c
+    assert np.array_equal(got, B)
+
+
+@pytest.mark.parametrize("kernel", [P.KERNEL_HASH, P.KERNEL_BITMAP, P.KERNEL_SEARCH])
+@pytest.mark.parametrize("waves", [2, 4, 8])
+def test_forced_kernels_agree(kernel, waves):
+    n, s, d = gen.rgg(6000, 40, gen.seed(97, 0))
+    want = oracle.tc(n, s, d)
+    say("kernel", kernel, waves, want)
+    for p in (1, 4):
+        assert gpu_count(n, s, d, p, kernel=kernel, waves_per_block=waves, rows_per_grab=3) == want
+
+
+def test_device_edges_torch_stream():
+    import torch
+    n, s, d = gen.rmat(14, 16, gen.seed(98, 0))
+    want = oracle.tc(n, s, d)
+    ds = torch.from_numpy(s).cuda()
+    dd = torch.from_numpy(d).cuda()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with P.Graph(n, ds, dd) as g:
+            g.partition(4)
+            assert g.count() == want
+    torch.cuda.synchronize()
+
+
+def test_device_ids_out_of_range():
+    import torch
+    ds = torch.tensor([0, 1, 9], dtype=torch.int32, device="cuda")
+    dd = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(P.PgabbError) as ei:
+        P.Graph(5, ds, dd)
+    assert ei.value.status == P.EINVAL
+
+
+def test_degenerate_graphs():
+    z = np.zeros(0, np.int32)
+    assert gpu_count(0, z, z, 1) == 0
+    assert gpu_count(1, z, z, 1) == 0
+    assert gpu_count(7, z, z, 3) == 0
+    loops = np.arange(5, dtype=np.int32)
+    assert gpu_count(5, loops, loops, 2) == 0
+    assert gpu_count(2, np.array([0], np.int32), np.array([1], np.int32), 2) == 0
+    tri_s = np.array([0, 1, 2, 2, 1], np.int32)
+    tri_d = np.array([1, 2, 0, 0, 1], np.int32)
+    assert gpu_count(3, tri_s, tri_d, 1) == 1
+    assert gpu_count(3, tri_s, tri_d, 3) == 1
+    # p larger than the number of non-isolated vertices, and the maximum p
+    n, s, d = graphs.complete(9)[0]
+    assert gpu_count(200, s, d, 64) == 84
+    with P.Graph(200, s, d) as g:
+        with pytest.raises(P.PgabbError):
+            g.partition(65)
+        with pytest.raises(P.PgabbError):
+            g.partition(0)
+    # count before partition means p = 1
+    with P.Graph(n, s, d) as g:
+        assert g.count() == 84
+        assert g.info()["p"] == 1
+
+
+@pytest.mark.parametrize("cap_kib", [0, 64, 256, 4096])
+def test_streamed_blocks_under_caps(cap_kib):
+    n, s, d = gen.rmat(14, 16, gen.seed(99, 0))
+    want = oracle.tc(n, s, d)
+    say("stream cap KiB", cap_kib, want)
+    with P.Graph(n, s, d) as g:
+        g.partition(8)
+        info0 = g.info()
+        try:
+            got = g.count(device_cap_bytes=cap_kib * 1024, stream_blocks=True, num_streams=3)
+        except P.PgabbError as e:
+            # a cap below one task's three blocks is refused, never miscounted
+            assert e.status == P.ENOMEM and cap_kib * 1024 < info0["block_bytes"]
+            return
+        info = g.info()
+        assert got == want
+        assert info["h2d_bytes"] >= info0["block_bytes"] * 0.99
+        # counting again from the host store gives the same answer
+        assert g.count(device_cap_bytes=cap_kib * 1024) == want
+
+
+def test_plain_workload():
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        gold = json.load(f)["plain"]
+    n, s, d = gen.plain_graph()
+    with P.Graph(n, s, d) as g:
+        g.partition(1)
+        assert g.count() == gold["triangles"]
+        info = g.info()
+    assert info["m"] == gold["m"] and info["probe_work"] == gold["probe_work"]
+
+
+@pytest.mark.parametrize("p", [1, 8])
+def test_block_workload(p):
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        gold = json.load(f)["block"]
+    n, s, d = gen.block_graph()
+    say("block workload p", p)
+    with P.Graph(n, s, d) as g:
+        g.partition(p)
+        assert g.count() == gold["triangles"]
+        info = g.info()
+    for k in ("m", "isolated", "max_out_degree", "probe_work"):
+        assert info[k] == gold[k], k
