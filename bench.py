@@ -1,11 +1,13 @@
 #!/usr/bin/env python3
 """Throughput of block-partitioned triangle counting on one MI355X.
 
-One step is one pass of the whole path over the R-MAT scale-20 edge list
-(16.8 M int32 pairs already resident in HBM): clean + degree-rank + orient
-(CSR build), symmetric 8 x 8 partition into blocks and block-list tasks, and
-the triangle count returned to the host as a uint64.  `value` is m' (the
-graph's distinct undirected edges) divided by the step time.
+Default workload ("block"): one step is one pass of the whole path over the
+R-MAT scale-20 edge list (16.8 M int32 pairs already resident in HBM):
+clean + degree-rank + orient (CSR build), symmetric 8 x 8 partition into
+blocks and block-list tasks, and the triangle count returned to the host as a
+uint64.  `value` is m' (the graph's distinct undirected edges) divided by the
+step time.  Other workloads (--workload plain|ooc|batch|served) print their
+own line; they are not the default.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU.
@@ -15,6 +17,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -22,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "TC edges/sec at 1 MI355X (% HBM roofline); batched graphs/sec; p50/p99 latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tc_block_rmat20_p8.json")
-KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_amd/csrc/count.hip"]
+KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_amd/csrc/count.hip",
+                  "paper_2209_04541_amd/csrc/count.hpp"]
 
 
 def kernel_digest():
@@ -34,11 +37,11 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launches_per_step):
+def measured_traffic(name):
     """HBM bytes per launch of the counting kernel from the committed
     rocprofv3 counter summary, or None when the kernel changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
     except OSError:
         return None
@@ -47,47 +50,48 @@ def measured_traffic(launches_per_step):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(n, s, d, m):
-    import oracle
-    t0 = time.perf_counter()
-    tri = oracle.tc(n, s, d)
-    dt = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "edges/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "one full oracle pass (clean, rank, orient, merge count) over the whole "
-                      "R-MAT scale-20 graph, %.1f s" % dt}, tri
+def golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", "workload_counts.json")) as f:
+        return json.load(f).get(name)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--kernel", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
+
+def base_line(args, value, unit, ms, config, dtype="int32"):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def roofline(W, m, kernel_ms, traffic_file):
+    # algorithmic bytes of one counting launch: every probed element of a row
+    # A_jk[v] (4 B each, W of them), every staged row and edge row once (4 B
+    # each per oriented edge) and the two row offsets of v (8 B per edge)
+    alg = 4 * W + 16 * m
+    achieved = alg / (kernel_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_file)}, alg
+
+
+# ---------------------------------------------------------------- graph
+
+def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cpu_sample=None):
     import numpy as np
     import torch
 
     import paper_2209_04541_amd as P
-    from paper_2209_04541_amd import gen
 
-    torch.cuda.set_device(0)
-    n, s, d = gen.rmat(args.scale, 16, gen.seed(2, 0))
     ds = torch.from_numpy(s).cuda()
     dd = torch.from_numpy(d).cuda()
     torch.cuda.synchronize()
-    opts = P.options(kernel=args.kernel)
+    opts = opts or P.options(kernel=args.kernel)
 
     def step():
         g = P.Graph(n, ds, dd)
-        g.partition(args.p)
+        g.partition(p)
         c = g.count(opts)
         info = g.info()
         g.close()
@@ -96,70 +100,352 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    infos = []
-    counts = []
+    infos, counts, step_ms = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        a = time.perf_counter()
         c, info = step()
+        step_ms.append((time.perf_counter() - a) * 1e3)
         counts.append(c)
         infos.append(info)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1000.0 / args.steps
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
 
     m = infos[0]["m"]
     W = infos[0]["probe_work"]
-    kernel_ms = float(np.mean([i["t_kernel_ms"] for i in infos]))
-    launches = infos[0]["kernel_launches"]
-    count_ms = float(np.mean([i["t_count_ms"] for i in infos]))
-    build_ms = float(np.mean([i["t_build_ms"] for i in infos]))
-    part_ms = float(np.mean([i["t_partition_ms"] for i in infos]))
-    # algorithmic bytes of one counting launch: every probed row A_jk[v]
-    # (4 B per element, W elements), every staged row and edge list once
-    # (4 B each per oriented edge) and the two row offsets of v (8 B)
-    alg_bytes = 4 * W + 16 * m
-    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-    traffic = measured_traffic(launches)
-
-    gold_tri = None
-    if args.scale == 20:
-        with open(os.path.join(ROOT, "tests", "golden", "workload_counts.json")) as f:
-            gold_tri = json.load(f)["block"]["triangles"]
-
-    out = {
-        "metric": METRIC,
-        "value": m / (ms / 1e3),
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "R-MAT scale %d, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), "
-                               "seed (2,0), %dx%d blocks" % (args.scale, args.p, args.p),
-                   "n": n, "m_input": len(s), "m": m, "p": args.p},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    launches = max(1, infos[0]["kernel_launches"])
+    kernel_ms = float(np.mean([i["t_kernel_ms"] for i in infos])) / launches
+    roof, alg = roofline(W, m, kernel_ms * launches, traffic_file)
+    gold = golden(gold_name) if gold_name else None
+    out = base_line(args, m / (ms / 1e3), "edges/s", ms, {
+        "workload": workload, "n": n, "m_input": len(s), "m": m, "p": p})
+    out["roofline"] = roof
+    out.update({
         "triangles": counts[0],
-        "parity": (gold_tri is None or all(c == gold_tri for c in counts)),
-        "count_edges_per_s": m / (count_ms / 1e3),
-        "kernel_edges_per_s": m / (kernel_ms / 1e3),
-        "t_build_ms": build_ms,
-        "t_partition_ms": part_ms,
-        "t_count_ms": count_ms,
-        "t_kernel_ms": kernel_ms,
+        "parity": gold is None or all(c == gold["triangles"] for c in counts),
+        "step_ms_p50": pct(step_ms, 50), "step_ms_p99": pct(step_ms, 99),
+        "count_edges_per_s": m / (float(np.mean([i["t_count_ms"] for i in infos])) / 1e3),
+        "kernel_edges_per_s": m / (kernel_ms * launches / 1e3),
+        "t_build_ms": float(np.mean([i["t_build_ms"] for i in infos])),
+        "t_partition_ms": float(np.mean([i["t_partition_ms"] for i in infos])),
+        "t_count_ms": float(np.mean([i["t_count_ms"] for i in infos])),
+        "t_kernel_ms_per_launch": kernel_ms,
         "kernel_launches_per_step": launches,
-        "algorithmic_bytes_per_launch": alg_bytes,
-    }
-    if not args.no_cpu_baseline:
-        cb, tri = cpu_baseline(n, s, d, m)
+        "algorithmic_bytes_per_step": alg,
+        "probe_work": W,
+        "h2d_bytes_per_step": infos[0]["h2d_bytes"],
+        "block_bytes": infos[0]["block_bytes"],
+    })
+    if not args.no_cpu_baseline and cpu_sample is not None:
+        cb, tri = cpu_sample()
         out["cpu_baseline"] = cb
-        out["parity"] = out["parity"] and tri == counts[0]
-    print(json.dumps(out), flush=True)
+        if tri is not None:
+            out["parity"] = out["parity"] and tri == counts[0]
+    return out
+
+
+def oracle_full_pass(n, s, d, m, label):
+    def run():
+        import oracle
+        t0 = time.perf_counter()
+        tri = oracle.tc(n, s, d)
+        dt = time.perf_counter() - t0
+        return {"value": m / dt, "unit": "edges/s", "cores": oracle.threads(), "kind": "oracle",
+                "sample": "one full oracle pass (clean, rank, orient, merge count) over %s, %.1f s"
+                          % (label, dt)}, tri
+    return run
+
+
+def bench_block(args):
+    from paper_2209_04541_amd import gen
+    n, s, d = gen.rmat(args.scale, 16, gen.seed(2, 0))
+    gold = "block" if args.scale == 20 else None
+    m_est = golden("block")["m"] if args.scale == 20 else len(s)
+    return run_graph(args, n, s, d, args.p or 8, gold,
+                     "R-MAT scale %d, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed (2,0), "
+                     "%dx%d blocks" % (args.scale, args.p or 8, args.p or 8),
+                     "traffic_tc_block_rmat20_p8.json",
+                     cpu_sample=oracle_full_pass(n, s, d, m_est, "the whole R-MAT scale-%d graph" % args.scale))
+
+
+def bench_plain(args):
+    from paper_2209_04541_amd import gen
+    n, s, d = gen.plain_graph()
+    return run_graph(args, n, s, d, 1, "plain", "ER G(n=4096, m=32768), seed (1,0), p=1",
+                     "traffic_tc_plain.json",
+                     cpu_sample=oracle_full_pass(n, s, d, 32768, "the whole ER graph"))
+
+
+def bench_ooc(args):
+    """R-MAT scale 24, 32x32 blocks streamed from pinned host memory under an
+    8 GB device cap; the step includes the host-to-device block copies."""
+    import paper_2209_04541_amd as P
+    from paper_2209_04541_amd import gen
+    n, s, d = gen.rmat(24, 16, gen.seed(3, 0))
+    cap = args.cap_gb * (1 << 30)
+    opts = P.options(kernel=args.kernel, device_cap_bytes=int(cap), stream_blocks=True)
+
+    def cpu_sample():
+        # a bounded sample: the oracle's merge count over the rows of the top
+        # 1/64 of the rank range (the densest rows), scaled to edges/s by the
+        # oriented edges those rows own
+        import numpy as np
+        import oracle
+        t0 = time.perf_counter()
+        keys, deg, rk, row_off, col = oracle.oriented_csr(n, s, d)
+        t_build = time.perf_counter() - t0
+        rows = row_off.shape[0] - 1
+        lo = rows - rows // 64
+        off = np.zeros(rows + 1, np.int64)
+        off[lo + 1:] = row_off[lo + 1:] - row_off[lo]
+        t1 = time.perf_counter()
+        # rows below lo are empty in this CSR; probed rows v >= lo are intact
+        oracle.count_csr(rows, off, np.ascontiguousarray(col[row_off[lo]:]))
+        dt = time.perf_counter() - t1
+        m_rows = int(row_off[-1] - row_off[lo])
+        return {"value": m_rows / dt, "unit": "edges/s", "cores": oracle.threads(), "kind": "oracle",
+                "sample": "oracle merge count over the top 1/64 of the rank range (%d oriented edges, "
+                          "%.1f s; the oracle's build of the whole graph took %.1f s)"
+                          % (m_rows, dt, t_build)}, None
+
+    return run_graph(args, n, s, d, 32, "ooc",
+                     "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed (3,0), 32x32 "
+                     "blocks in pinned host memory, %d GiB device cap" % args.cap_gb,
+                     "traffic_tc_ooc.json", opts=opts, cpu_sample=cpu_sample)
+
+
+# ---------------------------------------------------------------- batch
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_2209_04541_amd as P
+    from paper_2209_04541_amd import gen
+
+    G = args.graphs
+    t0 = time.perf_counter()
+    nv = np.empty(G, np.int32)
+    parts_s, parts_d = [], []
+    for g in range(G):
+        n, s, d = gen.batch_graph(g)
+        nv[g] = n
+        parts_s.append(s)
+        parts_d.append(d)
+    eoff = np.zeros(G + 1, np.int64)
+    eoff[1:] = np.cumsum([len(x) for x in parts_s])
+    src = np.concatenate(parts_s)
+    dst = np.concatenate(parts_d)
+    del parts_s, parts_d
+    t_gen = time.perf_counter() - t0
+    ds = torch.from_numpy(src).cuda()
+    dd = torch.from_numpy(dst).cuda()
+    torch.cuda.synchronize()
+    b = P.Batch((nv, eoff, ds, dd))
+    t_build = b.times()[0]
+    t_tune0 = time.perf_counter()
+    counts = b.count()  # autotune + capture on first use
+    t_tune = time.perf_counter() - t_tune0
+    for _ in range(args.warmup):
+        b.count()
+    rep_ms = []
+    for _ in range(args.steps):
+        c2 = b.count()
+        rep_ms.append(b.times()[1])
+        assert np.array_equal(c2, counts)
+    per_ms = []
+    for _ in range(max(1, args.steps // 5)):
+        c3 = b.count(per_graph=True)
+        per_ms.append(b.times()[1])
+        assert np.array_equal(c3, counts)
+    ms = float(np.median(rep_ms))
+    pg = float(np.median(per_ms))
+    mtot = int(eoff[-1])
+    out = base_line(args, G / (ms / 1e3), "graphs/s", ms, {
+        "workload": "%d graphs, seed (4,g): even g random geometric, odd g Erdos-Renyi, n ~ U{64..8192}, "
+                    "average degree ~ U{8..64}; one persistent HIP-graph launch, autotuned" % G,
+        "graphs": G, "pairs": mtot, "vertices": int(nv.sum())})
+    out.update({
+        "per_graph_launches_ms": pg, "per_graph_launches_graphs_per_s": G / (pg / 1e3),
+        "speedup_vs_per_graph": pg / ms, "batched_build_ms": t_build,
+        "end_to_end_graphs_per_s": G / ((t_build + ms) / 1e3), "autotune_s": t_tune,
+        "generation_s": t_gen, "triangles_total": int(counts.sum()),
+    })
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = list(range(0, G, max(1, G // 200)))
+        t1 = time.perf_counter()
+        ok = True
+        for g in sample:
+            n, s, d = gen.batch_graph(g)
+            ok = ok and oracle.tc(n, s, d) == int(counts[g])
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "graphs/s", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": "%d of the %d graphs (every %d-th), %.1f s"
+                               % (len(sample), G, max(1, G // 200), dt)}
+        out["parity"] = ok
+    b.close()
+    return out
+
+
+# ---------------------------------------------------------------- served
+
+def bench_served(args):
+    """Poisson request stream against the continuous-batching server, and the
+    same trace served one request at a time (plain sequential launches)."""
+    import numpy as np
+    import torch
+
+    import paper_2209_04541_amd as P
+    from paper_2209_04541_amd import gen
+
+    torch.cuda.init()
+    pool_size = args.pool
+    pool = []
+    for r in range(pool_size):
+        sc, ef = gen.served_params(r)
+        n, s, d = gen.served_graph(r)
+        # pinned host copies so request uploads run at full link speed
+        ps = torch.from_numpy(s).pin_memory().numpy()
+        pd = torch.from_numpy(d).pin_memory().numpy()
+        pool.append((n, ps, pd, sc, ef))
+    rate = args.rate
+    arrivals = gen.poisson_arrivals(rate, args.duration, gen.seed(5, 0))
+    reqs = [pool[i % pool_size] for i in range(len(arrivals))]
+
+    def drive(submit_fn):
+        """Submit requests at their arrival times; returns per-request
+        (arrival, done) times."""
+        t_start = time.perf_counter()
+        for i, a in enumerate(arrivals):
+            now = time.perf_counter() - t_start
+            if a > now:
+                time.sleep(a - now)
+            submit_fn(i, t_start)
+        return t_start
+
+    # continuous batching
+    with P.Server(args.budget_gb << 30, borrow=True) as srv:
+        tickets = [None] * len(arrivals)
+        sub_t = [0.0] * len(arrivals)
+        clock0 = srv.now()
+
+        def sub(i, t_start):
+            n, s, d, _, _ = reqs[i]
+            sub_t[i] = srv.now()
+            tickets[i] = srv.submit(n, s, d)
+
+        t_start = drive(sub)
+        srv.drain()
+        lat, res = [], []
+        for i, t in enumerate(tickets):
+            done, cnt, ts, td = srv.poll(t)
+            lat.append((td - (clock0 + arrivals[i])) * 1e3)
+            res.append(cnt)
+        t_end = max(srv.poll(t)[3] for t in tickets)
+        span = t_end - clock0
+        launches = srv.launches()
+
+    # sequential FIFO: one request at a time, build then count
+    seq_lat, seq_res = [], []
+    t0 = time.perf_counter()
+    free_at = 0.0
+    for i, a in enumerate(arrivals):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        n, s, d, _, _ = reqs[i]
+        with P.Graph(n, s, d) as g:
+            g.partition(1)
+            c = g.count()
+        done = time.perf_counter() - t0
+        seq_lat.append((done - a) * 1e3)
+        seq_res.append(c)
+    seq_span = time.perf_counter() - t0
+
+    edges = sum(len(reqs[i][1]) for i in range(len(arrivals)))
+    out = base_line(args, len(arrivals) / span, "requests/s", span * 1e3 / max(1, len(arrivals)), {
+        "workload": "Poisson arrivals at %.0f req/s for %.1f s; request r: R-MAT scale ~ U{10..22}, "
+                    "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget"
+                    % (rate, args.duration, pool_size, args.budget_gb),
+        "requests": len(arrivals), "pool": pool_size})
+    out.update({
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "input_pairs_per_s": edges / span,
+        "launches": launches,
+        "sequential": {"p50_ms": pct(seq_lat, 50), "p99_ms": pct(seq_lat, 99),
+                       "requests_per_s": len(arrivals) / seq_span},
+        "alone_equals_mix": res == seq_res,
+    })
+    if not args.no_cpu_baseline:
+        import oracle
+        small = [i for i in range(pool_size) if pool[i][3] <= 16][:8]
+        t1 = time.perf_counter()
+        ok = True
+        for i in small:
+            n, s, d, _, _ = pool[i]
+            ok = ok and oracle.tc(n, s, d) == res[i] if i < len(res) else ok
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": len(small) / dt if dt > 0 else None, "unit": "requests/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": "%d pool requests of scale <= 16 counted by the oracle, %.1f s"
+                               % (len(small), dt)}
+        out["parity"] = ok and res == seq_res
+    return out
+
+
+def bench_copy(args):
+    """A plain device-to-device copy of a known size: the reference that
+    scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    nbytes = args.copy_mib << 20
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        t.append(e0.elapsed_time(e1))
+    ms = min(t)
+    out = base_line(args, 2 * nbytes / (ms / 1e3) / 1e9, "GB/s", ms,
+                    {"workload": "device copy of %d MiB (read %d MiB + write %d MiB)"
+                                 % (args.copy_mib, args.copy_mib, args.copy_mib)})
+    out["bytes_read_per_copy"] = nbytes
+    out["bytes_written_per_copy"] = nbytes
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="block", choices=["block", "plain", "ooc", "batch", "served", "copy"])
+    ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--kernel", type=int, default=0)
+    ap.add_argument("--cap-gb", type=int, default=8)
+    ap.add_argument("--graphs", type=int, default=10000)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=0.25)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--budget-gb", type=int, default=64)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    fn = {"block": bench_block, "plain": bench_plain, "ooc": bench_ooc, "batch": bench_batch,
+          "served": bench_served, "copy": bench_copy}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

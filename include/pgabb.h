@@ -84,8 +84,11 @@ typedef struct pgabb_tc_options {
     int32_t num_streams;       /* compute streams of the streamer (0 = 4) */
     uint64_t device_cap_bytes; /* 0 = no cap; otherwise block cache bound */
     uint32_t flags;            /* PGABB_OPT_* */
-    int32_t waves_per_block;   /* 0 = library default */
-    int32_t rows_per_grab;     /* 0 = library default */
+    int32_t waves_per_block;   /* 2, 4 or 8 waves per workgroup (0 = default) */
+    int32_t rows_per_grab;     /* rows a wave takes per work-counter update (0 = default) */
+    int32_t unroll;            /* 64-element row chunks each wave loads ahead of
+                                  probing: 1, 2, 4 or 8 (0 = default) */
+    int32_t reserved;          /* must be 0 */
 } pgabb_tc_options;
 
 typedef struct pgabb_graph pgabb_graph;

@@ -38,7 +38,8 @@ class PgabbError(RuntimeError):
 class TcOptions(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("num_streams", ctypes.c_int32),
                 ("device_cap_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -158,7 +159,7 @@ def _edges(src, dst):
 
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
-            waves_per_block=0, rows_per_grab=0):
+            waves_per_block=0, rows_per_grab=0, unroll=0):
     o = TcOptions()
     o.kernel = kernel
     o.num_streams = num_streams
@@ -166,6 +167,7 @@ def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks
     o.flags = OPT_STREAM if stream_blocks else 0
     o.waves_per_block = waves_per_block
     o.rows_per_grab = rows_per_grab
+    o.unroll = unroll
     return o
 
 

@@ -108,14 +108,19 @@ __global__ void k_compact_b(const uint64_t *__restrict__ keys, const uint32_t *_
         if (flag[e]) out[pos[e]] = keys[e];
 }
 
+// Keys sorted by (g, lo, hi): lo ends form runs (one atomic per run), hi
+// ends add one each.
 __global__ void k_degrees_b(const uint64_t *__restrict__ keys, int64_t m, int nb,
                             const int64_t *__restrict__ vbase, int32_t *__restrict__ deg) {
     const uint64_t mask = (1ull << nb) - 1;
-    for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B) {
-        const uint64_t k = keys[e];
-        const int64_t vb = vbase[k >> (2 * nb)];
-        atomicAdd(&deg[vb + ((k >> nb) & mask)], 1);
-        atomicAdd(&deg[vb + (k & mask)], 1);
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        const uint64_t k = valid ? keys[e] : 0ull;
+        const int64_t vb = valid ? vbase[k >> (2 * nb)] : 0;
+        add_run_lengths(valid, vb + static_cast<int64_t>((k >> nb) & mask), deg);
+        if (valid) atomicAdd(&deg[vb + (k & mask)], 1);
     }
 }
 
@@ -156,14 +161,17 @@ __global__ void k_orient_b(const uint64_t *__restrict__ ukeys, int64_t m, int nb
 }
 
 __global__ void k_union_csr_b(const uint64_t *__restrict__ okeys, int64_t m, int nb,
-                              const int64_t *__restrict__ vbase, uint32_t *__restrict__ outdeg,
+                              const int64_t *__restrict__ vbase, int32_t *__restrict__ outdeg,
                               int32_t *__restrict__ col) {
     const uint64_t mask = (1ull << nb) - 1;
-    for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B) {
-        const uint64_t k = okeys[e];
-        const int64_t vb = vbase[k >> (2 * nb)];
-        atomicAdd(&outdeg[vb + ((k >> nb) & mask)], 1u);
-        col[e] = static_cast<int32_t>(vb + (k & mask));
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        const uint64_t k = valid ? okeys[e] : 0ull;
+        const int64_t vb = valid ? vbase[k >> (2 * nb)] : 0;
+        add_run_lengths(valid, vb + static_cast<int64_t>((k >> nb) & mask), outdeg);
+        if (valid) col[e] = static_cast<int32_t>(vb + (k & mask));
     }
 }
 
@@ -223,9 +231,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
     }
     BlockRef ref;
     ref.rptr = a.rptr;
-    ref.rid = a.rows;
+    ref.items = nullptr;
     ref.col = a.col;
-    ref.nrows = 0;
+    ref.nitems = 0;
     ref.width = 0;
     for (;;) {
         unsigned long long g0 = 0;
@@ -246,7 +254,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
             }
             const int64_t vb = a.vbase[gid];
             const int32_t nv = static_cast<int32_t>(a.vbase[gid + 1] - vb);
-            cnt += tc_row<MODE, LDS_WORDS>(ref, ref, ref, nv, static_cast<int32_t>(it), lds,
+            const int32_t u = a.rows[it];
+            cnt += tc_row<MODE, LDS_WORDS>(ref, ref, ref, nv, u, a.rptr[u], a.rptr[u + 1], lds,
                                            static_cast<int32_t>(vb));
         }
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
@@ -502,7 +511,8 @@ void batch_build(pgabb_batch *b, const int32_t *n, const int64_t *eoff, const in
             PGABB_HIP(hipGetLastError());
             if (radix_sort_u64_bits(k1, k0, nullptr, nullptr, mu, 0, kbits, s)) std::swap(k0, k1);
             b->col.reset(mu, s);
-            k_union_csr_b<<<cap_grid(mu), B, 0, s>>>(k1, mu, nb, b->dvbase.get(), outdeg.get(), b->col.get());
+            k_union_csr_b<<<cap_grid(mu), B, 0, s>>>(k1, mu, nb, b->dvbase.get(),
+                                                     reinterpret_cast<int32_t *>(outdeg.get()), b->col.get());
             PGABB_HIP(hipGetLastError());
         }
     }

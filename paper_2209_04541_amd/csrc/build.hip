@@ -58,13 +58,19 @@ __global__ void k_compact(const uint64_t *__restrict__ keys, const uint32_t *__r
         if (flag[e]) out[pos[e]] = keys[e];
 }
 
+// Distinct keys are sorted by (lo, hi): the lo ends form runs, so each run
+// adds its length once; the hi ends are scattered and add one each.  The loop
+// bound is uniform across a wave so every lane takes part in the ballots.
 __global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int nb,
                           int32_t *__restrict__ deg) {
     const uint64_t mask = (1ull << nb) - 1;
-    for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B) {
-        const uint64_t k = keys[e];
-        atomicAdd(&deg[k >> nb], 1);
-        atomicAdd(&deg[k & mask], 1);
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        const uint64_t k = valid ? keys[e] : 0ull;
+        add_run_lengths(valid, static_cast<int64_t>(k >> nb), deg);
+        if (valid) atomicAdd(&deg[k & mask], 1);
     }
 }
 
@@ -101,10 +107,13 @@ __global__ void k_orient(const uint64_t *__restrict__ ukeys, int64_t m, int nb,
 __global__ void k_row_counts_and_cols(const uint64_t *__restrict__ okeys, int64_t m, int nb,
                                       int32_t *__restrict__ outdeg, int32_t *__restrict__ col) {
     const uint64_t mask = (1ull << nb) - 1;
-    for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B) {
-        const uint64_t k = okeys[e];
-        atomicAdd(&outdeg[k >> nb], 1);
-        col[e] = static_cast<int32_t>(k & mask);
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        const uint64_t k = valid ? okeys[e] : 0ull;
+        add_run_lengths(valid, static_cast<int64_t>(k >> nb), outdeg);
+        if (valid) col[e] = static_cast<int32_t>(k & mask);
     }
 }
 
@@ -120,8 +129,12 @@ struct Stats {
     unsigned long long probe_work;
 };
 
-__global__ void k_vertex_stats(const int32_t *__restrict__ deg, const int32_t *__restrict__ outdeg,
-                               int32_t n, Stats *st) {
+// Workgroup reductions, one atomic per workgroup (launched with a small grid).
+__global__ __launch_bounds__(B) void k_vertex_stats(const int32_t *__restrict__ deg,
+                                                    const int32_t *__restrict__ outdeg, int32_t n,
+                                                    Stats *st) {
+    __shared__ int32_t s_mx[B / 64];
+    __shared__ unsigned long long s_iso[B / 64];
     int32_t mx = 0;
     unsigned long long iso = 0;
     for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B) {
@@ -129,24 +142,37 @@ __global__ void k_vertex_stats(const int32_t *__restrict__ deg, const int32_t *_
         iso += deg[v] == 0;
     }
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        mx = max(mx, __shfl_xor(mx, d));
-    }
+    for (int d = 1; d < kWave; d <<= 1) mx = max(mx, __shfl_xor(mx, d));
     iso = wave_sum(iso);
     if (lane_id() == 0) {
+        s_mx[threadIdx.x >> 6] = mx;
+        s_iso[threadIdx.x >> 6] = iso;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < B / 64; ++w) {
+            mx = max(mx, s_mx[w]);
+            iso += s_iso[w];
+        }
         atomicMax(&st->max_out, mx);
         atomicAdd(&st->isolated, iso);
     }
 }
 
 // probe work W = sum over oriented edges (x, y) of outdeg[y]
-__global__ void k_probe_work(const int32_t *__restrict__ col, int64_t m,
-                             const int32_t *__restrict__ outdeg, Stats *st) {
+__global__ __launch_bounds__(B) void k_probe_work(const int32_t *__restrict__ col, int64_t m,
+                                                  const int32_t *__restrict__ outdeg, Stats *st) {
+    __shared__ unsigned long long s_w[B / 64];
     unsigned long long w = 0;
     for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B)
         w += static_cast<unsigned long long>(outdeg[col[e]]);
     w = wave_sum(w);
-    if (lane_id() == 0) atomicAdd(&st->probe_work, w);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < B / 64; ++q) w += s_w[q];
+        atomicAdd(&st->probe_work, w);
+    }
 }
 
 unsigned cap_grid(int64_t work) {
@@ -250,8 +276,9 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
     // statistics for sizing kernels and stating algorithmic bytes
     DArray<Stats> st(1, s);
     PGABB_HIP(hipMemsetAsync(st.get(), 0, sizeof(Stats), s));
-    if (n > 0) k_vertex_stats<<<cap_grid(n), B, 0, s>>>(deg.get(), g->outdeg.get(), n, st.get());
-    if (g->m > 0) k_probe_work<<<cap_grid(g->m), B, 0, s>>>(g->col.get(), g->m, g->outdeg.get(), st.get());
+    if (n > 0) k_vertex_stats<<<std::min(cap_grid(n), 1024u), B, 0, s>>>(deg.get(), g->outdeg.get(), n, st.get());
+    if (g->m > 0)
+        k_probe_work<<<std::min(cap_grid(g->m), 2048u), B, 0, s>>>(g->col.get(), g->m, g->outdeg.get(), st.get());
     PGABB_HIP(hipGetLastError());
     Stats hs{};
     PGABB_HIP(hipMemcpyAsync(&hs, st.get(), sizeof(Stats), hipMemcpyDeviceToHost, s));

@@ -233,6 +233,9 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
         return set_err(PGABB_EINVAL, "negative option");
     if (o.waves_per_block && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
         return set_err(PGABB_EINVAL, "waves_per_block must be 2, 4 or 8");
+    if (o.unroll && o.unroll != 1 && o.unroll != 2 && o.unroll != 4 && o.unroll != 8)
+        return set_err(PGABB_EINVAL, "unroll must be 1, 2, 4 or 8");
+    if (o.reserved) return set_err(PGABB_EINVAL, "reserved option field must be 0");
     if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW))
         return set_err(PGABB_EINVAL, "unknown option flag bits");
     PGABB_TRY

@@ -22,7 +22,10 @@ namespace pgabb {
 
 namespace {
 
-template <int MODE, int LDS_WORDS, int WAVES>
+// Item g of the launch: task t = the task whose item range holds g; inside the
+// task, items are taken from the end of A_ij's item list (highest ranks,
+// the heaviest rows under the degree order) towards its start.
+template <int MODE, int LDS_WORDS, int WAVES, int UNROLL>
 __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
     __shared__ int32_t lds_all[WAVES][LDS_WORDS];
     const int w = threadIdx.x >> 6;
@@ -32,41 +35,54 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
         for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
         wave_lds_sync();
     }
-    for (;;) {
-        unsigned long long g0 = 0;
-        if (lane == 0) g0 = atomicAdd(a.next, static_cast<unsigned long long>(a.grab));
-        g0 = shfl_t(g0, 0);
-        if (static_cast<int64_t>(g0) >= a.total) break;
-        const int64_t g1 = min(static_cast<int64_t>(g0) + a.grab, a.total);
-        int32_t lo = 0, hi = a.ntasks - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (a.item_pre[mid] <= static_cast<int64_t>(g0)) lo = mid;
-            else hi = mid - 1;
-        }
-        int32_t t = __builtin_amdgcn_readfirstlane(lo);
-        int64_t t_end = a.item_pre[t + 1];
-        uint32_t cnt = 0;
-        for (int64_t g = static_cast<int64_t>(g0); g < g1; ++g) {
-            while (g >= t_end) {
-                const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
-                if (lane == 0 && s) atomicAdd(&a.counts[a.tasks[t].slot], s);
-                cnt = 0;
-                ++t;
-                t_end = a.item_pre[t + 1];
+    const int64_t units = (a.total + a.grab - 1) / a.grab;
+    const int home = static_cast<int>(blockIdx.x % kQueues);
+    for (int qi = 0; qi < kQueues; ++qi) {
+        const int q = (home + qi) % kQueues;
+        for (;;) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(&a.next[q * kQueueStride], 1ull);
+            c = shfl_t(c, 0);
+            const int64_t unit = static_cast<int64_t>(c) * kQueues + q;
+            if (unit >= units) break;
+            const int64_t g0 = unit * a.grab;
+            const int64_t g1 = min(g0 + a.grab, a.total);
+            int32_t lo = 0, hi = a.ntasks - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (a.item_pre[mid] <= g0) lo = mid;
+                else hi = mid - 1;
             }
-            const TaskDesc &T = a.tasks[t];
-            cnt += tc_row<MODE, LDS_WORDS>(T.ij, T.ik, T.jk, T.width_k,
-                                           static_cast<int32_t>(g - a.item_pre[t]), lds);
+            int32_t t = __builtin_amdgcn_readfirstlane(lo);
+            int64_t t_begin = a.item_pre[t], t_end = a.item_pre[t + 1];
+            uint32_t cnt = 0;
+            for (int64_t g = g0; g < g1; ++g) {
+                while (g >= t_end) {
+                    const unsigned long long sum = wave_sum(static_cast<unsigned long long>(cnt));
+                    if (lane == 0 && sum) atomicAdd(&a.counts[a.tasks[t].slot], sum);
+                    cnt = 0;
+                    ++t;
+                    t_begin = t_end;
+                    t_end = a.item_pre[t + 1];
+                }
+                const TaskDesc &T = a.tasks[t];
+                const int64_t it = T.ij.nitems - 1 - (g - t_begin);
+                const int32_t u = T.ij.items[2 * it];
+                const int32_t piece = T.ij.items[2 * it + 1];
+                const int32_t rb = T.ij.rptr[u], re = T.ij.rptr[u + 1];
+                const int32_t vb = rb + piece * kSplitV;
+                const int32_t ve = min(vb + kSplitV, re);
+                cnt += tc_row<MODE, LDS_WORDS, UNROLL>(T.ij, T.ik, T.jk, T.width_k, u, vb, ve, lds);
+            }
+            const unsigned long long sum = wave_sum(static_cast<unsigned long long>(cnt));
+            if (lane == 0 && sum) atomicAdd(&a.counts[a.tasks[t].slot], sum);
         }
-        const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
-        if (lane == 0 && s) atomicAdd(&a.counts[a.tasks[t].slot], s);
     }
 }
 
-template <int MODE, int LDS_WORDS, int WAVES>
+template <int MODE, int LDS_WORDS, int WAVES, int UNROLL>
 void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
-    auto kern = k_tc_tasks<MODE, LDS_WORDS, WAVES>;
+    auto kern = k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL>;
     int per_cu = 0;
     PGABB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, 0));
     if (per_cu < 1) per_cu = 1;
@@ -75,21 +91,38 @@ void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
     PGABB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int64_t grid = static_cast<int64_t>(cus) * per_cu;
     if (grid_override > 0) grid = grid_override;
-    const int64_t waves_needed = (a.total + a.grab - 1) / a.grab;
-    const int64_t blocks_needed = (waves_needed + WAVES - 1) / WAVES;
+    const int64_t units = (a.total + a.grab - 1) / a.grab;
+    const int64_t blocks_needed = (units + WAVES - 1) / WAVES;
     if (grid > blocks_needed) grid = blocks_needed;
     if (grid < 1) grid = 1;
     kern<<<static_cast<unsigned>(grid), WAVES * 64, 0, s>>>(a);
     PGABB_HIP(hipGetLastError());
 }
 
-template <int MODE, int WAVES>
+template <int MODE, int WAVES, int UNROLL>
 void launch_words(const CountArgs &a, int lds_words, hipStream_t s, int grid_override) {
-    if (lds_words <= 256) launch_one<MODE, 256, WAVES>(a, s, grid_override);
-    else if (lds_words <= 512) launch_one<MODE, 512, WAVES>(a, s, grid_override);
-    else if (lds_words <= 1024) launch_one<MODE, 1024, WAVES>(a, s, grid_override);
-    else if (lds_words <= 2048) launch_one<MODE, 2048, WAVES>(a, s, grid_override);
-    else launch_one<MODE, 4096, WAVES>(a, s, grid_override);
+    if (lds_words <= 256) launch_one<MODE, 256, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 512) launch_one<MODE, 512, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 1024) launch_one<MODE, 1024, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 2048) launch_one<MODE, 2048, WAVES, UNROLL>(a, s, grid_override);
+    else launch_one<MODE, 4096, WAVES, UNROLL>(a, s, grid_override);
+}
+
+template <int UNROLL>
+void launch_mode(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s, int grid_override) {
+    if (waves == 2) {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 2, UNROLL>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 2, UNROLL>(a, s, grid_override);
+        else launch_words<kModeHash, 2, UNROLL>(a, lds_words, s, grid_override);
+    } else if (waves == 8) {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 8, UNROLL>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 8, UNROLL>(a, s, grid_override);
+        else launch_words<kModeHash, 8, UNROLL>(a, lds_words, s, grid_override);
+    } else {
+        if (mode == kModeBitmap) launch_words<kModeBitmap, 4, UNROLL>(a, lds_words, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 4, UNROLL>(a, s, grid_override);
+        else launch_words<kModeHash, 4, UNROLL>(a, lds_words, s, grid_override);
+    }
 }
 
 }  // namespace
@@ -106,21 +139,22 @@ int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
 }
 
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
-                     int grid_override) {
+                     int grid_override, int unroll) {
     if (a.total <= 0) return;
-    if (waves == 2) {
-        if (mode == kModeBitmap) launch_words<kModeBitmap, 2>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 2>(a, s, grid_override);
-        else launch_words<kModeHash, 2>(a, lds_words, s, grid_override);
-    } else if (waves == 8) {
-        if (mode == kModeBitmap) launch_words<kModeBitmap, 8>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 8>(a, s, grid_override);
-        else launch_words<kModeHash, 8>(a, lds_words, s, grid_override);
-    } else {
-        if (mode == kModeBitmap) launch_words<kModeBitmap, 4>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 4>(a, s, grid_override);
-        else launch_words<kModeHash, 4>(a, lds_words, s, grid_override);
+    switch (unroll) {
+        case 1: launch_mode<1>(a, mode, lds_words, waves, s, grid_override); break;
+        case 2: launch_mode<2>(a, mode, lds_words, waves, s, grid_override); break;
+        case 8: launch_mode<8>(a, mode, lds_words, waves, s, grid_override); break;
+        default: launch_mode<4>(a, mode, lds_words, waves, s, grid_override); break;
     }
+}
+
+int default_grab(int64_t total_items) {
+    // at most ~32K counter updates per queue: device-scope atomics on one
+    // address serialise, and items are small enough that a few per grab
+    // keep the tail short
+    const int64_t g = (total_items + int64_t(kQueues) * 32768 - 1) / (int64_t(kQueues) * 32768);
+    return static_cast<int>(std::max<int64_t>(2, std::min<int64_t>(g, 64)));
 }
 
 int mode_of_option(int32_t kernel) {
@@ -138,9 +172,9 @@ TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &
         const int32_t *c = arena_base + (chunk_dev_off ? chunk_dev_off[b] : bi.chunk_off);
         BlockRef r;
         r.rptr = c;
-        r.rid = c + bi.width + 1;
-        r.col = r.rid + bi.nrows;
-        r.nrows = bi.nrows;
+        r.items = c + bi.width + 1;
+        r.col = r.items + 2 * static_cast<int64_t>(bi.nitems);
+        r.nitems = bi.nitems;
         r.width = bi.width;
         return r;
     };
@@ -161,15 +195,15 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     int32_t max_wk = 0;
     for (int32_t t = 0; t < T; ++t) {
         td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
-        pre[t + 1] = pre[t] + g->blocks[g->tasks[t].bij].nrows;
+        pre[t + 1] = pre[t] + g->blocks[g->tasks[t].bij].nitems;
         max_wk = std::max(max_wk, td[t].width_k);
     }
     DArray<TaskDesc> dtd(T, s);
     DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
-    DArray<unsigned long long> dcnt(static_cast<size_t>(T) + 1, s);  // last slot: work counter
+    DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kQueueWords, s);  // counts, then queues
     PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, s));
     PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
-    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + 1), s));
+    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kQueueWords), s));
 
     CountArgs a;
     a.tasks = dtd.get();
@@ -178,13 +212,13 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     a.total = pre[T];
     a.counts = dcnt.get();
     a.next = dcnt.get() + T;
-    a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : 8;
+    a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T]);
     const int mode = mode_of_option(opt.kernel);
     const int words = choose_lds_words(mode, g->max_out, max_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     StreamTimer tm;
     tm.start(s);
-    launch_tc_tasks(a, mode, words, waves, s, 0);
+    launch_tc_tasks(a, mode, words, waves, s, 0, opt.unroll);
     tm.stop(s);
 
     g->task_counts.assign(T, 0);

@@ -5,20 +5,29 @@
 
 namespace pgabb {
 
+// Work queues of a counting launch: grab units are dealt round-robin to
+// kQueues counters; a workgroup starts on queue blockIdx % kQueues (its XCD
+// under round-robin dispatch) and moves on to the others once it is empty.
+constexpr int kQueues = 8;
+// Counters sit 256 bytes apart so no two share a memory channel's line.
+constexpr int kQueueStride = 32;
+constexpr int kQueueWords = kQueues * kQueueStride;
+
 struct CountArgs {
     const TaskDesc *tasks;     // device
     const int64_t *item_pre;   // device, ntasks + 1 prefix of rows per task
     int32_t ntasks;
-    int32_t grab;              // rows taken per counter increment
+    int32_t grab;              // items taken per counter increment
     int64_t total;             // item_pre[ntasks]
     unsigned long long *counts;  // device, indexed by TaskDesc::slot
-    unsigned long long *next;    // device work counter (zero before launch)
+    unsigned long long *next;    // device, kQueueWords (zero before launch); queue q at q * kQueueStride
 };
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 int mode_of_option(int32_t kernel);
+int default_grab(int64_t total_items);
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
-                     int grid_override);
+                     int grid_override, int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
                    const int64_t *chunk_dev_off);
 uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt);

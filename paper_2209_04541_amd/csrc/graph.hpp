@@ -10,33 +10,38 @@
 namespace pgabb {
 
 // One block A_ij of the p x p grid, stored as a chunk of int32 words:
-//   [ rptr : width + 1 ]  dense row offsets over the stripe's row range,
-//                         relative to the block's first column entry
-//   [ rid  : nrows     ]  local ids of the rows that hold entries, increasing
-//   [ col  : nnz       ]  local column ids (rank - base of stripe j), each
-//                         row's run increasing
+//   [ rptr  : width + 1   ]  dense row offsets over the stripe's row range,
+//                            relative to the block's first column entry
+//   [ items : 2 * nitems  ]  work items (u, c): local row u, and c, the index
+//                            of a run of at most kSplitV entries of row u;
+//                            increasing in (u, c)
+//   [ col   : nnz         ]  local column ids (rank - base of stripe j), each
+//                            row's run increasing
 // Local row ids are rank - base_i, where base_i is stripe i's first rank that
 // can own an edge (isolated vertices rank lowest and own none).  One chunk is
-// the unit of host<->device movement.
+// the unit of host<->device movement.  Splitting long rows into items bounds
+// the work of one item when the block plays A_ij in a task.
+constexpr int32_t kSplitV = 32;
+
 struct BlockInfo {
     int32_t i = 0, j = 0;
-    int32_t width = 0;  // rows of the dense range of stripe i
-    int32_t nrows = 0;  // rows with at least one entry
+    int32_t width = 0;   // rows of the dense range of stripe i
+    int32_t nitems = 0;  // work items (rows split into runs of kSplitV)
     int64_t nnz = 0;
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
 };
 
-inline int64_t block_chunk_words(int32_t width, int32_t nrows, int64_t nnz) {
-    return static_cast<int64_t>(width) + 1 + nrows + nnz;
+inline int64_t block_chunk_words(int32_t width, int32_t nitems, int64_t nnz) {
+    return static_cast<int64_t>(width) + 1 + 2 * static_cast<int64_t>(nitems) + nnz;
 }
 
 // Device view of one block.
 struct BlockRef {
     const int32_t *rptr;
-    const int32_t *rid;
+    const int32_t *items;
     const int32_t *col;
-    int32_t nrows;
+    int32_t nitems;
     int32_t width;
 };
 

@@ -51,17 +51,18 @@ __global__ void k_nnz_cuts(const int64_t *__restrict__ row_off, int32_t n, int64
     if (s == p) { cuts[p] = n; return; }
     // smallest x in [0, n] with row_off[x] * p >= s * m
     int64_t lo = 0, hi = n;
-    const __int128 target = static_cast<__int128>(s) * m;
+    const int64_t target = static_cast<int64_t>(s) * m;  // < 2^38 for m' < 2^32
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (static_cast<__int128>(row_off[mid]) * p >= target) hi = mid;
+        if (row_off[mid] * p >= target) hi = mid;
         else lo = mid + 1;
     }
     cuts[s] = static_cast<int32_t>(lo);
 }
 
-// Per block (i, j): number of entries and number of rows holding entries.
-// Each workgroup accumulates in LDS and flushes its non-zero counters.
+// Per block (i, j): number of entries and number of work items (each row's
+// run split into pieces of at most kSplitV entries).  Each workgroup
+// accumulates in LDS and flushes its non-zero counters.
 __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ row_off,
                                                    const int32_t *__restrict__ col, int32_t n,
                                                    CutTable ct,
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
             while (y >= ct.c[j + 1]) {
                 if (run) {
                     atomicAdd(&s_nnz[si * ct.p + j], run);
-                    atomicAdd(&s_rows[si * ct.p + j], 1u);
+                    atomicAdd(&s_rows[si * ct.p + j], (run + kSplitV - 1) / kSplitV);
                 }
                 run = 0;
                 ++j;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
             ++run;
         }
         atomicAdd(&s_nnz[si * ct.p + j], run);
-        atomicAdd(&s_rows[si * ct.p + j], 1u);
+        atomicAdd(&s_rows[si * ct.p + j], (run + kSplitV - 1) / kSplitV);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < pp; q += B) {
@@ -143,7 +144,7 @@ __device__ __forceinline__ int32_t block_of_slot(int64_t q, const int64_t *sb, i
 }
 
 // Dense row offsets of every block from the scanned slot counts, and the
-// "row holds entries" flags for the row-list compaction.
+// number of work items of every row (for the item-list compaction).
 __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ scanned,
                                                  int64_t nslots,
                                                  const int64_t *__restrict__ slot_base_dense,
@@ -159,25 +160,30 @@ __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ sc
         const int64_t r = q - s_sb[b];
         const uint32_t v = scanned[q] - scanned[s_sb[b]];
         arena[chunk_off[b] + r] = static_cast<int32_t>(v);
-        flags[q] = (r < width[b] && scanned[q + 1] != scanned[q]) ? 1u : 0u;
+        flags[q] = r < width[b] ? (scanned[q + 1] - scanned[q] + kSplitV - 1) / kSplitV : 0u;
     }
 }
 
-__global__ __launch_bounds__(B) void k_fill_rid(const uint32_t *__restrict__ flags,
-                                                const uint32_t *__restrict__ pos, int64_t nslots,
-                                                const int64_t *__restrict__ slot_base_dense,
-                                                const int64_t *__restrict__ chunk_off,
-                                                const int32_t *__restrict__ width, int32_t nblk,
-                                                int32_t *__restrict__ arena) {
+__global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ flags,
+                                                  const uint32_t *__restrict__ pos, int64_t nslots,
+                                                  const int64_t *__restrict__ slot_base_dense,
+                                                  const int64_t *__restrict__ chunk_off,
+                                                  const int32_t *__restrict__ width, int32_t nblk,
+                                                  int32_t *__restrict__ arena) {
     extern __shared__ int64_t s_sb[];
     for (int q = threadIdx.x; q < nblk; q += B) s_sb[q] = slot_base_dense[q];
     __syncthreads();
     for (int64_t q = blockIdx.x * int64_t(B) + threadIdx.x; q < nslots; q += int64_t(gridDim.x) * B) {
-        if (!flags[q]) continue;
+        const uint32_t f = flags[q];
+        if (!f) continue;
         const int32_t b = block_of_slot(q, s_sb, nblk);
         const int64_t r = q - s_sb[b];
         const uint32_t at = pos[q] - pos[s_sb[b]];
-        arena[chunk_off[b] + width[b] + 1 + at] = static_cast<int32_t>(r);
+        int32_t *it = arena + chunk_off[b] + width[b] + 1 + 2 * static_cast<int64_t>(at);
+        for (uint32_t c = 0; c < f; ++c) {
+            it[2 * c] = static_cast<int32_t>(r);
+            it[2 * c + 1] = static_cast<int32_t>(c);
+        }
     }
 }
 
@@ -187,7 +193,7 @@ __global__ void k_fill_cols(const int64_t *__restrict__ row_off, const int32_t *
                             int32_t n, CutTable ct, const int32_t *__restrict__ blk_index,
                             const int64_t *__restrict__ chunk_off,
                             const int32_t *__restrict__ width,
-                            const int32_t *__restrict__ nrows, int32_t *__restrict__ arena) {
+                            const int32_t *__restrict__ nitems, int32_t *__restrict__ arena) {
     for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
         const int64_t e0 = row_off[x], e1 = row_off[x + 1];
         if (e0 == e1) continue;
@@ -202,7 +208,7 @@ __global__ void k_fill_cols(const int64_t *__restrict__ row_off, const int32_t *
                 j = stripe_of(y, ct);
                 const int32_t b = blk_index[si * ct.p + j];
                 const int64_t c0 = chunk_off[b];
-                dst = arena + c0 + width[b] + 1 + nrows[b] + arena[c0 + lx];
+                dst = arena + c0 + width[b] + 1 + 2 * static_cast<int64_t>(nitems[b]) + arena[c0 + lx];
                 cbase = ct.base[j];
             }
             *dst++ = y - cbase;
@@ -291,10 +297,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 bi.i = i;
                 bi.j = j;
                 bi.width = cuts[i + 1] - base[i];
-                bi.nrows = static_cast<int32_t>(hrows[q]);
+                bi.nitems = static_cast<int32_t>(hrows[q]);
                 bi.nnz = static_cast<int64_t>(hnnz[q]);
                 bi.chunk_off = words;
-                bi.chunk_len = block_chunk_words(bi.width, bi.nrows, bi.nnz);
+                bi.chunk_len = block_chunk_words(bi.width, bi.nitems, bi.nnz);
                 words += bi.chunk_len;
                 g->block_of[q] = static_cast<int32_t>(g->blocks.size());
                 g->blocks.push_back(bi);
@@ -302,7 +308,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 slot_base_dense.push_back(nslots);
                 chunk_off_dense.push_back(bi.chunk_off);
                 width_dense.push_back(bi.width);
-                nrows_dense.push_back(bi.nrows);
+                nrows_dense.push_back(bi.nitems);
                 nslots += static_cast<int64_t>(bi.width) + 1;
             }
         }
@@ -329,11 +335,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb.get(), d_co.get(), d_w.get(), nblk,
                                                      g->arena.get(), flags.get());
         PGABB_HIP(hipGetLastError());
-        // ---- row lists: compaction of the rows that hold entries
+        // ---- item lists: each row's items at the scanned item offsets
         PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
         scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // reuse slots as positions
-        // k_fill_rid needs the flags before the scan overwrote nothing: flags kept intact
-        k_fill_rid<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_co.get(), d_w.get(),
+        k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_co.get(), d_w.get(),
                                                     nblk, g->arena.get());
         PGABB_HIP(hipGetLastError());
         // ---- column entries

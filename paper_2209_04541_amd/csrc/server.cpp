@@ -186,7 +186,7 @@ static void counter_loop(pgabb_server *s) {
             pgabb_graph *g = r->g;
             for (const Task &t : g->tasks) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
-                pre.push_back(pre.back() + g->blocks[t.bij].nrows);
+                pre.push_back(pre.back() + g->blocks[t.bij].nitems);
                 max_wk = std::max(max_wk, td.back().width_k);
             }
             max_out = std::max(max_out, g->max_out);
@@ -200,8 +200,8 @@ static void counter_loop(pgabb_server *s) {
             hipStream_t cs = s->count_stream;
             const int32_t T = static_cast<int32_t>(td.size());
             const size_t L = live.size();
-            if (dcnt.size() < L + 1) {
-                dcnt.reset(std::max<size_t>(2 * (L + 1), 64), cs);
+            if (dcnt.size() < L + kQueueWords) {
+                dcnt.reset(std::max<size_t>(2 * L + kQueueWords, 64), cs);
                 hcnt.reset(dcnt.size());
             }
             if (T > 0) {
@@ -210,19 +210,19 @@ static void counter_loop(pgabb_server *s) {
                 PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, cs));
                 PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, cs));
             }
-            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + 1), cs));
+            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + kQueueWords), cs));
             if (T > 0) {
                 CountArgs a;
                 a.tasks = dtd.get();
                 a.item_pre = dpre.get();
                 a.ntasks = T;
-                a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : 8;
+                a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back());
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;
                 const int mode = mode_of_option(s->opt.kernel);
                 launch_tc_tasks(a, mode, choose_lds_words(mode, max_out, max_wk),
-                                s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0);
+                                s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0, s->opt.unroll);
             }
             PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, cs));
             PGABB_HIP(hipStreamSynchronize(cs));

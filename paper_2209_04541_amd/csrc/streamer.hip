@@ -118,8 +118,10 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     DArray<uint8_t> pool(static_cast<size_t>(cap), s);
     DArray<TaskDesc> ddesc(static_cast<size_t>(T), s);
     DArray<int64_t> dpre(static_cast<size_t>(2 * T + 1), s);
-    DArray<unsigned long long> dcnt(static_cast<size_t>(2 * T), s);  // counts then window counters
-    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * 2 * T, s));
+    // counts, then kQueues work counters per window (at most T windows)
+    const size_t ncnt = static_cast<size_t>(T) * (1 + kQueueWords);
+    DArray<unsigned long long> dcnt(ncnt, s);
+    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * ncnt, s));
     PinnedArray<TaskDesc> hdesc;
     hdesc.reset(static_cast<size_t>(T));
     PinnedArray<int64_t> hpre;
@@ -133,13 +135,14 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     std::vector<std::list<int32_t>::iterator> lru_pos(nblk);
     std::vector<hipEvent_t> done;                     // per window
     std::vector<hipEvent_t> copied;
+    std::vector<hipEvent_t> kstart, kstop;            // per window launch timing
 
     int32_t max_wk = 0;
     for (int32_t t = 0; t < T; ++t) max_wk = std::max(max_wk, g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k]);
     const int mode = mode_of_option(opt.kernel);
     const int words = choose_lds_words(mode, g->max_out, max_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
-    const int grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : 8;
+    const int grab_opt = opt.rows_per_grab;
     const int window_tasks = 64;
     const uint64_t window_new_bytes = std::max<uint64_t>(cap / 4, 64ull << 20);
 
@@ -256,11 +259,16 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 const int32_t ti = wtasks[q];
                 hdesc[ti] = make_desc(g, reinterpret_cast<const int32_t *>(pool.get()), g->tasks[ti], ti,
                                       chunk_dev.data());
-                items += g->blocks[g->tasks[ti].bij].nrows;
+                items += g->blocks[g->tasks[ti].bij].nitems;
                 hpre[pre_at + q + 1] = items;
             }
             hipStream_t st = cs[win % nstreams];
             PGABB_HIP(hipStreamWaitEvent(st, ce, 0));
+            hipEvent_t k0 = nullptr, k1 = nullptr;
+            PGABB_HIP(hipEventCreate(&k0));
+            PGABB_HIP(hipEventCreate(&k1));
+            kstart.push_back(k0);
+            kstop.push_back(k1);
             PGABB_HIP(hipMemcpyAsync(ddesc.get() + w0, hdesc.get() + w0, sizeof(TaskDesc) * W,
                                      hipMemcpyHostToDevice, st));
             PGABB_HIP(hipMemcpyAsync(dpre.get() + pre_at, hpre.get() + pre_at, sizeof(int64_t) * (W + 1),
@@ -269,11 +277,13 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             a.tasks = ddesc.get() + w0;
             a.item_pre = dpre.get() + pre_at;
             a.ntasks = W;
-            a.grab = grab;
+            a.grab = grab_opt > 0 ? grab_opt : default_grab(items);
             a.total = items;
             a.counts = dcnt.get();
-            a.next = dcnt.get() + T + win;
-            launch_tc_tasks(a, mode, words, waves, st, 0);
+            a.next = dcnt.get() + T + static_cast<size_t>(win) * kQueueWords;
+            PGABB_HIP(hipEventRecord(k0, st));
+            launch_tc_tasks(a, mode, words, waves, st, 0, opt.unroll);
+            PGABB_HIP(hipEventRecord(k1, st));
             PGABB_HIP(hipEventRecord(de, st));
             for (int32_t ti : wtasks)
                 for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) last_window[b] = win;
@@ -282,6 +292,13 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         }
         for (auto x : cs) PGABB_HIP(hipStreamSynchronize(x));
         PGABB_HIP(hipStreamSynchronize(copy_s));
+        double kms = 0;
+        for (size_t q = 0; q < kstart.size(); ++q) {
+            float t = 0;
+            PGABB_HIP(hipEventElapsedTime(&t, kstart[q], kstop[q]));
+            kms += t;
+        }
+        g->t_kernel_ms = kms;
         g->task_counts.assign(T, 0);
         PGABB_HIP(hipMemcpyAsync(g->task_counts.data(), dcnt.get(), sizeof(uint64_t) * T, hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
@@ -290,12 +307,16 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         (void)hipStreamSynchronize(copy_s);
         for (auto e : copied) (void)hipEventDestroy(e);
         for (auto e : done) (void)hipEventDestroy(e);
+        for (auto e : kstart) (void)hipEventDestroy(e);
+        for (auto e : kstop) (void)hipEventDestroy(e);
         for (auto x : cs) (void)hipStreamDestroy(x);
         (void)hipStreamDestroy(copy_s);
         throw;
     }
     for (auto e : copied) (void)hipEventDestroy(e);
     for (auto e : done) (void)hipEventDestroy(e);
+    for (auto e : kstart) (void)hipEventDestroy(e);
+    for (auto e : kstop) (void)hipEventDestroy(e);
     for (auto x : cs) (void)hipStreamDestroy(x);
     (void)hipStreamDestroy(copy_s);
     g->h2d_bytes = h2d;

@@ -3,7 +3,8 @@
 // PGAbB Section 3.6: for a block-list (A_ij, A_ik, A_jk) and each edge (u, v)
 // of A_ij, the triangles closed inside the list are the common entries of
 // row u of A_ik and row v of A_jk; the intersection may be list based or
-// hash based.  Here one wavefront takes one row u of A_ij:
+// hash based.  Here one wavefront takes one work item of A_ij, a run of at
+// most kSplitV entries v of a row u:
 //   1. stage row u of A_ik (the list every probe of this row is checked
 //      against) in the wave's LDS -- an open-addressing hash table, or a
 //      bitmap over stripe k's columns -- or leave it in place for binary
@@ -38,20 +39,20 @@ __device__ __forceinline__ uint32_t sorted_contains(const int32_t *__restrict__ 
     return (lo < end && a[lo] == w) ? 1u : 0u;
 }
 
-// Triangles of row r of ij inside the block-list, per lane (sum over lanes is
-// the row's count).  `lds` holds LDS_WORDS int32 words private to the wave.
-// Column ids of ik and jk lie in [wbase, wbase + width_k).  Every lane of the
-// wave must call this with the same arguments.
-template <int MODE, int LDS_WORDS>
+// Triangles closed by the entries [vb, ve) of row u of ij inside the
+// block-list, per lane (the sum over lanes is the item's count).  `lds` holds
+// LDS_WORDS int32 words private to the wave.  Column ids of ik and jk lie in
+// [wbase, wbase + width_k).  Every lane of the wave must call this with the
+// same arguments.
+template <int MODE, int LDS_WORDS, int UNROLL = 4>
 __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &ik,
-                                           const BlockRef &jk, int32_t width_k, int32_t r,
-                                           int32_t *__restrict__ lds, int32_t wbase = 0) {
+                                           const BlockRef &jk, int32_t width_k, int32_t u,
+                                           int32_t vb, int32_t ve, int32_t *__restrict__ lds,
+                                           int32_t wbase = 0) {
     const int lane = lane_id();
-    const int32_t u = ij.rid[r];
     const int32_t sb = ik.rptr[u], se = ik.rptr[u + 1];
     const int32_t slen = se - sb;
-    if (slen == 0) return 0u;
-    const int32_t vb = ij.rptr[u], ve = ij.rptr[u + 1];
+    if (slen == 0 || vb >= ve) return 0u;
 
     // ---- stage row u of A_ik
     int mode = MODE;
@@ -90,7 +91,9 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
         wave_lds_sync();
     }
 
-    // ---- flattened walk over the rows A_jk[v], v in A_ij[u]
+    // ---- flattened walk over the rows A_jk[v], v in A_ij[u].  UNROLL
+    // chunks of 64 elements are located and loaded before any is probed, so
+    // each wave keeps UNROLL independent row loads in flight.
     uint32_t cnt = 0;
     for (int32_t b0 = vb; b0 < ve; b0 += kWave) {
         const int32_t idx = b0 + lane;
@@ -103,24 +106,34 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t pre = incl - len;
         const int32_t total = __shfl(incl, kWave - 1);
-        for (int32_t base = 0; base < total; base += kWave) {
-            const int32_t e = base + lane;
-            // the lane holding e's row: largest l with pre_l <= e
-            int lo = 0;
+        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
+            int32_t w[UNROLL];
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const int cand = lo + step;
-                if (__shfl(pre, cand) <= e) lo = cand;
+            for (int q = 0; q < UNROLL; ++q) {
+                w[q] = -1;
+                if (base + q * kWave < total) {  // uniform across the wave
+                    const int32_t e = base + q * kWave + lane;
+                    // the lane holding e's row: largest l with pre_l <= e
+                    int lo = 0;
+#pragma unroll
+                    for (int step = 32; step >= 1; step >>= 1) {
+                        const int cand = lo + step;
+                        if (__shfl(pre, cand) <= e) lo = cand;
+                    }
+                    const int32_t spre = __shfl(pre, lo);
+                    const int32_t spb = __shfl(pb, lo);
+                    if (e < total) w[q] = jk.col[spb + (e - spre)];
+                }
             }
-            const int32_t spre = __shfl(pre, lo);
-            const int32_t spb = __shfl(pb, lo);
-            if (e < total) {
-                const int32_t w = jk.col[spb + (e - spre)];
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                const int32_t wq = w[q];
+                if (wq < 0) continue;
                 if (mode == kModeHash) {
-                    uint32_t h = hash_slot(w, shift);
+                    uint32_t h = hash_slot(wq, shift);
                     for (;;) {
                         const int32_t sv = lds[h];
-                        if (sv == w) {
+                        if (sv == wq) {
                             ++cnt;
                             break;
                         }
@@ -128,10 +141,10 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
                         h = (h + 1) & tmask;
                     }
                 } else if (mode == kModeBitmap) {
-                    const int32_t wl = w - wbase;
+                    const int32_t wl = wq - wbase;
                     cnt += (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
                 } else {
-                    cnt += sorted_contains(ik.col, sb, se, w);
+                    cnt += sorted_contains(ik.col, sb, se, wq);
                 }
             }
         }

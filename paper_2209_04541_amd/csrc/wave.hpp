@@ -69,6 +69,25 @@ __device__ __forceinline__ T wave_sum(T x) {
     return x;
 }
 
+// For the 64 consecutive elements handled by one wave, where equal keys form
+// runs (the input is sorted), add each run's length to counter[key] with one
+// atomic from the run's first lane.  `valid` lanes must form a prefix.
+__device__ __forceinline__ void add_run_lengths(bool valid, int64_t key, int32_t *counter) {
+    const int lane = lane_id();
+    const uint64_t vmask = __ballot(valid);
+    const int nvalid = __popcll(vmask);
+    const uint32_t klo = __shfl_up(static_cast<uint32_t>(key), 1);
+    const uint32_t khi = __shfl_up(static_cast<uint32_t>(static_cast<uint64_t>(key) >> 32), 1);
+    const int64_t prev = static_cast<int64_t>((static_cast<uint64_t>(khi) << 32) | klo);
+    const bool start = valid && (lane == 0 || prev != key);
+    const uint64_t starts = __ballot(start);
+    if (start) {
+        const uint64_t after = lane == 63 ? 0ull : (starts & (~0ull << (lane + 1)));
+        const int next = after ? __ffsll(static_cast<long long>(after)) - 1 : nvalid;
+        atomicAdd(&counter[key], next - lane);
+    }
+}
+
 // Order LDS accesses of the lanes of one wave: what a lane wrote before the
 // call is visible to every lane of the wave after it.
 __device__ __forceinline__ void wave_lds_sync() {
