@@ -78,6 +78,10 @@ typedef enum pgabb_status {
                                     against) */
 #define PGABB_SERVER_BORROW 0x4u /* server only: submitted arrays are borrowed
                                     until the request finishes, not copied */
+#define PGABB_OPT_ROWS      0x8u /* walk each edge block by rows (stage the row
+                                    of A_ik, probe the rows of A_jk) instead of
+                                    the default by columns (stage the row of
+                                    A_jk, probe the rows of A_ik) */
 
 typedef struct pgabb_tc_options {
     int32_t kernel;            /* PGABB_KERNEL_* */

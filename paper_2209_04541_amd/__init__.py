@@ -27,6 +27,7 @@ ORDER_BY_ID = 0x2
 CUT_NNZ, CUT_UNIFORM = 0, 1
 KERNEL_AUTO, KERNEL_HASH, KERNEL_BITMAP, KERNEL_SEARCH = 0, 1, 2, 3
 OPT_STREAM = 0x1
+OPT_ROWS = 0x8
 
 
 class PgabbError(RuntimeError):
@@ -159,12 +160,12 @@ def _edges(src, dst):
 
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
-            waves_per_block=0, rows_per_grab=0, unroll=0):
+            waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=False):
     o = TcOptions()
     o.kernel = kernel
     o.num_streams = num_streams
     o.device_cap_bytes = device_cap_bytes
-    o.flags = OPT_STREAM if stream_blocks else 0
+    o.flags = (OPT_STREAM if stream_blocks else 0) | (OPT_ROWS if by_rows else 0)
     o.waves_per_block = waves_per_block
     o.rows_per_grab = rows_per_grab
     o.unroll = unroll

@@ -229,12 +229,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
         for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
         wave_lds_sync();
     }
-    BlockRef ref;
-    ref.rptr = a.rptr;
-    ref.items = nullptr;
-    ref.col = a.col;
-    ref.nitems = 0;
-    ref.width = 0;
     for (;;) {
         unsigned long long g0 = 0;
         if (lane == 0) g0 = atomicAdd(a.next, static_cast<unsigned long long>(a.grab));
@@ -255,8 +249,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
             const int64_t vb = a.vbase[gid];
             const int32_t nv = static_cast<int32_t>(a.vbase[gid + 1] - vb);
             const int32_t u = a.rows[it];
-            cnt += tc_row<MODE, LDS_WORDS>(ref, ref, ref, nv, u, a.rptr[u], a.rptr[u + 1], lds,
-                                           static_cast<int32_t>(vb));
+            cnt += tc_item<MODE, LDS_WORDS>(a.rptr, a.col, u, a.rptr, a.col, a.col, a.rptr[u],
+                                            a.rptr[u + 1], nv, lds, static_cast<int32_t>(vb));
         }
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
         if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);
@@ -286,12 +280,10 @@ void launch_batch_one(const BatchArgs &a, hipStream_t s) {
 
 template <int MODE, int WAVES>
 void launch_batch_words(const BatchArgs &a, int words, hipStream_t s) {
-    if (words <= 64) launch_batch_one<MODE, 64, WAVES>(a, s);
-    else if (words <= 128) launch_batch_one<MODE, 128, WAVES>(a, s);
-    else if (words <= 256) launch_batch_one<MODE, 256, WAVES>(a, s);
-    else if (words <= 512) launch_batch_one<MODE, 512, WAVES>(a, s);
-    else if (words <= 1024) launch_batch_one<MODE, 1024, WAVES>(a, s);
-    else launch_batch_one<MODE, 2048, WAVES>(a, s);
+    if (words <= 320) launch_batch_one<MODE, 320, WAVES>(a, s);
+    else if (words <= 640) launch_batch_one<MODE, 640, WAVES>(a, s);
+    else if (words <= 1280) launch_batch_one<MODE, 1280, WAVES>(a, s);
+    else launch_batch_one<MODE, 2304, WAVES>(a, s);
 }
 
 void launch_batch(const BatchArgs &a, int mode, int words, int waves, hipStream_t s) {
@@ -308,11 +300,18 @@ void launch_batch(const BatchArgs &a, int mode, int words, int waves, hipStream_
 }
 
 int words_for(int mode, const pgabb_batch *b) {
-    int64_t need = mode == kModeBitmap ? (static_cast<int64_t>(b->max_n) + 31) / 32
-                                       : 2 * static_cast<int64_t>(b->max_out);
-    int w = 64;
-    while (w < need && w < 2048) w <<= 1;
-    return w;
+    static const int kClass[] = {320, 640, 1280, 2304};
+    static const int kTable[] = {256, 512, 1024, 2048};
+    if (mode == kModeBitmap) {
+        const int64_t w = (static_cast<int64_t>(b->max_n) + 31) / 32;
+        for (int c = 0; c < 4; ++c)
+            if (w <= kClass[c]) return kClass[c];
+        return kClass[3];
+    }
+    const int64_t need = (3 * static_cast<int64_t>(b->max_out) + 1) / 2;
+    for (int c = 0; c < 4; ++c)
+        if (need <= kTable[c]) return kClass[c];
+    return kClass[3];
 }
 
 BatchArgs batch_args(pgabb_batch *b, int grab) {
@@ -373,7 +372,7 @@ TuneVal autotune(pgabb_batch *b) {
     const int wavess[] = {2, 4, 8};
     const int grabs[] = {1, 4, 16};
     for (int mode : modes) {
-        if (mode == kModeBitmap && (static_cast<int64_t>(b->max_n) + 31) / 32 > 2048) continue;
+        if (mode == kModeBitmap && (static_cast<int64_t>(b->max_n) + 31) / 32 > 2304) continue;
         for (int waves : wavess)
             for (int grab : grabs) {
                 enqueue_count(b, mode, waves, grab, s);  // warm
@@ -582,7 +581,7 @@ void batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uint64_t *out) {
         int mode, waves, grab;
         if (opts) {
             mode = (opts->kernel == PGABB_KERNEL_HASH || opts->kernel == PGABB_KERNEL_SEARCH) ? kModeHash : kModeBitmap;
-            if (mode == kModeBitmap && (static_cast<int64_t>(b->max_n) + 31) / 32 > 2048) mode = kModeHash;
+            if (mode == kModeBitmap && (static_cast<int64_t>(b->max_n) + 31) / 32 > 2304) mode = kModeHash;
             waves = opts->waves_per_block > 0 ? opts->waves_per_block : 4;
             grab = opts->rows_per_grab > 0 ? opts->rows_per_grab : 4;
         } else {

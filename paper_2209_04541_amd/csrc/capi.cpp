@@ -236,7 +236,7 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
     if (o.unroll && o.unroll != 1 && o.unroll != 2 && o.unroll != 4 && o.unroll != 8)
         return set_err(PGABB_EINVAL, "unroll must be 1, 2, 4 or 8");
     if (o.reserved) return set_err(PGABB_EINVAL, "reserved option field must be 0");
-    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW))
+    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW | PGABB_OPT_ROWS))
         return set_err(PGABB_EINVAL, "unknown option flag bits");
     PGABB_TRY
     *count = count_graph(g, o);

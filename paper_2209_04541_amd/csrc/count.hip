@@ -24,8 +24,9 @@ namespace {
 
 // Item g of the launch: task t = the task whose item range holds g; inside the
 // task, items are taken from the end of A_ij's item list (highest ranks,
-// the heaviest rows under the degree order) towards its start.
-template <int MODE, int LDS_WORDS, int WAVES, int UNROLL>
+// the heaviest rows under the degree order) towards its start.  ORIENT picks
+// the row items (stage A_ik[u]) or the column items (stage A_jk[v]).
+template <int MODE, int LDS_WORDS, int WAVES, int UNROLL, int ORIENT>
 __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
     __shared__ int32_t lds_all[WAVES][LDS_WORDS];
     const int w = threadIdx.x >> 6;
@@ -66,13 +67,23 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                     t_end = a.item_pre[t + 1];
                 }
                 const TaskDesc &T = a.tasks[t];
-                const int64_t it = T.ij.nitems - 1 - (g - t_begin);
-                const int32_t u = T.ij.items[2 * it];
-                const int32_t piece = T.ij.items[2 * it + 1];
-                const int32_t rb = T.ij.rptr[u], re = T.ij.rptr[u + 1];
-                const int32_t vb = rb + piece * kSplitV;
-                const int32_t ve = min(vb + kSplitV, re);
-                cnt += tc_row<MODE, LDS_WORDS, UNROLL>(T.ij, T.ik, T.jk, T.width_k, u, vb, ve, lds);
+                if (ORIENT == kOrientRow) {
+                    const int64_t it = T.ij.nitems - 1 - (g - t_begin);
+                    const int32_t u = T.ij.items[2 * it];
+                    const int32_t piece = T.ij.items[2 * it + 1];
+                    const int32_t rb = T.ij.rptr[u] + piece * kSplitV;
+                    const int32_t re = min(rb + kSplitV, T.ij.rptr[u + 1]);
+                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.ik.rptr, T.ik.col, u, T.jk.rptr, T.jk.col,
+                                                            T.ij.col, rb, re, T.width_k, lds);
+                } else {
+                    const int64_t it = T.ij.ncitems - 1 - (g - t_begin);
+                    const int32_t v = T.ij.citems[2 * it];
+                    const int32_t piece = T.ij.citems[2 * it + 1];
+                    const int32_t cb = T.ij.cptr[v] + piece * kSplitV;
+                    const int32_t ce = min(cb + kSplitV, T.ij.cptr[v + 1]);
+                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.jk.rptr, T.jk.col, v, T.ik.rptr, T.ik.col,
+                                                            T.ij.crow, cb, ce, T.width_k, lds);
+                }
             }
             const unsigned long long sum = wave_sum(static_cast<unsigned long long>(cnt));
             if (lane == 0 && sum) atomicAdd(&a.counts[a.tasks[t].slot], sum);
@@ -82,7 +93,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
 
 template <int MODE, int LDS_WORDS, int WAVES, int UNROLL>
 void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
-    auto kern = k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL>;
+    auto kern = a.orient == kOrientCol ? k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientCol>
+                                       : k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientRow>;
     int per_cu = 0;
     PGABB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, 0));
     if (per_cu < 1) per_cu = 1;
@@ -99,28 +111,30 @@ void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
     PGABB_HIP(hipGetLastError());
 }
 
+// LDS words per wave come in five classes; a hash-mode class holds a table of
+// 256 .. 4096 words plus a filter (see HashLds).
 template <int MODE, int WAVES, int UNROLL>
 void launch_words(const CountArgs &a, int lds_words, hipStream_t s, int grid_override) {
-    if (lds_words <= 256) launch_one<MODE, 256, WAVES, UNROLL>(a, s, grid_override);
-    else if (lds_words <= 512) launch_one<MODE, 512, WAVES, UNROLL>(a, s, grid_override);
-    else if (lds_words <= 1024) launch_one<MODE, 1024, WAVES, UNROLL>(a, s, grid_override);
-    else if (lds_words <= 2048) launch_one<MODE, 2048, WAVES, UNROLL>(a, s, grid_override);
-    else launch_one<MODE, 4096, WAVES, UNROLL>(a, s, grid_override);
+    if (lds_words <= 320) launch_one<MODE, 320, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 640) launch_one<MODE, 640, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 1280) launch_one<MODE, 1280, WAVES, UNROLL>(a, s, grid_override);
+    else if (lds_words <= 2304) launch_one<MODE, 2304, WAVES, UNROLL>(a, s, grid_override);
+    else launch_one<MODE, 4352, WAVES, UNROLL>(a, s, grid_override);
 }
 
 template <int UNROLL>
 void launch_mode(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s, int grid_override) {
     if (waves == 2) {
         if (mode == kModeBitmap) launch_words<kModeBitmap, 2, UNROLL>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 2, UNROLL>(a, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 320, 2, UNROLL>(a, s, grid_override);
         else launch_words<kModeHash, 2, UNROLL>(a, lds_words, s, grid_override);
     } else if (waves == 8) {
         if (mode == kModeBitmap) launch_words<kModeBitmap, 8, UNROLL>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 8, UNROLL>(a, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 320, 8, UNROLL>(a, s, grid_override);
         else launch_words<kModeHash, 8, UNROLL>(a, lds_words, s, grid_override);
     } else {
         if (mode == kModeBitmap) launch_words<kModeBitmap, 4, UNROLL>(a, lds_words, s, grid_override);
-        else if (mode == kModeSearch) launch_one<kModeSearch, 64, 4, UNROLL>(a, s, grid_override);
+        else if (mode == kModeSearch) launch_one<kModeSearch, 320, 4, UNROLL>(a, s, grid_override);
         else launch_words<kModeHash, 4, UNROLL>(a, lds_words, s, grid_override);
     }
 }
@@ -128,14 +142,22 @@ void launch_mode(const CountArgs &a, int mode, int lds_words, int waves, hipStre
 }  // namespace
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
-    int need = 256;
+    static const int kClass[] = {320, 640, 1280, 2304, 4352};
+    static const int kTable[] = {256, 512, 1024, 2048, 4096};
     if (mode == kModeBitmap) {
         const int64_t w = (static_cast<int64_t>(max_width_k) + 31) / 32;
-        while (need < w && need < 4096) need <<= 1;
-    } else if (mode == kModeHash) {
-        while (need < 2 * static_cast<int64_t>(max_stage_len) && need < 4096) need <<= 1;
+        for (int c = 0; c < 5; ++c)
+            if (w <= kClass[c]) return kClass[c];
+        return kClass[4];
     }
-    return need;
+    if (mode == kModeHash) {
+        // table of at least 1.5 x the longest staged row (load <= 2/3)
+        const int64_t need = (3 * static_cast<int64_t>(max_stage_len) + 1) / 2;
+        for (int c = 0; c < 5; ++c)
+            if (need <= kTable[c]) return kClass[c];
+        return kClass[4];  // longer rows fall back to in-place search
+    }
+    return 320;
 }
 
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
@@ -172,10 +194,13 @@ TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &
         const int32_t *c = arena_base + (chunk_dev_off ? chunk_dev_off[b] : bi.chunk_off);
         BlockRef r;
         r.rptr = c;
-        r.items = c + bi.width + 1;
-        r.col = r.items + 2 * static_cast<int64_t>(bi.nitems);
+        r.items = c + (bi.off_items() - bi.chunk_off);
+        r.col = c + (bi.off_col() - bi.chunk_off);
+        r.cptr = c + (bi.off_cptr() - bi.chunk_off);
+        r.citems = c + (bi.off_citems() - bi.chunk_off);
+        r.crow = c + (bi.off_crow() - bi.chunk_off);
         r.nitems = bi.nitems;
-        r.width = bi.width;
+        r.ncitems = bi.ncitems;
         return r;
     };
     TaskDesc d;
@@ -187,15 +212,25 @@ TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &
     return d;
 }
 
+int orient_of_option(const pgabb_tc_options &opt) {
+    return (opt.flags & PGABB_OPT_ROWS) ? kOrientRow : kOrientCol;
+}
+
+int64_t task_items(const pgabb_graph *g, const Task &t, int orient) {
+    const BlockInfo &b = g->blocks[t.bij];
+    return orient == kOrientCol ? b.ncitems : b.nitems;
+}
+
 static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     hipStream_t s = g->stream;
+    const int orient = orient_of_option(opt);
     const int32_t T = static_cast<int32_t>(g->tasks.size());
     std::vector<TaskDesc> td(T);
     std::vector<int64_t> pre(static_cast<size_t>(T) + 1, 0);
     int32_t max_wk = 0;
     for (int32_t t = 0; t < T; ++t) {
         td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
-        pre[t + 1] = pre[t] + g->blocks[g->tasks[t].bij].nitems;
+        pre[t + 1] = pre[t] + task_items(g, g->tasks[t], orient);
         max_wk = std::max(max_wk, td[t].width_k);
     }
     DArray<TaskDesc> dtd(T, s);
@@ -213,6 +248,7 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     a.counts = dcnt.get();
     a.next = dcnt.get() + T;
     a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T]);
+    a.orient = orient;
     const int mode = mode_of_option(opt.kernel);
     const int words = choose_lds_words(mode, g->max_out, max_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;

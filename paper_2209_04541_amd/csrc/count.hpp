@@ -21,11 +21,14 @@ struct CountArgs {
     int64_t total;             // item_pre[ntasks]
     unsigned long long *counts;  // device, indexed by TaskDesc::slot
     unsigned long long *next;    // device, kQueueWords (zero before launch); queue q at q * kQueueStride
+    int32_t orient;              // kOrientRow or kOrientCol (which item lists)
 };
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 int mode_of_option(int32_t kernel);
 int default_grab(int64_t total_items);
+int orient_of_option(const pgabb_tc_options &opt);
+int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
                      int grid_override, int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,

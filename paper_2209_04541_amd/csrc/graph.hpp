@@ -9,40 +9,51 @@
 
 namespace pgabb {
 
-// One block A_ij of the p x p grid, stored as a chunk of int32 words:
-//   [ rptr  : width + 1   ]  dense row offsets over the stripe's row range,
-//                            relative to the block's first column entry
-//   [ items : 2 * nitems  ]  work items (u, c): local row u, and c, the index
-//                            of a run of at most kSplitV entries of row u;
-//                            increasing in (u, c)
-//   [ col   : nnz         ]  local column ids (rank - base of stripe j), each
-//                            row's run increasing
-// Local row ids are rank - base_i, where base_i is stripe i's first rank that
+// One block A_ij of the p x p grid, stored as a chunk of int32 words holding
+// the block and its transpose:
+//   [ rptr   : width + 1    ]  dense row offsets over stripe i's row range,
+//                              relative to the start of `col`
+//   [ items  : 2 * nitems   ]  row work items (u, c): local row u and c, the
+//                              index of a run of at most kSplitV entries of u
+//   [ col    : nnz          ]  local column ids (rank - base of stripe j)
+//   [ cptr   : cwidth + 1   ]  dense column offsets over stripe j's range,
+//                              relative to the start of `crow`
+//   [ citems : 2 * ncitems  ]  column work items (v, c), as above per column
+//   [ crow   : nnz          ]  local row ids of each column's entries
+// Local ids are rank - base_s, where base_s is stripe s's first rank that
 // can own an edge (isolated vertices rank lowest and own none).  One chunk is
-// the unit of host<->device movement.  Splitting long rows into items bounds
-// the work of one item when the block plays A_ij in a task.
+// the unit of host<->device movement.  Items bound the work of one wave when
+// the block plays A_ij in a task (rows when the row of A_ik is staged,
+// columns when the row of A_jk is staged).
 constexpr int32_t kSplitV = 32;
 
 struct BlockInfo {
     int32_t i = 0, j = 0;
-    int32_t width = 0;   // rows of the dense range of stripe i
-    int32_t nitems = 0;  // work items (rows split into runs of kSplitV)
+    int32_t width = 0;    // rows of the dense range of stripe i
+    int32_t cwidth = 0;   // columns of the dense range of stripe j
+    int32_t nitems = 0;   // row work items
+    int32_t ncitems = 0;  // column work items
     int64_t nnz = 0;
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
+    int64_t off_items() const { return chunk_off + width + 1; }
+    int64_t off_col() const { return off_items() + 2 * static_cast<int64_t>(nitems); }
+    int64_t off_cptr() const { return off_col() + nnz; }
+    int64_t off_citems() const { return off_cptr() + cwidth + 1; }
+    int64_t off_crow() const { return off_citems() + 2 * static_cast<int64_t>(ncitems); }
+    int64_t end() const { return off_crow() + nnz; }
 };
-
-inline int64_t block_chunk_words(int32_t width, int32_t nitems, int64_t nnz) {
-    return static_cast<int64_t>(width) + 1 + 2 * static_cast<int64_t>(nitems) + nnz;
-}
 
 // Device view of one block.
 struct BlockRef {
     const int32_t *rptr;
     const int32_t *items;
     const int32_t *col;
+    const int32_t *cptr;
+    const int32_t *citems;
+    const int32_t *crow;
     int32_t nitems;
-    int32_t width;
+    int32_t ncitems;
 };
 
 // One task: the block-list (A_ij, A_ik, A_jk).
@@ -58,6 +69,11 @@ struct TaskDesc {
     int32_t width_k;  // columns of stripe k
     int32_t slot;     // index of the task's counter
 };
+
+// Which list of a block-list edge (u, v) is staged in LDS: the row u of A_ik
+// (the edge block is walked by rows) or the row v of A_jk (walked by
+// columns).  Both count the same common entries.
+enum Orient : int { kOrientRow = 0, kOrientCol = 1 };
 
 }  // namespace pgabb
 

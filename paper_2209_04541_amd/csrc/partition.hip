@@ -21,6 +21,9 @@
 
 namespace pgabb {
 
+bool radix_sort_u64_bits(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+                         int64_t n, int lo_bit, int hi_bit, hipStream_t s);
+
 namespace {
 
 constexpr int B = 256;
@@ -60,6 +63,55 @@ __global__ void k_nnz_cuts(const int64_t *__restrict__ row_off, int32_t n, int64
     cuts[s] = static_cast<int32_t>(lo);
 }
 
+// The row walks below give each row to one wavefront: rows of the reversed
+// graph (in-edges) reach tens of thousands of entries on skewed graphs.
+// Lane l of the wave handles stripe j0 + l of the row's column stripes
+// [j0, j1] (p <= 64), finding the run of that stripe by binary search in the
+// sorted row; per-entry work strides the row 64 entries at a time.
+
+// First index in [lo, hi) whose column is >= c (hi when none).
+__device__ __forceinline__ int64_t first_at_least(const int32_t *__restrict__ col, int64_t lo,
+                                                  int64_t hi, int32_t c) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Stripe of x from cuts held in LDS (largest s < p with c[s] <= x).
+__device__ __forceinline__ int32_t stripe_lds(int32_t x, const int32_t *c, int32_t p) {
+    int32_t lo = 0, hi = p - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (c[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct RowRun {
+    int32_t si, j;   // row stripe; this lane's column stripe
+    int64_t lo, hi;  // this lane's run [lo, hi) (empty when lo == hi)
+};
+
+// Row x's run in stripe j0 + lane.  Every lane calls it for the same x.
+__device__ __forceinline__ RowRun row_run(const int32_t *__restrict__ col, int64_t e0, int64_t e1,
+                                          int32_t x, const int32_t *c, int32_t p) {
+    RowRun r;
+    r.si = stripe_lds(x, c, p);
+    const int32_t j0 = stripe_lds(col[e0], c, p);
+    const int32_t j1 = stripe_lds(col[e1 - 1], c, p);
+    r.j = j0 + lane_id();
+    r.lo = r.hi = 0;
+    if (r.j <= j1) {
+        r.lo = r.j == j0 ? e0 : first_at_least(col, e0, e1, c[r.j]);
+        r.hi = r.j == j1 ? e1 : first_at_least(col, e0, e1, c[r.j + 1]);
+    }
+    return r;
+}
+
 // Per block (i, j): number of entries and number of work items (each row's
 // run split into pieces of at most kSplitV entries).  Each workgroup
 // accumulates in LDS and flushes its non-zero counters.
@@ -67,68 +119,57 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
                                                    const int32_t *__restrict__ col, int32_t n,
                                                    CutTable ct,
                                                    unsigned long long *__restrict__ nnz,
-                                                   unsigned int *__restrict__ rows) {
+                                                   unsigned int *__restrict__ items) {
     __shared__ unsigned int s_nnz[kMaxP * kMaxP];
-    __shared__ unsigned int s_rows[kMaxP * kMaxP];
-    const int pp = ct.p * ct.p;
+    __shared__ unsigned int s_items[kMaxP * kMaxP];
+    __shared__ int32_t s_c[kMaxP + 1];
+    const int p = ct.p;
+    const int pp = p * p;
     for (int q = threadIdx.x; q < pp; q += B) {
         s_nnz[q] = 0;
-        s_rows[q] = 0;
+        s_items[q] = 0;
     }
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
     __syncthreads();
-    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
         const int64_t e0 = row_off[x], e1 = row_off[x + 1];
         if (e0 == e1) continue;
-        const int32_t si = stripe_of(static_cast<int32_t>(x), ct);
-        int32_t j = stripe_of(col[e0], ct);
-        unsigned int run = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int32_t y = col[e];
-            while (y >= ct.c[j + 1]) {
-                if (run) {
-                    atomicAdd(&s_nnz[si * ct.p + j], run);
-                    atomicAdd(&s_rows[si * ct.p + j], (run + kSplitV - 1) / kSplitV);
-                }
-                run = 0;
-                ++j;
-            }
-            ++run;
+        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
+        const int64_t cnt = r.hi - r.lo;
+        if (cnt > 0) {
+            atomicAdd(&s_nnz[r.si * p + r.j], static_cast<unsigned int>(cnt));
+            atomicAdd(&s_items[r.si * p + r.j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
         }
-        atomicAdd(&s_nnz[si * ct.p + j], run);
-        atomicAdd(&s_rows[si * ct.p + j], (run + kSplitV - 1) / kSplitV);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < pp; q += B) {
         if (s_nnz[q]) {
             atomicAdd(&nnz[q], static_cast<unsigned long long>(s_nnz[q]));
-            atomicAdd(&rows[q], s_rows[q]);
+            atomicAdd(&items[q], s_items[q]);
         }
     }
 }
 
 // Per-row entry counts of every block the row touches, written at the row's
-// slot of the block's dense row range.
-__global__ void k_row_slot_counts(const int64_t *__restrict__ row_off,
-                                  const int32_t *__restrict__ col, int32_t n, CutTable ct,
-                                  const int64_t *__restrict__ slot_base,  // p*p, -1 if no block
-                                  uint32_t *__restrict__ slots) {
-    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+// slot of the block's dense row range (slot_base indexed by (row stripe,
+// column stripe)).
+__global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict__ row_off,
+                                                       const int32_t *__restrict__ col, int32_t n,
+                                                       CutTable ct,
+                                                       const int64_t *__restrict__ slot_base,
+                                                       uint32_t *__restrict__ slots) {
+    __shared__ int32_t s_c[kMaxP + 1];
+    const int p = ct.p;
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
+    __syncthreads();
+    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
         const int64_t e0 = row_off[x], e1 = row_off[x + 1];
         if (e0 == e1) continue;
-        const int32_t si = stripe_of(static_cast<int32_t>(x), ct);
-        const int64_t lx = x - ct.base[si];
-        int32_t j = stripe_of(col[e0], ct);
-        uint32_t run = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int32_t y = col[e];
-            while (y >= ct.c[j + 1]) {
-                if (run) slots[slot_base[si * ct.p + j] + lx] = run;
-                run = 0;
-                ++j;
-            }
-            ++run;
-        }
-        slots[slot_base[si * ct.p + j] + lx] = run;
+        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
+        if (r.hi > r.lo)
+            slots[slot_base[r.si * p + r.j] + (x - ct.base[r.si])] = static_cast<uint32_t>(r.hi - r.lo);
     }
 }
 
@@ -144,11 +185,12 @@ __device__ __forceinline__ int32_t block_of_slot(int64_t q, const int64_t *sb, i
 }
 
 // Dense row offsets of every block from the scanned slot counts, and the
-// number of work items of every row (for the item-list compaction).
+// number of work items of every row (for the item-list compaction).  The
+// region offsets are absolute int32-word offsets in the arena.
 __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ scanned,
                                                  int64_t nslots,
                                                  const int64_t *__restrict__ slot_base_dense,
-                                                 const int64_t *__restrict__ chunk_off,
+                                                 const int64_t *__restrict__ rptr_off,
                                                  const int32_t *__restrict__ width, int32_t nblk,
                                                  int32_t *__restrict__ arena,
                                                  uint32_t *__restrict__ flags) {
@@ -159,7 +201,7 @@ __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ sc
         const int32_t b = block_of_slot(q, s_sb, nblk);
         const int64_t r = q - s_sb[b];
         const uint32_t v = scanned[q] - scanned[s_sb[b]];
-        arena[chunk_off[b] + r] = static_cast<int32_t>(v);
+        arena[rptr_off[b] + r] = static_cast<int32_t>(v);
         flags[q] = r < width[b] ? (scanned[q + 1] - scanned[q] + kSplitV - 1) / kSplitV : 0u;
     }
 }
@@ -167,9 +209,8 @@ __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ sc
 __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ flags,
                                                   const uint32_t *__restrict__ pos, int64_t nslots,
                                                   const int64_t *__restrict__ slot_base_dense,
-                                                  const int64_t *__restrict__ chunk_off,
-                                                  const int32_t *__restrict__ width, int32_t nblk,
-                                                  int32_t *__restrict__ arena) {
+                                                  const int64_t *__restrict__ items_off,
+                                                  int32_t nblk, int32_t *__restrict__ arena) {
     extern __shared__ int64_t s_sb[];
     for (int q = threadIdx.x; q < nblk; q += B) s_sb[q] = slot_base_dense[q];
     __syncthreads();
@@ -179,7 +220,7 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
         const int32_t b = block_of_slot(q, s_sb, nblk);
         const int64_t r = q - s_sb[b];
         const uint32_t at = pos[q] - pos[s_sb[b]];
-        int32_t *it = arena + chunk_off[b] + width[b] + 1 + 2 * static_cast<int64_t>(at);
+        int32_t *it = arena + items_off[b] + 2 * static_cast<int64_t>(at);
         for (uint32_t c = 0; c < f; ++c) {
             it[2 * c] = static_cast<int32_t>(r);
             it[2 * c + 1] = static_cast<int32_t>(c);
@@ -187,33 +228,72 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
     }
 }
 
-// Column entries: row x's run in stripe j goes to block (stripe(x), j) at the
-// row's dense offset, as local column ids.
-__global__ void k_fill_cols(const int64_t *__restrict__ row_off, const int32_t *__restrict__ col,
-                            int32_t n, CutTable ct, const int32_t *__restrict__ blk_index,
-                            const int64_t *__restrict__ chunk_off,
-                            const int32_t *__restrict__ width,
-                            const int32_t *__restrict__ nitems, int32_t *__restrict__ arena) {
-    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+// Entries: row x's run in stripe j goes to the block of (stripe(x), j) at the
+// row's dense offset, as local column ids.  The lane of stripe j first
+// computes where entry e of its run lands (dst[j] + e); then the wave strides
+// the row's entries.
+__global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row_off,
+                                                 const int32_t *__restrict__ col, int32_t n,
+                                                 CutTable ct, const int32_t *__restrict__ blk_index,
+                                                 const int64_t *__restrict__ rptr_off,
+                                                 const int64_t *__restrict__ col_off,
+                                                 int32_t *__restrict__ arena) {
+    __shared__ int32_t s_c[kMaxP + 1];
+    __shared__ int32_t s_base[kMaxP];
+    __shared__ int64_t s_dst[B / 64][kMaxP];
+    const int p = ct.p;
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
+    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ct.base[q];
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
         const int64_t e0 = row_off[x], e1 = row_off[x + 1];
         if (e0 == e1) continue;
-        const int32_t si = stripe_of(static_cast<int32_t>(x), ct);
-        const int64_t lx = x - ct.base[si];
-        int32_t j = -1;
-        int32_t *dst = nullptr;
-        int32_t cbase = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int32_t y = col[e];
-            if (j < 0 || y >= ct.c[j + 1]) {
-                j = stripe_of(y, ct);
-                const int32_t b = blk_index[si * ct.p + j];
-                const int64_t c0 = chunk_off[b];
-                dst = arena + c0 + width[b] + 1 + 2 * static_cast<int64_t>(nitems[b]) + arena[c0 + lx];
-                cbase = ct.base[j];
-            }
-            *dst++ = y - cbase;
+        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
+        if (r.hi > r.lo) {
+            const int32_t b = blk_index[r.si * p + r.j];
+            const int64_t lx = x - s_base[r.si];
+            s_dst[w][lane] = col_off[b] + arena[rptr_off[b] + lx] - r.lo;
         }
+        wave_lds_sync();
+        const int32_t j0 = r.j - lane;
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const int32_t y = col[e];
+            const int32_t j = stripe_lds(y, s_c, p);
+            arena[s_dst[w][j - j0] + e] = y - s_base[j];
+        }
+        wave_lds_sync();
     }
+}
+
+// Reversed oriented graph: key = y << nb | x for every entry (x, y).
+__global__ __launch_bounds__(B) void k_rev_keys(const int64_t *__restrict__ row_off,
+                                                const int32_t *__restrict__ col, int32_t n, int nb,
+                                                uint64_t *__restrict__ keys) {
+    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves)
+        for (int64_t e = row_off[x] + lane_id(); e < row_off[x + 1]; e += kWave)
+            keys[e] = (static_cast<uint64_t>(col[e]) << nb) | static_cast<uint64_t>(x);
+}
+
+__global__ void k_rev_counts_cols(const uint64_t *__restrict__ keys, int64_t m, int nb,
+                                  int32_t *__restrict__ cnt, int32_t *__restrict__ rcol) {
+    const uint64_t mask = (1ull << nb) - 1;
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        const uint64_t k = valid ? keys[e] : 0ull;
+        add_run_lengths(valid, static_cast<int64_t>(k >> nb), cnt);
+        if (valid) rcol[e] = static_cast<int32_t>(k & mask);
+    }
+}
+
+__global__ void k_widen32(const int32_t *__restrict__ in, int32_t n, int64_t *__restrict__ out) {
+    for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B)
+        out[v] = in[v];
 }
 
 unsigned cap_grid(int64_t work) {
@@ -269,25 +349,47 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
     g->arena_words = 0;
 
     if (g->m > 0) {
-        // ---- block sizes
         const size_t pp = static_cast<size_t>(p) * p;
-        DArray<unsigned long long> dnnz(pp, s);
-        DArray<unsigned int> drows(pp, s);
+        const unsigned lgrid = cap_grid(n);
+        const unsigned wgrid = cap_grid(static_cast<int64_t>(n) * 64);  // a wave per row
+
+        // ---- reversed oriented graph (in-edges, sorted by (y, x)): its blocks
+        // are the transposes of the forward blocks
+        DArray<int64_t> rev_off(static_cast<size_t>(n) + 1, s);
+        DArray<int32_t> rev_col(static_cast<size_t>(g->m), s);
+        {
+            DArray<uint64_t> k0(g->m, s), k1(g->m, s);
+            k_rev_keys<<<wgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, k0.get());
+            PGABB_HIP(hipGetLastError());
+            uint64_t *kk = k0.get();
+            if (radix_sort_u64_bits(k0.get(), k1.get(), nullptr, nullptr, g->m, 0, 2 * g->nb, s)) kk = k1.get();
+            DArray<int32_t> cnt(static_cast<size_t>(n), s);
+            PGABB_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * n, s));
+            k_rev_counts_cols<<<cap_grid(g->m), B, 0, s>>>(kk, g->m, g->nb, cnt.get(), rev_col.get());
+            DArray<int64_t> wide(static_cast<size_t>(n), s);
+            k_widen32<<<lgrid, B, 0, s>>>(cnt.get(), n, wide.get());
+            PGABB_HIP(hipGetLastError());
+            scan_exclusive_i64(wide.get(), rev_off.get(), n, rev_off.get() + n, s);
+        }
+
+        // ---- block sizes, forward (entries, row items) and reversed (column items)
+        DArray<unsigned long long> dnnz(pp, s), dnnz_r(pp, s);
+        DArray<unsigned int> ditems(pp, s), ditems_r(pp, s);
         PGABB_HIP(hipMemsetAsync(dnnz.get(), 0, pp * sizeof(unsigned long long), s));
-        PGABB_HIP(hipMemsetAsync(drows.get(), 0, pp * sizeof(unsigned int), s));
-        k_block_sizes<<<cap_grid(n), B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, dnnz.get(), drows.get());
+        PGABB_HIP(hipMemsetAsync(dnnz_r.get(), 0, pp * sizeof(unsigned long long), s));
+        PGABB_HIP(hipMemsetAsync(ditems.get(), 0, pp * sizeof(unsigned int), s));
+        PGABB_HIP(hipMemsetAsync(ditems_r.get(), 0, pp * sizeof(unsigned int), s));
+        k_block_sizes<<<wgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, dnnz.get(), ditems.get());
+        k_block_sizes<<<wgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, dnnz_r.get(), ditems_r.get());
         PGABB_HIP(hipGetLastError());
         std::vector<unsigned long long> hnnz(pp);
-        std::vector<unsigned int> hrows(pp);
+        std::vector<unsigned int> hitems(pp), hitems_r(pp);
         PGABB_HIP(hipMemcpyAsync(hnnz.data(), dnnz.get(), pp * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipMemcpyAsync(hrows.data(), drows.get(), pp * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        PGABB_HIP(hipMemcpyAsync(hitems.data(), ditems.get(), pp * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        PGABB_HIP(hipMemcpyAsync(hitems_r.data(), ditems_r.get(), pp * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
 
-        // ---- block table (row-major block order), chunk and slot layout
-        std::vector<int64_t> slot_base_pp(pp, -1);
-        std::vector<int64_t> slot_base_dense, chunk_off_dense;
-        std::vector<int32_t> width_dense, nrows_dense;
-        int64_t nslots = 0, words = 0;
+        // ---- block table (row-major block order) and chunk layout
         for (int32_t i = 0; i < p; ++i) {
             for (int32_t j = 0; j < p; ++j) {
                 const size_t q = static_cast<size_t>(i) * p + j;
@@ -297,54 +399,72 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 bi.i = i;
                 bi.j = j;
                 bi.width = cuts[i + 1] - base[i];
-                bi.nitems = static_cast<int32_t>(hrows[q]);
+                bi.cwidth = cuts[j + 1] - base[j];
+                bi.nitems = static_cast<int32_t>(hitems[q]);
+                bi.ncitems = static_cast<int32_t>(hitems_r[static_cast<size_t>(j) * p + i]);
                 bi.nnz = static_cast<int64_t>(hnnz[q]);
-                bi.chunk_off = words;
-                bi.chunk_len = block_chunk_words(bi.width, bi.nitems, bi.nnz);
-                words += bi.chunk_len;
+                bi.chunk_off = g->arena_words;
+                bi.chunk_len = bi.end() - bi.chunk_off;
+                g->arena_words += bi.chunk_len;
                 g->block_of[q] = static_cast<int32_t>(g->blocks.size());
                 g->blocks.push_back(bi);
-                slot_base_pp[q] = nslots;
-                slot_base_dense.push_back(nslots);
-                chunk_off_dense.push_back(bi.chunk_off);
-                width_dense.push_back(bi.width);
-                nrows_dense.push_back(bi.nitems);
-                nslots += static_cast<int64_t>(bi.width) + 1;
             }
         }
         const int32_t nblk = static_cast<int32_t>(g->blocks.size());
-        g->arena_words = words;
-        g->arena.reset(static_cast<size_t>(words), s);
+        g->arena.reset(static_cast<size_t>(g->arena_words), s);
 
-        DArray<int64_t> d_sb_pp(pp, s), d_sb(nblk, s), d_co(nblk, s);
-        DArray<int32_t> d_w(nblk, s), d_nr(nblk, s), d_bidx(pp, s);
-        PGABB_HIP(hipMemcpyAsync(d_sb_pp.get(), slot_base_pp.data(), pp * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(d_sb.get(), slot_base_dense.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(d_co.get(), chunk_off_dense.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(d_w.get(), width_dense.data(), nblk * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(d_nr.get(), nrows_dense.data(), nblk * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(d_bidx.get(), g->block_of.data(), pp * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // Both passes run the same machinery: per-row run counts at dense
+        // slots, one scan (row offsets), per-row item counts, one scan (item
+        // lists), then the entries.  The reversed pass fills the transposes.
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool rev = pass == 1;
+            const int64_t *off = rev ? rev_off.get() : g->row_off.get();
+            const int32_t *cl = rev ? rev_col.get() : g->col.get();
+            std::vector<int64_t> sb_pp(pp, -1), sb_dense(nblk), rptr_off(nblk), items_off(nblk), col_off(nblk);
+            std::vector<int32_t> width(nblk), bidx(pp, -1);
+            int64_t nslots = 0;
+            for (int32_t b = 0; b < nblk; ++b) {
+                const BlockInfo &bi = g->blocks[b];
+                // forward: rows in stripe i, columns in stripe j; reversed: the
+                // transpose, rows in stripe j, columns in stripe i
+                const size_t q = rev ? static_cast<size_t>(bi.j) * p + bi.i : static_cast<size_t>(bi.i) * p + bi.j;
+                sb_pp[q] = nslots;
+                bidx[q] = b;
+                sb_dense[b] = nslots;
+                width[b] = rev ? bi.cwidth : bi.width;
+                rptr_off[b] = rev ? bi.off_cptr() : bi.chunk_off;
+                items_off[b] = rev ? bi.off_citems() : bi.off_items();
+                col_off[b] = rev ? bi.off_crow() : bi.off_col();
+                nslots += static_cast<int64_t>(width[b]) + 1;
+            }
+            DArray<int64_t> d_sb_pp(pp, s), d_sb(nblk, s), d_ro(nblk, s), d_io(nblk, s), d_co(nblk, s);
+            DArray<int32_t> d_w(nblk, s), d_bidx(pp, s);
+            PGABB_HIP(hipMemcpyAsync(d_sb_pp.get(), sb_pp.data(), pp * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_sb.get(), sb_dense.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_ro.get(), rptr_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_io.get(), items_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_co.get(), col_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_w.get(), width.data(), nblk * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            PGABB_HIP(hipMemcpyAsync(d_bidx.get(), bidx.data(), pp * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
-        // ---- dense row offsets: per-row counts at their slots, one global scan
-        DArray<uint32_t> slots(static_cast<size_t>(nslots) + 1, s), flags(static_cast<size_t>(nslots) + 1, s);
-        PGABB_HIP(hipMemsetAsync(slots.get(), 0, (nslots + 1) * sizeof(uint32_t), s));
-        k_row_slot_counts<<<cap_grid(n), B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, d_sb_pp.get(), slots.get());
-        PGABB_HIP(hipGetLastError());
-        scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
-        const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
-        k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb.get(), d_co.get(), d_w.get(), nblk,
-                                                     g->arena.get(), flags.get());
-        PGABB_HIP(hipGetLastError());
-        // ---- item lists: each row's items at the scanned item offsets
-        PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
-        scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // reuse slots as positions
-        k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_co.get(), d_w.get(),
-                                                    nblk, g->arena.get());
-        PGABB_HIP(hipGetLastError());
-        // ---- column entries
-        k_fill_cols<<<cap_grid(n), B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, d_bidx.get(), d_co.get(), d_w.get(),
-                                              d_nr.get(), g->arena.get());
-        PGABB_HIP(hipGetLastError());
+            DArray<uint32_t> slots(static_cast<size_t>(nslots) + 1, s), flags(static_cast<size_t>(nslots) + 1, s);
+            PGABB_HIP(hipMemsetAsync(slots.get(), 0, (nslots + 1) * sizeof(uint32_t), s));
+            k_row_slot_counts<<<wgrid, B, 0, s>>>(off, cl, n, ct, d_sb_pp.get(), slots.get());
+            PGABB_HIP(hipGetLastError());
+            scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
+            const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
+            k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb.get(), d_ro.get(), d_w.get(), nblk,
+                                                         g->arena.get(), flags.get());
+            PGABB_HIP(hipGetLastError());
+            PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
+            scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // slots now item positions
+            k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_io.get(),
+                                                          nblk, g->arena.get());
+            PGABB_HIP(hipGetLastError());
+            k_fill_cols<<<wgrid, B, 0, s>>>(off, cl, n, ct, d_bidx.get(), d_ro.get(), d_co.get(), g->arena.get());
+            PGABB_HIP(hipGetLastError());
+            PGABB_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
+        }
 
         // ---- tasks: i <= j <= k with three non-empty blocks
         for (int32_t i = 0; i < p; ++i)

@@ -186,7 +186,7 @@ static void counter_loop(pgabb_server *s) {
             pgabb_graph *g = r->g;
             for (const Task &t : g->tasks) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
-                pre.push_back(pre.back() + g->blocks[t.bij].nitems);
+                pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt)));
                 max_wk = std::max(max_wk, td.back().width_k);
             }
             max_out = std::max(max_out, g->max_out);
@@ -217,6 +217,7 @@ static void counter_loop(pgabb_server *s) {
                 a.item_pre = dpre.get();
                 a.ntasks = T;
                 a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back());
+                a.orient = orient_of_option(s->opt);
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;

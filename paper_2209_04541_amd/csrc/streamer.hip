@@ -141,6 +141,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     for (int32_t t = 0; t < T; ++t) max_wk = std::max(max_wk, g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k]);
     const int mode = mode_of_option(opt.kernel);
     const int words = choose_lds_words(mode, g->max_out, max_wk);
+    const int orient = orient_of_option(opt);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     const int grab_opt = opt.rows_per_grab;
     const int window_tasks = 64;
@@ -259,7 +260,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 const int32_t ti = wtasks[q];
                 hdesc[ti] = make_desc(g, reinterpret_cast<const int32_t *>(pool.get()), g->tasks[ti], ti,
                                       chunk_dev.data());
-                items += g->blocks[g->tasks[ti].bij].nitems;
+                items += task_items(g, g->tasks[ti], orient);
                 hpre[pre_at + q + 1] = items;
             }
             hipStream_t st = cs[win % nstreams];
@@ -278,6 +279,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             a.item_pre = dpre.get() + pre_at;
             a.ntasks = W;
             a.grab = grab_opt > 0 ? grab_opt : default_grab(items);
+            a.orient = orient;
             a.total = items;
             a.counts = dcnt.get();
             a.next = dcnt.get() + T + static_cast<size_t>(win) * kQueueWords;

@@ -3,16 +3,16 @@
 // PGAbB Section 3.6: for a block-list (A_ij, A_ik, A_jk) and each edge (u, v)
 // of A_ij, the triangles closed inside the list are the common entries of
 // row u of A_ik and row v of A_jk; the intersection may be list based or
-// hash based.  Here one wavefront takes one work item of A_ij, a run of at
-// most kSplitV entries v of a row u:
-//   1. stage row u of A_ik (the list every probe of this row is checked
-//      against) in the wave's LDS -- an open-addressing hash table, or a
-//      bitmap over stripe k's columns -- or leave it in place for binary
-//      search when it is too long to stage;
-//   2. walk the rows A_jk[v] of all v in A_ij[u] as one flattened sequence:
-//      lane l takes element base + l, so every 64-wide load is contiguous
-//      within a row and no lane idles on short rows;
-//   3. probe each element against the staged row and count hits in
+// hash based.  Here one wavefront takes one work item of A_ij: a run of at
+// most kSplitV entries v of a row u (stage A_ik[u], walk the A_jk[v]), or of
+// entries u of a column v (stage A_jk[v], walk the A_ik[u]):
+//   1. stage the shared list in the wave's LDS -- an open-addressing hash
+//      table behind a bit filter, or a bitmap over stripe k's columns -- or
+//      leave it in place for binary search when it is too long to stage;
+//   2. walk the other lists as one flattened sequence: lane l takes element
+//      base + l, so every 64-wide load is contiguous within a list and no
+//      lane idles on short lists;
+//   3. probe each element against the staged list and count hits in
 //      registers; the caller reduces across the wave.
 #pragma once
 
@@ -39,73 +39,118 @@ __device__ __forceinline__ uint32_t sorted_contains(const int32_t *__restrict__ 
     return (lo < end && a[lo] == w) ? 1u : 0u;
 }
 
-// Triangles closed by the entries [vb, ve) of row u of ij inside the
-// block-list, per lane (the sum over lanes is the item's count).  `lds` holds
-// LDS_WORDS int32 words private to the wave.  Column ids of ik and jk lie in
-// [wbase, wbase + width_k).  Every lane of the wave must call this with the
-// same arguments.
-template <int MODE, int LDS_WORDS, int UNROLL = 4>
-__device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &ik,
-                                           const BlockRef &jk, int32_t width_k, int32_t u,
-                                           int32_t vb, int32_t ve, int32_t *__restrict__ lds,
-                                           int32_t wbase = 0) {
-    const int lane = lane_id();
-    const int32_t sb = ik.rptr[u], se = ik.rptr[u + 1];
-    const int32_t slen = se - sb;
-    if (slen == 0 || vb >= ve) return 0u;
+// LDS split of a hash-mode wave region of LDS_WORDS words: a power-of-two
+// table of kTableCap words and a membership filter of the rest.  The
+// template sizes used are 320, 640, 1280, 2304 and 4352 words.
+template <int LDS_WORDS>
+struct HashLds {
+    static constexpr int kTableCap = LDS_WORDS >= 4352 ? 4096
+                                     : LDS_WORDS >= 2304 ? 2048
+                                     : LDS_WORDS >= 1280 ? 1024
+                                     : LDS_WORDS >= 640 ? 512
+                                     : LDS_WORDS >= 320 ? 256 : 64;
+    static constexpr int kFilterCap = LDS_WORDS - kTableCap;  // words
+};
 
-    // ---- stage row u of A_ik
+__device__ __forceinline__ uint32_t filter_slot(int32_t w, int fshift) {
+    return (static_cast<uint32_t>(w) * 0x85EBCA77u) >> fshift;
+}
+
+// One work item of a block-list: the staged list S = st_col[st_rptr[srow] ..
+// st_rptr[srow + 1]) and the walked lists L_x = wk_col[wk_rptr[x] ..
+// wk_rptr[x + 1]) for the ids x in ids[ib .. ie).  Returns, per lane, part of
+// sum_x |S & L_x| (the sum over lanes is the item's count).  With the edge
+// block walked by rows this is S = A_ik[u], L_v = A_jk[v] for v in A_ij[u];
+// walked by columns, S = A_jk[v], L_u = A_ik[u] for u with (u, v) in A_ij.
+// `lds` holds LDS_WORDS int32 words private to the wave.  Column ids of both
+// lists lie in [wbase, wbase + width_k).  Every lane of the wave must call
+// this with the same arguments.
+//
+// Hash staging: S goes into an open-addressing table (load <= 2/3) and into
+// a bit filter with about eight bits per entry; a probe reads the filter
+// first, so most misses -- nine in ten probes on skewed graphs -- cost one
+// LDS read.
+template <int MODE, int LDS_WORDS, int UNROLL = 4>
+__device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
+                                            const int32_t *__restrict__ st_col, int32_t srow,
+                                            const int32_t *__restrict__ wk_rptr,
+                                            const int32_t *__restrict__ wk_col,
+                                            const int32_t *__restrict__ ids, int32_t ib,
+                                            int32_t ie, int32_t width_k,
+                                            int32_t *__restrict__ lds, int32_t wbase = 0) {
+    const int lane = lane_id();
+    const int32_t sb = st_rptr[srow], se = st_rptr[srow + 1];
+    const int32_t slen = se - sb;
+    if (slen == 0 || ib >= ie) return 0u;
+    const int32_t vb = ib, ve = ie;
+
+    // ---- stage S
     int mode = MODE;
-    int shift = 0;
+    int shift = 0, fshift = 0;
     uint32_t tmask = 0;
-    int words = 0;
+    int words = 0, fwords = 0;
+    int32_t *table = lds;
     if (mode == kModeBitmap) {
         words = (width_k + 31) >> 5;
         if (words > LDS_WORDS) mode = kModeHash;
     }
     if (mode == kModeHash) {
+        constexpr int TC = HashLds<LDS_WORDS>::kTableCap;
+        constexpr int FC = HashLds<LDS_WORDS>::kFilterCap;
         int lg = 6;
-        while ((1 << lg) < 2 * slen) ++lg;
-        if ((1 << lg) > LDS_WORDS) {
+        while ((1 << lg) * 2 < 3 * slen) ++lg;
+        if ((1 << lg) > TC || FC < 2) {
             mode = kModeSearch;
         } else {
             words = 1 << lg;
             shift = 32 - lg;
             tmask = static_cast<uint32_t>(words - 1);
+            int flg = 8;  // filter bits: a power of two >= 8 * slen, >= 256
+            while ((1 << flg) < 8 * slen && (1 << flg) < 32 * FC) ++flg;
+            while ((1 << flg) > 32 * FC) --flg;
+            fwords = (1 << flg) >> 5;
+            fshift = 32 - flg;
+            table = lds + FC;
         }
     }
     if (mode == kModeHash) {
-        for (int q = lane; q < words; q += kWave) lds[q] = -1;
+        for (int q = lane; q < words; q += kWave) table[q] = -1;
+        for (int q = lane; q < fwords; q += kWave) lds[q] = 0;
         wave_lds_sync();
         for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-            const int32_t w = ik.col[idx];
+            const int32_t w = st_col[idx];
+            const uint32_t f = filter_slot(w, fshift);
+            atomicOr(reinterpret_cast<uint32_t *>(&lds[f >> 5]), 1u << (f & 31));
             uint32_t h = hash_slot(w, shift);
-            while (atomicCAS(&lds[h], -1, w) != -1) h = (h + 1) & tmask;
+            while (atomicCAS(&table[h], -1, w) != -1) h = (h + 1) & tmask;
         }
         wave_lds_sync();
     } else if (mode == kModeBitmap) {
         for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-            const int32_t w = ik.col[idx] - wbase;
+            const int32_t w = st_col[idx] - wbase;
             atomicOr(reinterpret_cast<uint32_t *>(&lds[w >> 5]), 1u << (w & 31));
         }
         wave_lds_sync();
     }
 
-    // ---- flattened walk over the rows A_jk[v], v in A_ij[u].  UNROLL
+    // ---- flattened walk over the lists L_x, x in ids[ib, ie).  UNROLL
     // chunks of 64 elements are located and loaded before any is probed, so
-    // each wave keeps UNROLL independent row loads in flight.
+    // each wave keeps UNROLL independent row loads in flight.  Each lane
+    // tracks the lane sg holding the row of its element; element numbers only
+    // grow, so sg only moves forward.
     uint32_t cnt = 0;
     for (int32_t b0 = vb; b0 < ve; b0 += kWave) {
         const int32_t idx = b0 + lane;
         int32_t pb = 0, len = 0;
         if (idx < ve) {
-            const int32_t v = ij.col[idx];
-            pb = jk.rptr[v];
-            len = jk.rptr[v + 1] - pb;
+            const int32_t v = ids[idx];
+            pb = wk_rptr[v];
+            len = wk_rptr[v + 1] - pb;
         }
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t pre = incl - len;
         const int32_t total = __shfl(incl, kWave - 1);
+        int sg = 0;
         for (int32_t base = 0; base < total; base += UNROLL * kWave) {
             int32_t w[UNROLL];
 #pragma unroll
@@ -113,16 +158,22 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
                 w[q] = -1;
                 if (base + q * kWave < total) {  // uniform across the wave
                     const int32_t e = base + q * kWave + lane;
-                    // the lane holding e's row: largest l with pre_l <= e
-                    int lo = 0;
-#pragma unroll
-                    for (int step = 32; step >= 1; step >>= 1) {
-                        const int cand = lo + step;
-                        if (__shfl(pre, cand) <= e) lo = cand;
+                    const int32_t es = e < total ? e : total - 1;
+                    // advance to the largest lane whose list starts at or before
+                    // es.  The shuffle runs on every lane before any test (a
+                    // shuffle under a partial mask does not read the masked
+                    // lanes' values), and the exit test is a wave-wide ballot.
+                    // At most 63 steps.
+                    for (int step = 0; step < kWave - 1; ++step) {
+                        const int nx = sg < kWave - 1 ? sg + 1 : sg;
+                        const int32_t pn = __shfl(pre, nx);
+                        const bool adv = (sg < kWave - 1) & (pn <= es);
+                        sg += adv ? 1 : 0;
+                        if (__ballot(adv) == 0) break;
                     }
-                    const int32_t spre = __shfl(pre, lo);
-                    const int32_t spb = __shfl(pb, lo);
-                    if (e < total) w[q] = jk.col[spb + (e - spre)];
+                    const int32_t spre = __shfl(pre, sg);
+                    const int32_t spb = __shfl(pb, sg);
+                    if (e < total) w[q] = wk_col[spb + (e - spre)];
                 }
             }
 #pragma unroll
@@ -130,21 +181,24 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
                 const int32_t wq = w[q];
                 if (wq < 0) continue;
                 if (mode == kModeHash) {
-                    uint32_t h = hash_slot(wq, shift);
-                    for (;;) {
-                        const int32_t sv = lds[h];
-                        if (sv == wq) {
-                            ++cnt;
-                            break;
+                    const uint32_t f = filter_slot(wq, fshift);
+                    if ((static_cast<uint32_t>(lds[f >> 5]) >> (f & 31)) & 1u) {
+                        uint32_t h = hash_slot(wq, shift);
+                        for (;;) {
+                            const int32_t sv = table[h];
+                            if (sv == wq) {
+                                ++cnt;
+                                break;
+                            }
+                            if (sv < 0) break;
+                            h = (h + 1) & tmask;
                         }
-                        if (sv < 0) break;
-                        h = (h + 1) & tmask;
                     }
                 } else if (mode == kModeBitmap) {
                     const int32_t wl = wq - wbase;
                     cnt += (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
                 } else {
-                    cnt += sorted_contains(ik.col, sb, se, wq);
+                    cnt += sorted_contains(st_col, sb, se, wq);
                 }
             }
         }
@@ -153,13 +207,14 @@ __device__ __forceinline__ uint32_t tc_row(const BlockRef &ij, const BlockRef &i
     // ---- leave the LDS clean for the next row of this wave
     if (mode == kModeBitmap) {
         wave_lds_sync();
-        for (int32_t idx = sb + lane; idx < se; idx += kWave) lds[(ik.col[idx] - wbase) >> 5] = 0;
+        for (int32_t idx = sb + lane; idx < se; idx += kWave) lds[(st_col[idx] - wbase) >> 5] = 0;
         wave_lds_sync();
     } else if (mode == kModeHash) {
         wave_lds_sync();
         if (MODE == kModeBitmap) {
             // a bitmap kernel expects zeroed LDS between rows
-            for (int q = lane; q < words; q += kWave) lds[q] = 0;
+            constexpr int FC = HashLds<LDS_WORDS>::kFilterCap;
+            for (int q = lane; q < FC + words; q += kWave) lds[q] = 0;
             wave_lds_sync();
         }
     }

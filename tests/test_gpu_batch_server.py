@@ -127,3 +127,15 @@ def test_server_small_budget_and_rejection():
         with pytest.raises(P.PgabbError) as ei:
             srv.submit(4, np.array([0], np.int32), np.array([7], np.int32))
         assert ei.value.status == P.EINVAL
+
+
+def test_batch_rows_longer_than_a_wave():
+    """Rows with more than 64 out-neighbours fill a whole 64-lane batch of
+    walked lists (the flattened walk's lane search then reaches lane 63)."""
+    gl = [graphs.complete(100)[0], graphs.complete(130)[0], graphs.wheel(300)[0],
+          gen.rgg(3000, 150, gen.seed(4, 99999))]
+    want = np.array([oracle.tc(*g) for g in gl], np.uint64)
+    with P.Batch(gl) as b:
+        for kernel in (P.KERNEL_HASH, P.KERNEL_BITMAP):
+            assert np.array_equal(b.count(kernel=kernel, waves_per_block=4, rows_per_grab=2), want)
+        assert np.array_equal(b.count(), want)

@@ -110,12 +110,33 @@ def test_explicit_cuts_with_empty_stripes():
 
 @pytest.mark.parametrize("kernel", [P.KERNEL_HASH, P.KERNEL_BITMAP, P.KERNEL_SEARCH])
 @pytest.mark.parametrize("waves", [2, 4, 8])
-def test_forced_kernels_agree(kernel, waves):
+@pytest.mark.parametrize("by_rows", [False, True])
+def test_forced_kernels_agree(kernel, waves, by_rows):
     n, s, d = gen.rgg(6000, 40, gen.seed(97, 0))
     want = oracle.tc(n, s, d)
-    say("kernel", kernel, waves, want)
+    say("kernel", kernel, waves, by_rows, want)
     for p in (1, 4):
-        assert gpu_count(n, s, d, p, kernel=kernel, waves_per_block=waves, rows_per_grab=3) == want
+        for unroll in (1, 8):
+            assert gpu_count(n, s, d, p, kernel=kernel, waves_per_block=waves, rows_per_grab=3,
+                             unroll=unroll, by_rows=by_rows) == want
+
+
+@pytest.mark.parametrize("by_rows", [False, True])
+def test_orientations_task_counts(by_rows):
+    """Row- and column-walked edge blocks find the same triangles per task."""
+    n, s, d = gen.rmat(12, 16, gen.seed(95, 77))
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    with P.Graph(n, s, d) as g:
+        g.partition(6)
+        total = g.count(by_rows=by_rows)
+        cuts = g.cuts()
+        ijk, cnt = g.task_counts()
+    B = oracle.block_counts(n, row_off, col, cuts)
+    got = np.zeros_like(B)
+    for (i, j, k), c in zip(ijk, cnt):
+        got[i, j, k] += c
+    assert np.array_equal(got, B)
+    assert total == int(B.sum())
 
 
 def test_device_edges_torch_stream():
