@@ -112,12 +112,70 @@ __device__ __forceinline__ RowRun row_run(const int32_t *__restrict__ col, int64
     return r;
 }
 
+// Rows are walked in two kinds of launch: short rows (at most kLongRow
+// entries) by one thread each, with a stripe pointer that moves forward as
+// the sorted row is read; long rows, collected into a device list first, by
+// one wave each, lane l finding the run of stripe j0 + l by binary search.
+constexpr int64_t kLongRow = 64;
+
+// Calls f(si, j, lo, hi) for every non-empty run [lo, hi) of row x (a short
+// row) in column stripe j.
+template <class F>
+__device__ __forceinline__ void short_row_runs(const int32_t *__restrict__ col, int64_t e0,
+                                               int64_t e1, int32_t x, const int32_t *c,
+                                               int32_t p, F f) {
+    const int32_t si = stripe_lds(x, c, p);
+    int32_t j = stripe_lds(col[e0], c, p);
+    int64_t lo = e0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int32_t y = col[e];
+        if (y >= c[j + 1]) {
+            f(si, j, lo, e);
+            lo = e;
+            j = stripe_lds(y, c, p);
+        }
+    }
+    f(si, j, lo, e1);
+}
+
+__global__ void k_collect_long(const int64_t *__restrict__ row_off, int32_t n,
+                               int32_t *__restrict__ list, unsigned int *__restrict__ count) {
+    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B)
+        if (row_off[x + 1] - row_off[x] > kLongRow) list[atomicAdd(count, 1u)] = static_cast<int32_t>(x);
+}
+
+// Row x of launch kind LONG: short launches take every row x < n a thread
+// at a time and skip long rows; long launches take the listed rows a wave at
+// a time.  Calls g(x, e0, e1) for each row taken, uniformly across a wave in
+// long launches.
+template <bool LONG, class G>
+__device__ __forceinline__ void for_rows(const int64_t *__restrict__ row_off, int32_t n,
+                                         const int32_t *__restrict__ list,
+                                         const unsigned int *__restrict__ count, G g) {
+    if (!LONG) {
+        for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+            const int64_t e0 = row_off[x], e1 = row_off[x + 1];
+            if (e0 == e1 || e1 - e0 > kLongRow) continue;
+            g(static_cast<int32_t>(x), e0, e1);
+        }
+    } else {
+        const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+        const int64_t nl = *count;
+        for (int64_t i = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; i < nl; i += nwaves) {
+            const int32_t x = list[i];
+            g(x, row_off[x], row_off[x + 1]);
+        }
+    }
+}
+
 // Per block (i, j): number of entries and number of work items (each row's
 // run split into pieces of at most kSplitV entries).  Each workgroup
 // accumulates in LDS and flushes its non-zero counters.
+template <bool LONG>
 __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ row_off,
                                                    const int32_t *__restrict__ col, int32_t n,
-                                                   CutTable ct,
+                                                   CutTable ct, const int32_t *__restrict__ list,
+                                                   const unsigned int *__restrict__ count,
                                                    unsigned long long *__restrict__ nnz,
                                                    unsigned int *__restrict__ items) {
     __shared__ unsigned int s_nnz[kMaxP * kMaxP];
@@ -131,17 +189,21 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
     }
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
     __syncthreads();
-    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
-    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
-        const int64_t e0 = row_off[x], e1 = row_off[x + 1];
-        if (e0 == e1) continue;
-        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
-        const int64_t cnt = r.hi - r.lo;
+    auto add = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
+        const int64_t cnt = hi - lo;
         if (cnt > 0) {
-            atomicAdd(&s_nnz[r.si * p + r.j], static_cast<unsigned int>(cnt));
-            atomicAdd(&s_items[r.si * p + r.j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
+            atomicAdd(&s_nnz[si * p + j], static_cast<unsigned int>(cnt));
+            atomicAdd(&s_items[si * p + j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
         }
-    }
+    };
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+        if (LONG) {
+            const RowRun r = row_run(col, e0, e1, x, s_c, p);
+            add(r.si, r.j, r.lo, r.hi);
+        } else {
+            short_row_runs(col, e0, e1, x, s_c, p, add);
+        }
+    });
     __syncthreads();
     for (int q = threadIdx.x; q < pp; q += B) {
         if (s_nnz[q]) {
@@ -154,23 +216,30 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
 // Per-row entry counts of every block the row touches, written at the row's
 // slot of the block's dense row range (slot_base indexed by (row stripe,
 // column stripe)).
+template <bool LONG>
 __global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict__ row_off,
                                                        const int32_t *__restrict__ col, int32_t n,
-                                                       CutTable ct,
+                                                       CutTable ct, const int32_t *__restrict__ list,
+                                                       const unsigned int *__restrict__ count,
                                                        const int64_t *__restrict__ slot_base,
                                                        uint32_t *__restrict__ slots) {
     __shared__ int32_t s_c[kMaxP + 1];
+    __shared__ int32_t s_base[kMaxP];
     const int p = ct.p;
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
+    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ct.base[q];
     __syncthreads();
-    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
-    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
-        const int64_t e0 = row_off[x], e1 = row_off[x + 1];
-        if (e0 == e1) continue;
-        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
-        if (r.hi > r.lo)
-            slots[slot_base[r.si * p + r.j] + (x - ct.base[r.si])] = static_cast<uint32_t>(r.hi - r.lo);
-    }
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+        auto put = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
+            if (hi > lo) slots[slot_base[si * p + j] + (x - s_base[si])] = static_cast<uint32_t>(hi - lo);
+        };
+        if (LONG) {
+            const RowRun r = row_run(col, e0, e1, x, s_c, p);
+            put(r.si, r.j, r.lo, r.hi);
+        } else {
+            short_row_runs(col, e0, e1, x, s_c, p, put);
+        }
+    });
 }
 
 // Block of slot q: the last block whose slot range starts at or before q.
@@ -229,12 +298,15 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
 }
 
 // Entries: row x's run in stripe j goes to the block of (stripe(x), j) at the
-// row's dense offset, as local column ids.  The lane of stripe j first
-// computes where entry e of its run lands (dst[j] + e); then the wave strides
-// the row's entries.
+// row's dense offset, as local column ids.  In long launches the lane of
+// stripe j first computes where entry e of its run lands (dst[j] + e), then
+// the wave strides the row's entries.
+template <bool LONG>
 __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row_off,
                                                  const int32_t *__restrict__ col, int32_t n,
-                                                 CutTable ct, const int32_t *__restrict__ blk_index,
+                                                 CutTable ct, const int32_t *__restrict__ list,
+                                                 const unsigned int *__restrict__ count,
+                                                 const int32_t *__restrict__ blk_index,
                                                  const int64_t *__restrict__ rptr_off,
                                                  const int64_t *__restrict__ col_off,
                                                  int32_t *__restrict__ arena) {
@@ -247,15 +319,20 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
-    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves) {
-        const int64_t e0 = row_off[x], e1 = row_off[x + 1];
-        if (e0 == e1) continue;
-        const RowRun r = row_run(col, e0, e1, static_cast<int32_t>(x), s_c, p);
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+        if (!LONG) {
+            short_row_runs(col, e0, e1, x, s_c, p, [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
+                if (hi <= lo) return;
+                const int32_t b = blk_index[si * p + j];
+                int32_t *dst = arena + col_off[b] + arena[rptr_off[b] + (x - s_base[si])];
+                for (int64_t e = lo; e < hi; ++e) *dst++ = col[e] - s_base[j];
+            });
+            return;
+        }
+        const RowRun r = row_run(col, e0, e1, x, s_c, p);
         if (r.hi > r.lo) {
             const int32_t b = blk_index[r.si * p + r.j];
-            const int64_t lx = x - s_base[r.si];
-            s_dst[w][lane] = col_off[b] + arena[rptr_off[b] + lx] - r.lo;
+            s_dst[w][lane] = col_off[b] + arena[rptr_off[b] + (x - s_base[r.si])] - r.lo;
         }
         wave_lds_sync();
         const int32_t j0 = r.j - lane;
@@ -265,17 +342,22 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
             arena[s_dst[w][j - j0] + e] = y - s_base[j];
         }
         wave_lds_sync();
-    }
+    });
 }
 
 // Reversed oriented graph: key = y << nb | x for every entry (x, y).
+template <bool LONG>
 __global__ __launch_bounds__(B) void k_rev_keys(const int64_t *__restrict__ row_off,
                                                 const int32_t *__restrict__ col, int32_t n, int nb,
+                                                const int32_t *__restrict__ list,
+                                                const unsigned int *__restrict__ count,
                                                 uint64_t *__restrict__ keys) {
-    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
-    for (int64_t x = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; x < n; x += nwaves)
-        for (int64_t e = row_off[x] + lane_id(); e < row_off[x + 1]; e += kWave)
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+        const int64_t first = LONG ? e0 + lane_id() : e0;
+        const int64_t step = LONG ? kWave : 1;
+        for (int64_t e = first; e < e1; e += step)
             keys[e] = (static_cast<uint64_t>(col[e]) << nb) | static_cast<uint64_t>(x);
+    });
 }
 
 __global__ void k_rev_counts_cols(const uint64_t *__restrict__ keys, int64_t m, int nb,
@@ -351,7 +433,14 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
     if (g->m > 0) {
         const size_t pp = static_cast<size_t>(p) * p;
         const unsigned lgrid = cap_grid(n);
-        const unsigned wgrid = cap_grid(static_cast<int64_t>(n) * 64);  // a wave per row
+        constexpr unsigned kLongGrid = 1024;  // workgroups of a long-row launch
+
+        // rows longer than kLongRow, of the forward and the reversed graph
+        DArray<int32_t> long_f(static_cast<size_t>(n) + 1, s), long_r(static_cast<size_t>(n) + 1, s);
+        DArray<unsigned int> nlong(2, s);
+        PGABB_HIP(hipMemsetAsync(nlong.get(), 0, 2 * sizeof(unsigned int), s));
+        k_collect_long<<<lgrid, B, 0, s>>>(g->row_off.get(), n, long_f.get(), nlong.get());
+        PGABB_HIP(hipGetLastError());
 
         // ---- reversed oriented graph (in-edges, sorted by (y, x)): its blocks
         // are the transposes of the forward blocks
@@ -359,7 +448,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         DArray<int32_t> rev_col(static_cast<size_t>(g->m), s);
         {
             DArray<uint64_t> k0(g->m, s), k1(g->m, s);
-            k_rev_keys<<<wgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, k0.get());
+            k_rev_keys<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, long_f.get(),
+                                                  nlong.get(), k0.get());
+            k_rev_keys<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, long_f.get(),
+                                                     nlong.get(), k0.get());
             PGABB_HIP(hipGetLastError());
             uint64_t *kk = k0.get();
             if (radix_sort_u64_bits(k0.get(), k1.get(), nullptr, nullptr, g->m, 0, 2 * g->nb, s)) kk = k1.get();
@@ -371,6 +463,8 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             PGABB_HIP(hipGetLastError());
             scan_exclusive_i64(wide.get(), rev_off.get(), n, rev_off.get() + n, s);
         }
+        k_collect_long<<<lgrid, B, 0, s>>>(rev_off.get(), n, long_r.get(), nlong.get() + 1);
+        PGABB_HIP(hipGetLastError());
 
         // ---- block sizes, forward (entries, row items) and reversed (column items)
         DArray<unsigned long long> dnnz(pp, s), dnnz_r(pp, s);
@@ -379,8 +473,14 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         PGABB_HIP(hipMemsetAsync(dnnz_r.get(), 0, pp * sizeof(unsigned long long), s));
         PGABB_HIP(hipMemsetAsync(ditems.get(), 0, pp * sizeof(unsigned int), s));
         PGABB_HIP(hipMemsetAsync(ditems_r.get(), 0, pp * sizeof(unsigned int), s));
-        k_block_sizes<<<wgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, dnnz.get(), ditems.get());
-        k_block_sizes<<<wgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, dnnz_r.get(), ditems_r.get());
+        k_block_sizes<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
+                                                  dnnz.get(), ditems.get());
+        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
+                                                     dnnz.get(), ditems.get());
+        k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(), nlong.get() + 1,
+                                                  dnnz_r.get(), ditems_r.get());
+        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(),
+                                                     nlong.get() + 1, dnnz_r.get(), ditems_r.get());
         PGABB_HIP(hipGetLastError());
         std::vector<unsigned long long> hnnz(pp);
         std::vector<unsigned int> hitems(pp), hitems_r(pp);
@@ -420,6 +520,8 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             const bool rev = pass == 1;
             const int64_t *off = rev ? rev_off.get() : g->row_off.get();
             const int32_t *cl = rev ? rev_col.get() : g->col.get();
+            const int32_t *lst = rev ? long_r.get() : long_f.get();
+            const unsigned int *nl = nlong.get() + (rev ? 1 : 0);
             std::vector<int64_t> sb_pp(pp, -1), sb_dense(nblk), rptr_off(nblk), items_off(nblk), col_off(nblk);
             std::vector<int32_t> width(nblk), bidx(pp, -1);
             int64_t nslots = 0;
@@ -449,7 +551,8 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
 
             DArray<uint32_t> slots(static_cast<size_t>(nslots) + 1, s), flags(static_cast<size_t>(nslots) + 1, s);
             PGABB_HIP(hipMemsetAsync(slots.get(), 0, (nslots + 1) * sizeof(uint32_t), s));
-            k_row_slot_counts<<<wgrid, B, 0, s>>>(off, cl, n, ct, d_sb_pp.get(), slots.get());
+            k_row_slot_counts<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp.get(), slots.get());
+            k_row_slot_counts<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp.get(), slots.get());
             PGABB_HIP(hipGetLastError());
             scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
             const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
@@ -461,7 +564,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_io.get(),
                                                           nblk, g->arena.get());
             PGABB_HIP(hipGetLastError());
-            k_fill_cols<<<wgrid, B, 0, s>>>(off, cl, n, ct, d_bidx.get(), d_ro.get(), d_co.get(), g->arena.get());
+            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx.get(), d_ro.get(), d_co.get(),
+                                                   g->arena.get());
+            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx.get(), d_ro.get(), d_co.get(),
+                                                      g->arena.get());
             PGABB_HIP(hipGetLastError());
             PGABB_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
         }

@@ -144,8 +144,11 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     const int orient = orient_of_option(opt);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     const int grab_opt = opt.rows_per_grab;
-    const int window_tasks = 64;
-    const uint64_t window_new_bytes = std::max<uint64_t>(cap / 4, 64ull << 20);
+    // A window is cut when its blocks would exceed the cap or when it would
+    // copy more than about an eighth of all block bytes: the first launch
+    // starts after a short copy, and later copies overlap earlier launches.
+    const int window_tasks = T;
+    const uint64_t window_new_bytes = std::max<uint64_t>(64ull << 20, std::min<uint64_t>(cap / 4, total_bytes / 8));
 
     std::vector<int64_t> chunk_dev(nblk, 0);  // in int32 words from pool start
     uint64_t h2d = 0;
