@@ -59,10 +59,11 @@ __global__ void k_compact(const uint64_t *__restrict__ keys, const uint32_t *__r
 }
 
 // Distinct keys are sorted by (lo, hi): the lo ends form runs, so each run
-// adds its length once; the hi ends are scattered and add one each.  The loop
+// adds its length once.  The hi ends are copied out, sorted, and counted the
+// same way (scattered atomics on hub vertices would serialise).  The loop
 // bound is uniform across a wave so every lane takes part in the ballots.
-__global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int nb,
-                          int32_t *__restrict__ deg) {
+__global__ void k_degrees_lo(const uint64_t *__restrict__ keys, int64_t m, int nb,
+                             int32_t *__restrict__ deg, uint32_t *__restrict__ his) {
     const uint64_t mask = (1ull << nb) - 1;
     const int64_t stride = int64_t(gridDim.x) * B;
     for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
@@ -70,7 +71,16 @@ __global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int nb,
         const bool valid = e < m;
         const uint64_t k = valid ? keys[e] : 0ull;
         add_run_lengths(valid, static_cast<int64_t>(k >> nb), deg);
-        if (valid) atomicAdd(&deg[k & mask], 1);
+        if (valid) his[e] = static_cast<uint32_t>(k & mask);
+    }
+}
+
+__global__ void k_degrees_hi(const uint32_t *__restrict__ his, int64_t m, int32_t *__restrict__ deg) {
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
+        const int64_t e = base + lane_id();
+        const bool valid = e < m;
+        add_run_lengths(valid, valid ? static_cast<int64_t>(his[e]) : 0, deg);
     }
 }
 
@@ -234,7 +244,12 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
 
         // 3: degrees
         if (mu > 0) {
-            k_degrees<<<cap_grid(mu), B, 0, s>>>(k0, mu, nb, deg.get());
+            DArray<uint32_t> his(static_cast<size_t>(mu), s), his_alt(static_cast<size_t>(mu), s);
+            k_degrees_lo<<<cap_grid(mu), B, 0, s>>>(k0, mu, nb, deg.get(), his.get());
+            PGABB_HIP(hipGetLastError());
+            uint32_t *hs = his.get();
+            if (radix_sort_u32(his.get(), his_alt.get(), nullptr, nullptr, mu, nb, s)) hs = his_alt.get();
+            k_degrees_hi<<<cap_grid(mu), B, 0, s>>>(hs, mu, deg.get());
             PGABB_HIP(hipGetLastError());
         }
         // 4: ranks

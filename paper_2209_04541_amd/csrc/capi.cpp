@@ -42,6 +42,27 @@ void fail(pgabb_status st, const char *fmt, ...) {
     throw Error{st, buf};
 }
 
+// The stream-ordered allocator's default pool returns freed memory to the
+// device at every synchronisation (release threshold 0), so each build would
+// map its scratch again.  Keep freed memory in the pool instead, once per
+// device.
+static void retain_pool_memory() {
+    static std::mutex mu;
+    static std::vector<char> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.size() <= static_cast<size_t>(dev)) done.resize(dev + 1, 0);
+    if (done[dev]) return;
+    done[dev] = 1;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+}
+
 void *dalloc(size_t bytes, hipStream_t s) {
     if (!bytes) return nullptr;
     pgabb_alloc_fn fa;
@@ -57,6 +78,7 @@ void *dalloc(size_t bytes, hipStream_t s) {
         if (!p) fail(PGABB_ENOMEM, "allocator hook failed for %zu bytes", bytes);
         return p;
     }
+    retain_pool_memory();
     hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess || !p) {
         (void)hipGetLastError();
