@@ -226,12 +226,14 @@ void pgabb_batch_destroy(pgabb_batch *b);
 
 /*
  * A request server with continuous batching: requests (one graph each) are
- * admitted while their estimated device bytes fit the budget, are built on a
- * build stream while earlier requests are being counted, and join the next
- * counting launch as soon as they are built.  Finished requests release
- * their memory and let queued ones in.
+ * admitted in arrival order while their estimated device bytes fit the
+ * budget, are built by builder threads on their own streams while earlier
+ * requests are being counted, and join the next counting launch as soon as
+ * they are built.  Finished requests release their memory and let queued
+ * ones in.
  *   device_budget_bytes : bound on the device bytes held by admitted requests
- *   opts                : counting options (NULL = defaults)
+ *   opts                : counting options (NULL = defaults); num_streams is
+ *                         the number of builders (0 = 2, at most 8)
  */
 typedef struct pgabb_server pgabb_server;
 

@@ -1,9 +1,10 @@
 // Request server with continuous batching.
 //
-// Two host threads drive two HIP streams:
-//  - the builder admits queued requests in arrival order while their
-//    estimated device bytes fit the budget, and builds each one (clean, rank,
-//    orient, partition) on the build stream;
+// Host threads drive HIP streams:
+//  - builders (options.num_streams of them, default 2, each with its own
+//    stream) admit queued requests in arrival order while their estimated
+//    device bytes fit the budget, and build each one (clean, rank, orient,
+//    partition);
 //  - the counter takes every request built so far, runs all their tasks in
 //    one counting launch on the count stream, returns each request's uint64
 //    count, frees its device memory and wakes the builder.
@@ -62,9 +63,11 @@ struct pgabb_server {
     uint64_t next_ticket = 1;
     int64_t in_flight = 0;  // admitted, not finished
     bool stop = false;
-    bool builder_done = false;
-    std::thread builder, counter;
-    hipStream_t build_stream = nullptr, count_stream = nullptr;
+    int builders_left = 0;  // builder threads still running
+    std::vector<std::thread> builders;
+    std::thread counter;
+    std::vector<hipStream_t> build_streams;
+    hipStream_t count_stream = nullptr;
     int device = 0;
     Clock::time_point t0 = Clock::now();
     uint64_t launches = 0;
@@ -79,7 +82,7 @@ uint64_t request_bytes(int32_t n, int64_t m) {
     return static_cast<uint64_t>(m) * 40 + static_cast<uint64_t>(n) * 48 + (4ull << 20);
 }
 
-static void builder_loop(pgabb_server *s) {
+static void builder_loop(pgabb_server *s, int idx) {
     (void)hipSetDevice(s->device);
     for (;;) {
         Request *r = nullptr;
@@ -110,7 +113,7 @@ static void builder_loop(pgabb_server *s) {
             pgabb_graph *g = new pgabb_graph();
             r->g = g;
             g->n = r->n;
-            g->stream = s->build_stream;
+            g->stream = s->build_streams[idx];
             const int32_t *hs = r->bsrc ? r->bsrc : r->src.data();
             const int32_t *hd = r->bdst ? r->bdst : r->dst.data();
             if (r->m > 0) {
@@ -138,7 +141,7 @@ static void builder_loop(pgabb_server *s) {
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        s->builder_done = true;
+        --s->builders_left;
     }
     s->cv_count.notify_one();
 }
@@ -166,8 +169,8 @@ static void counter_loop(pgabb_server *s) {
         std::vector<Request *> batch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_count.wait(lk, [&] { return !s->ready.empty() || s->builder_done; });
-            if (s->ready.empty() && s->builder_done) break;
+            s->cv_count.wait(lk, [&] { return !s->ready.empty() || s->builders_left == 0; });
+            if (s->ready.empty() && s->builders_left == 0) break;
             batch.assign(s->ready.begin(), s->ready.end());
             s->ready.clear();
         }
@@ -257,15 +260,19 @@ PGABB_API pgabb_status pgabb_server_create(uint64_t device_budget_bytes, const p
         s->budget = device_budget_bytes;
         if (opts) s->opt = *opts;
         PGABB_HIP(hipGetDevice(&s->device));
-        PGABB_HIP(hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking));
+        const int nb = s->opt.num_streams > 0 ? std::min(s->opt.num_streams, 8) : 2;
+        s->build_streams.assign(nb, nullptr);
+        for (auto &bs : s->build_streams) PGABB_HIP(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
         PGABB_HIP(hipStreamCreateWithFlags(&s->count_stream, hipStreamNonBlocking));
-        s->builder = std::thread(builder_loop, s);
+        s->builders_left = nb;
+        for (int q = 0; q < nb; ++q) s->builders.emplace_back(builder_loop, s, q);
         s->counter = std::thread(counter_loop, s);
         *out = s;
         return capture_status(Error{PGABB_OK, ""});
     } catch (const Error &e) {
         if (s) {
-            if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+            for (auto bs : s->build_streams)
+                if (bs) (void)hipStreamDestroy(bs);
             if (s->count_stream) (void)hipStreamDestroy(s->count_stream);
             delete s;
         }
@@ -347,9 +354,10 @@ PGABB_API void pgabb_server_destroy(pgabb_server *s) {
     }
     s->cv_build.notify_all();
     s->cv_count.notify_all();
-    if (s->builder.joinable()) s->builder.join();
+    for (auto &t : s->builders)
+        if (t.joinable()) t.join();
     if (s->counter.joinable()) s->counter.join();
-    (void)hipStreamDestroy(s->build_stream);
+    for (auto bs : s->build_streams) (void)hipStreamDestroy(bs);
     (void)hipStreamDestroy(s->count_stream);
     delete s;
 }
