@@ -67,9 +67,11 @@ def base_line(args, value, unit, ms, config, dtype="int32"):
 
 
 def roofline(W, m, kernel_ms, traffic_file):
-    # algorithmic bytes of one counting launch: every probed element of a row
-    # A_jk[v] (4 B each, W of them), every staged row and edge row once (4 B
-    # each per oriented edge) and the two row offsets of v (8 B per edge)
+    # algorithmic bytes of one counting launch: every entry of the walked
+    # partial lists (4 B each, W of them: A_jk[v] per edge (u, v) of A_ij for
+    # row walks, A_ik[u] for column walks), every staged list and edge list
+    # once (4 B each per oriented edge) and the two row offsets of the walked
+    # endpoint (8 B per oriented edge)
     alg = 4 * W + 16 * m
     achieved = alg / (kernel_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -112,7 +114,7 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
 
     m = infos[0]["m"]
-    W = infos[0]["probe_work"]
+    W = infos[0]["probe_work_col"] if infos[0]["walked_columns"] else infos[0]["probe_work"]
     launches = max(1, infos[0]["kernel_launches"])
     kernel_ms = float(np.mean([i["t_kernel_ms"] for i in infos])) / launches
     roof, alg = roofline(W, m, kernel_ms * launches, traffic_file)
@@ -132,16 +134,41 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
         "t_kernel_ms_per_launch": kernel_ms,
         "kernel_launches_per_step": launches,
         "algorithmic_bytes_per_step": alg,
-        "probe_work": W,
+        "probe_work": infos[0]["probe_work"],
+        "probe_work_col": infos[0]["probe_work_col"],
+        "walk": "columns" if infos[0]["walked_columns"] else "rows",
         "h2d_bytes_per_step": infos[0]["h2d_bytes"],
         "block_bytes": infos[0]["block_bytes"],
     })
+    out["copy_probe_gbs"] = copy_probe_gbs()
+    out["frac_of_copy_probe"] = roof["achieved"] / out["copy_probe_gbs"]
     if not args.no_cpu_baseline and cpu_sample is not None:
         cb, tri = cpu_sample()
         out["cpu_baseline"] = cb
         if tri is not None:
             out["parity"] = out["parity"] and tri == counts[0]
     return out
+
+
+def copy_probe_gbs(mib=1024, reps=5):
+    """Achievable HBM bandwidth on this GPU: the best of a few device copies
+    (read + write bytes over time), beside the 8 TB/s published peak."""
+    import torch
+    nbytes = mib << 20
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * nbytes / (best / 1e3) / 1e9
 
 
 def oracle_full_pass(n, s, d, m, label):

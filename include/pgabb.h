@@ -78,10 +78,15 @@ typedef enum pgabb_status {
                                     against) */
 #define PGABB_SERVER_BORROW 0x4u /* server only: submitted arrays are borrowed
                                     until the request finishes, not copied */
-#define PGABB_OPT_ROWS      0x8u /* walk each edge block by rows (stage the row
-                                    of A_ik, probe the rows of A_jk) instead of
-                                    the default by columns (stage the row of
-                                    A_jk, probe the rows of A_ik) */
+#define PGABB_OPT_ROWS      0x8u /* walk each edge block by rows: stage the row
+                                    of A_ik, probe the rows of A_jk */
+#define PGABB_OPT_COLS     0x10u /* walk each edge block by columns: stage the
+                                    row of A_jk, probe the rows of A_ik.  With
+                                    neither flag a graph count takes the walk
+                                    that reads fewer entries (probe_work or
+                                    probe_work_col of pgabb_graph_info, columns
+                                    on a tie) and the server walks columns;
+                                    both flags are EINVAL */
 
 typedef struct pgabb_tc_options {
     int32_t kernel;            /* PGABB_KERNEL_* */
@@ -106,7 +111,8 @@ typedef struct pgabb_graph_info {
     int32_t p;              /* grid size (0 before partitioning) */
     int64_t num_blocks;     /* non-empty blocks */
     int64_t num_tasks;      /* block-lists with three non-empty blocks */
-    uint64_t probe_work;    /* sum over oriented edges (u,v) of |N+(v)| */
+    uint64_t probe_work;    /* sum over oriented edges (u,v) of |N+(v)|: entries
+                               read by row walks (A_jk[v] per edge of A_ij) */
     uint64_t block_bytes;   /* bytes of all block storage */
     uint64_t h2d_bytes;     /* bytes copied host->device by the last count */
     double t_build_ms;      /* device time of the last build phase */
@@ -114,6 +120,11 @@ typedef struct pgabb_graph_info {
     double t_count_ms;      /* time of the last count (incl. transfers) */
     double t_kernel_ms;     /* device time of the last count's kernels */
     int64_t kernel_launches; /* counting launches of the last count */
+    uint64_t probe_work_col; /* entries read by column walks (A_ik[u] for every
+                                edge (u,v) of A_ij and k >= j) under the current
+                                cuts: sum over oriented edges (u,v) of
+                                |{w in N+(u): stripe(w) >= stripe(v)}| */
+    int64_t walked_columns;  /* 1 if the last count walked columns, 0 rows */
 } pgabb_graph_info;
 
 /*
@@ -272,13 +283,26 @@ void pgabb_server_destroy(pgabb_server *s);
 
 /*
  * Route the library's device allocations through caller functions (NULL,
- * NULL restores the default stream-ordered HIP allocator).  alloc returns
- * NULL on failure, which the library reports as ENOMEM.  Applies to
- * allocations made after the call.
+ * NULL restores the library's caching allocator).  alloc returns NULL on
+ * failure, which the library reports as ENOMEM.  Applies to allocations made
+ * after the call; memory the caching allocator handed out earlier still goes
+ * back to it when freed.
+ *
+ * The caching allocator keeps freed device blocks (and the pinned host
+ * blocks it stages small copies through) for reuse by size class: up to a
+ * quarter of device memory and 4 GiB of pinned memory stay cached, and a
+ * failed allocation first returns every cached block to HIP.
  */
 typedef void *(*pgabb_alloc_fn)(size_t bytes, void *hip_stream, void *ctx);
 typedef void (*pgabb_free_fn)(void *ptr, void *hip_stream, void *ctx);
 pgabb_status pgabb_set_allocator(pgabb_alloc_fn alloc, pgabb_free_fn free_fn, void *ctx);
+
+/*
+ * Return every cached free block (device memory of every device the library
+ * used, and pinned host memory) to HIP, after the work that last used each
+ * block has finished.  Blocks in use by live objects are not affected.
+ */
+pgabb_status pgabb_release_cached_memory(void);
 
 /* Library version string. */
 const char *pgabb_version(void);

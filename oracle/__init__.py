@@ -59,6 +59,8 @@ def _load():
         L.oracle_tc.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
         L.oracle_probe_work.restype = ctypes.c_uint64
         L.oracle_probe_work.argtypes = [ctypes.c_int32, vp, vp]
+        L.oracle_probe_work_col.restype = ctypes.c_uint64
+        L.oracle_probe_work_col.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -135,6 +137,18 @@ def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:
     if len(col) == 0:
         col = np.zeros(1, dtype=np.int32)
     return int(_load().oracle_probe_work(n, _p(row_off), _p(col)))
+
+
+def probe_work_col(n: int, row_off: np.ndarray, col: np.ndarray, cuts) -> int:
+    """W_col: over oriented edges (x, y), the out-neighbours w of x with
+    stripe(w) >= stripe(y) (the entries a walk of the first endpoint's
+    partial lists reads)."""
+    cuts = np.ascontiguousarray(cuts, dtype=np.int32)
+    row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    if len(col) == 0:
+        col = np.zeros(1, dtype=np.int32)
+    return int(_load().oracle_probe_work_col(n, _p(row_off), _p(col), len(cuts) - 1, _p(cuts)))
 
 
 def block_counts(n: int, row_off: np.ndarray, col: np.ndarray, cuts) -> np.ndarray:

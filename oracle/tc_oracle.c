@@ -252,7 +252,11 @@ uint64_t oracle_tc(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
 
 /* Probe work of the oriented formulation: W = sum over oriented edges (x, y)
  * of |N+(y)|, the number of list elements a merge streams from the second
- * list.  Used to state the algorithmic bytes of a count, not the count. */
+ * list.  Used to state the algorithmic bytes of a count, not the count.
+ * This is what a kernel reads when it walks the partial list of the second
+ * endpoint (A_jk[y]) for every edge: in block form the walked lists over all
+ * k >= j still cover N+(y) whole, since every out-neighbour of y ranks above
+ * y. */
 uint64_t oracle_probe_work(int32_t n, const int64_t *row_off, const int32_t *col)
 {
     uint64_t w = 0;
@@ -260,6 +264,25 @@ uint64_t oracle_probe_work(int32_t n, const int64_t *row_off, const int32_t *col
         for (int64_t t = row_off[x]; t < row_off[x + 1]; ++t) {
             int32_t y = col[t];
             w += (uint64_t)(row_off[y + 1] - row_off[y]);
+        }
+    return w;
+}
+
+/* Probe work when the kernel walks the first endpoint's partial lists
+ * instead: for every oriented edge (x, y) of block A_ij and every k >= j,
+ * the list A_ik[x] = N+(x) restricted to stripe k is read, so the work is
+ * W_col = sum over oriented edges (x, y) of |{w in N+(x) : stripe(w) >=
+ * stripe(y)}|, under the cut vector cuts[0..p].  For p = 1 it is the sum of
+ * |N+(x)|^2.  Evaluated here by the definition, pair by pair. */
+uint64_t oracle_probe_work_col(int32_t n, const int64_t *row_off, const int32_t *col,
+                               int32_t p, const int32_t *cuts)
+{
+    uint64_t w = 0;
+    for (int32_t x = 0; x < n; ++x)
+        for (int64_t t = row_off[x]; t < row_off[x + 1]; ++t) {
+            int32_t sy = stripe_of(col[t], p, cuts);
+            for (int64_t q = row_off[x]; q < row_off[x + 1]; ++q)
+                if (stripe_of(col[q], p, cuts) >= sy) ++w;
         }
     return w;
 }

@@ -28,6 +28,7 @@ CUT_NNZ, CUT_UNIFORM = 0, 1
 KERNEL_AUTO, KERNEL_HASH, KERNEL_BITMAP, KERNEL_SEARCH = 0, 1, 2, 3
 OPT_STREAM = 0x1
 OPT_ROWS = 0x8
+OPT_COLS = 0x10
 
 
 class PgabbError(RuntimeError):
@@ -51,7 +52,8 @@ class GraphInfo(ctypes.Structure):
                 ("block_bytes", ctypes.c_uint64), ("h2d_bytes", ctypes.c_uint64),
                 ("t_build_ms", ctypes.c_double), ("t_partition_ms", ctypes.c_double),
                 ("t_count_ms", ctypes.c_double), ("t_kernel_ms", ctypes.c_double),
-                ("kernel_launches", ctypes.c_int64)]
+                ("kernel_launches", ctypes.c_int64), ("probe_work_col", ctypes.c_uint64),
+                ("walked_columns", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +107,7 @@ def lib():
             "pgabb_server_stats": (st, [vp, ctypes.POINTER(u64)]),
             "pgabb_server_destroy": (None, [vp]),
             "pgabb_set_allocator": (st, [vp, vp, vp]),
+            "pgabb_release_cached_memory": (st, []),
             "pgabb_version": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -160,12 +163,16 @@ def _edges(src, dst):
 
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
-            waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=False):
+            waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=None):
+    """by_rows: True walks edge blocks by rows, False by columns, None lets
+    the library take the walk that reads fewer entries."""
     o = TcOptions()
     o.kernel = kernel
     o.num_streams = num_streams
     o.device_cap_bytes = device_cap_bytes
-    o.flags = (OPT_STREAM if stream_blocks else 0) | (OPT_ROWS if by_rows else 0)
+    o.flags = OPT_STREAM if stream_blocks else 0
+    if by_rows is not None:
+        o.flags |= OPT_ROWS if by_rows else OPT_COLS
     o.waves_per_block = waves_per_block
     o.rows_per_grab = rows_per_grab
     o.unroll = unroll
@@ -261,6 +268,11 @@ def tc_count(n, src, dst, p=1, **kw):
 
 def version():
     return lib().pgabb_version().decode()
+
+
+def release_cached_memory():
+    """Return the library's cached free device and pinned host blocks to HIP."""
+    _check(lib().pgabb_release_cached_memory())
 
 
 OPT_PER_GRAPH = 0x2

@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpgabb.so")
 
 SOURCES = ["prims.hip", "build.hip", "partition.hip", "count.hip", "streamer.hip",
-           "batch.hip", "server.cpp", "capi.cpp"]
+           "batch.hip", "server.cpp", "memory.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -28,12 +28,12 @@ constexpr uint64_t kSentinel = ~0ull;
 
 __global__ void k_make_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                             int64_t m, int32_t n, int nb, uint64_t *__restrict__ keys,
-                            int32_t *__restrict__ bad) {
+                            uint32_t *__restrict__ bad) {
     for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B) {
         const int32_t a = src[e], b = dst[e];
         uint64_t key = kSentinel;
         if (a < 0 || b < 0 || a >= n || b >= n) {
-            *bad = 1;
+            *bad = 1u;
         } else if (a != b) {
             const uint64_t lo = static_cast<uint32_t>(a < b ? a : b);
             const uint64_t hi = static_cast<uint32_t>(a < b ? b : a);
@@ -211,14 +211,13 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
 
     if (m > 0) {
         DArray<uint64_t> keys(static_cast<size_t>(m), s), alt(static_cast<size_t>(m), s);
-        DArray<int32_t> bad(1, s);
-        PGABB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
-        k_make_keys<<<cap_grid(m), B, 0, s>>>(src, dst, m, n, nb, keys.get(), bad.get());
+        // meta[0]: an endpoint lay out of range; meta[1]: distinct edges.
+        // Out-of-range edges get the sentinel key, so sorting and compacting
+        // them is harmless and one round trip reports both.
+        DArray<uint32_t> meta(2, s);
+        PGABB_HIP(hipMemsetAsync(meta.get(), 0, 2 * sizeof(uint32_t), s));
+        k_make_keys<<<cap_grid(m), B, 0, s>>>(src, dst, m, n, nb, keys.get(), meta.get());
         PGABB_HIP(hipGetLastError());
-        int32_t bad_h = 0;
-        PGABB_HIP(hipMemcpyAsync(&bad_h, bad.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipStreamSynchronize(s));
-        PGABB_REQUIRE(!bad_h, PGABB_EINVAL, "an edge endpoint lies outside [0, %d)", n);
 
         // 1-2: sort and dedupe.  Valid keys are below (n-1) << nb | (n-1) + 1;
         // the sentinel has every low 2nb bit set, so it sorts after them.
@@ -228,16 +227,16 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
         const uint64_t valid_limit = (static_cast<uint64_t>(n - 1) << nb) + static_cast<uint64_t>(n);
         {
             DArray<uint32_t> flag(static_cast<size_t>(m), s), pos(static_cast<size_t>(m), s);
-            DArray<uint32_t> total(1, s);
             k_first_of_run<<<cap_grid(m), B, 0, s>>>(k0, m, valid_limit, flag.get());
             PGABB_HIP(hipGetLastError());
-            scan_exclusive_u32(flag.get(), pos.get(), m, total.get(), s);
+            scan_exclusive_u32(flag.get(), pos.get(), m, meta.get() + 1, s);
             k_compact<<<cap_grid(m), B, 0, s>>>(k0, flag.get(), pos.get(), m, k1);
             PGABB_HIP(hipGetLastError());
-            uint32_t mu = 0;
-            PGABB_HIP(hipMemcpyAsync(&mu, total.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            Staged<uint32_t> mh(2, s);
+            PGABB_HIP(hipMemcpyAsync(mh.get(), meta.get(), mh.bytes(), hipMemcpyDeviceToHost, s));
             PGABB_HIP(hipStreamSynchronize(s));
-            g->m = mu;
+            PGABB_REQUIRE(!mh[0], PGABB_EINVAL, "an edge endpoint lies outside [0, %d)", n);
+            g->m = mh[1];
         }
         std::swap(k0, k1);  // k0: distinct keys [0, m')
         const int64_t mu = g->m;
@@ -295,12 +294,12 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
     if (g->m > 0)
         k_probe_work<<<std::min(cap_grid(g->m), 2048u), B, 0, s>>>(g->col.get(), g->m, g->outdeg.get(), st.get());
     PGABB_HIP(hipGetLastError());
-    Stats hs{};
-    PGABB_HIP(hipMemcpyAsync(&hs, st.get(), sizeof(Stats), hipMemcpyDeviceToHost, s));
+    Staged<Stats> hs(1, s);
+    PGABB_HIP(hipMemcpyAsync(hs.get(), st.get(), sizeof(Stats), hipMemcpyDeviceToHost, s));
     PGABB_HIP(hipStreamSynchronize(s));
-    g->max_out = hs.max_out;
-    g->isolated = static_cast<int64_t>(hs.isolated);
-    g->probe_work = hs.probe_work;
+    g->max_out = hs[0].max_out;
+    g->isolated = static_cast<int64_t>(hs[0].isolated);
+    g->probe_work = hs[0].probe_work;
 }
 
 }  // namespace pgabb

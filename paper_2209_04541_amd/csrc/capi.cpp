@@ -14,11 +14,6 @@ namespace {
 thread_local pgabb_status t_status = PGABB_OK;
 thread_local std::string t_message;
 
-std::mutex g_alloc_mu;
-pgabb_alloc_fn g_alloc = nullptr;
-pgabb_free_fn g_free = nullptr;
-void *g_alloc_ctx = nullptr;
-
 pgabb_status set_ok() {
     t_status = PGABB_OK;
     t_message.clear();
@@ -40,64 +35,6 @@ void fail(pgabb_status st, const char *fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     throw Error{st, buf};
-}
-
-// The stream-ordered allocator's default pool returns freed memory to the
-// device at every synchronisation (release threshold 0), so each build would
-// map its scratch again.  Keep freed memory in the pool instead, once per
-// device.
-static void retain_pool_memory() {
-    static std::mutex mu;
-    static std::vector<char> done;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    std::lock_guard<std::mutex> lk(mu);
-    if (done.size() <= static_cast<size_t>(dev)) done.resize(dev + 1, 0);
-    if (done[dev]) return;
-    done[dev] = 1;
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
-        uint64_t keep = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    (void)hipGetLastError();
-}
-
-void *dalloc(size_t bytes, hipStream_t s) {
-    if (!bytes) return nullptr;
-    pgabb_alloc_fn fa;
-    void *ctx;
-    {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
-        fa = g_alloc;
-        ctx = g_alloc_ctx;
-    }
-    void *p = nullptr;
-    if (fa) {
-        p = fa(bytes, s, ctx);
-        if (!p) fail(PGABB_ENOMEM, "allocator hook failed for %zu bytes", bytes);
-        return p;
-    }
-    retain_pool_memory();
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        fail(PGABB_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
-    }
-    return p;
-}
-
-void dfree(void *p, hipStream_t s) {
-    if (!p) return;
-    pgabb_free_fn ff;
-    void *ctx;
-    {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
-        ff = g_free;
-        ctx = g_alloc_ctx;
-    }
-    if (ff) ff(p, s, ctx);
-    else (void)hipFreeAsync(p, s);
 }
 
 StreamTimer::StreamTimer() {
@@ -154,11 +91,15 @@ PGABB_API const char *pgabb_version(void) { return "pgabb-mi355x 0.1 (gfx950)"; 
 PGABB_API pgabb_status pgabb_set_allocator(pgabb_alloc_fn alloc, pgabb_free_fn free_fn, void *ctx) {
     if ((alloc == nullptr) != (free_fn == nullptr))
         return set_err(PGABB_EINVAL, "alloc and free must both be set or both be NULL");
-    std::lock_guard<std::mutex> lk(g_alloc_mu);
-    g_alloc = alloc;
-    g_free = free_fn;
-    g_alloc_ctx = alloc ? ctx : nullptr;
+    set_allocator_hook(alloc, free_fn, alloc ? ctx : nullptr);
     return set_ok();
+}
+
+PGABB_API pgabb_status pgabb_release_cached_memory(void) {
+    PGABB_TRY
+    release_cached_memory();
+    return set_ok();
+    PGABB_CATCH
 }
 
 PGABB_API pgabb_status pgabb_graph_from_edges(int32_t n, int64_t m, const int32_t *src,
@@ -258,8 +199,10 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
     if (o.unroll && o.unroll != 1 && o.unroll != 2 && o.unroll != 4 && o.unroll != 8)
         return set_err(PGABB_EINVAL, "unroll must be 1, 2, 4 or 8");
     if (o.reserved) return set_err(PGABB_EINVAL, "reserved option field must be 0");
-    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW | PGABB_OPT_ROWS))
+    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW | PGABB_OPT_ROWS | PGABB_OPT_COLS))
         return set_err(PGABB_EINVAL, "unknown option flag bits");
+    if ((o.flags & PGABB_OPT_ROWS) && (o.flags & PGABB_OPT_COLS))
+        return set_err(PGABB_EINVAL, "PGABB_OPT_ROWS and PGABB_OPT_COLS together");
     PGABB_TRY
     *count = count_graph(g, o);
     return set_ok();
@@ -290,6 +233,8 @@ PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_in
     info->t_count_ms = g->t_count_ms;
     info->t_kernel_ms = g->t_kernel_ms;
     info->kernel_launches = g->kernel_launches;
+    info->probe_work_col = g->probe_work_col;
+    info->walked_columns = g->walked_columns;
     return set_ok();
 }
 

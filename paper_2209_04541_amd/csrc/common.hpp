@@ -38,11 +38,19 @@ struct Error {
 
 // --------------------------------------------------------- device memory
 
-// Allocation goes through the caller's hook when one is installed, else the
-// stream-ordered HIP allocator (hipMallocAsync keeps a pool, so repeated
-// builds do not pay for fresh device mappings).
+// Device allocation goes through the caller's hook when one is installed,
+// else through the library's caching allocator (memory.cpp): blocks are
+// reused by size class, and reuse on any stream is ordered after the
+// block's last free by an event.
 void *dalloc(size_t bytes, hipStream_t s);
-void dfree(void *p, hipStream_t s);
+void dfree(void *p, hipStream_t s) noexcept;
+// Pinned host blocks from a cache of the same kind; hfree(p, s) returns the
+// block once the work enqueued on s so far has finished with it.
+void *halloc(size_t bytes);
+void hfree(void *p, hipStream_t s) noexcept;
+void set_allocator_hook(pgabb_alloc_fn fa, pgabb_free_fn ff, void *ctx);
+void release_cached_memory();
+size_t cached_bytes(bool host);
 
 // Owning device array.  Freed on the stream it was allocated on.
 template <class T>
@@ -117,6 +125,31 @@ class PinnedArray {
   private:
     T *ptr_ = nullptr;
     size_t n_ = 0;
+};
+
+// Pinned host staging array from the host cache, for copies between host
+// tables and the device.  Released on the stream given at construction.
+template <class T>
+class Staged {
+  public:
+    Staged(size_t n, hipStream_t s) : n_(n), stream_(s) {
+        ptr_ = n ? static_cast<T *>(halloc(n * sizeof(T))) : nullptr;
+    }
+    ~Staged() {
+        if (ptr_) hfree(ptr_, stream_);
+    }
+    Staged(const Staged &) = delete;
+    Staged &operator=(const Staged &) = delete;
+    T *get() const { return ptr_; }
+    size_t size() const { return n_; }
+    size_t bytes() const { return n_ * sizeof(T); }
+    T &operator[](size_t i) { return ptr_[i]; }
+    const T &operator[](size_t i) const { return ptr_[i]; }
+
+  private:
+    T *ptr_ = nullptr;
+    size_t n_ = 0;
+    hipStream_t stream_ = nullptr;
 };
 
 // Event pair timing a region of one stream.

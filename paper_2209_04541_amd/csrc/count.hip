@@ -212,8 +212,12 @@ TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &
     return d;
 }
 
-int orient_of_option(const pgabb_tc_options &opt) {
-    return (opt.flags & PGABB_OPT_ROWS) ? kOrientRow : kOrientCol;
+int orient_of_option(const pgabb_tc_options &opt, const pgabb_graph *g) {
+    if (opt.flags & PGABB_OPT_ROWS) return kOrientRow;
+    if (opt.flags & PGABB_OPT_COLS) return kOrientCol;
+    // the walk that reads fewer entries of the probed lists
+    if (g && g->probe_work < g->probe_work_col) return kOrientRow;
+    return kOrientCol;
 }
 
 int64_t task_items(const pgabb_graph *g, const Task &t, int orient) {
@@ -223,10 +227,12 @@ int64_t task_items(const pgabb_graph *g, const Task &t, int orient) {
 
 static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     hipStream_t s = g->stream;
-    const int orient = orient_of_option(opt);
+    const int orient = orient_of_option(opt, g);
+    g->walked_columns = orient == kOrientCol;
     const int32_t T = static_cast<int32_t>(g->tasks.size());
-    std::vector<TaskDesc> td(T);
-    std::vector<int64_t> pre(static_cast<size_t>(T) + 1, 0);
+    Staged<TaskDesc> td(T, s);
+    Staged<int64_t> pre(static_cast<size_t>(T) + 1, s);
+    pre[0] = 0;
     int32_t max_wk = 0;
     for (int32_t t = 0; t < T; ++t) {
         td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
@@ -236,8 +242,8 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     DArray<TaskDesc> dtd(T, s);
     DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
     DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kQueueWords, s);  // counts, then queues
-    PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, s));
-    PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+    PGABB_HIP(hipMemcpyAsync(dtd.get(), td.get(), td.bytes(), hipMemcpyHostToDevice, s));
+    PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.get(), pre.bytes(), hipMemcpyHostToDevice, s));
     PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kQueueWords), s));
 
     CountArgs a;
@@ -257,9 +263,10 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     launch_tc_tasks(a, mode, words, waves, s, 0, opt.unroll);
     tm.stop(s);
 
-    g->task_counts.assign(T, 0);
-    PGABB_HIP(hipMemcpyAsync(g->task_counts.data(), dcnt.get(), sizeof(uint64_t) * T, hipMemcpyDeviceToHost, s));
+    Staged<unsigned long long> hcnt(T, s);
+    PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), hcnt.bytes(), hipMemcpyDeviceToHost, s));
     PGABB_HIP(hipStreamSynchronize(s));
+    g->task_counts.assign(hcnt.get(), hcnt.get() + T);
     g->t_kernel_ms = tm.ms();
     g->kernel_launches = 1;
     uint64_t total = 0;

@@ -27,7 +27,9 @@ struct CountArgs {
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 int mode_of_option(int32_t kernel);
 int default_grab(int64_t total_items);
-int orient_of_option(const pgabb_tc_options &opt);
+// kOrientRow or kOrientCol for a count of graph g (g = nullptr: a launch
+// over several graphs, which walks columns unless told otherwise).
+int orient_of_option(const pgabb_tc_options &opt, const pgabb_graph *g);
 int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
                      int grid_override, int unroll);

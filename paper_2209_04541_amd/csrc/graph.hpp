@@ -88,7 +88,9 @@ struct pgabb_graph {
     int nb = 1;     // bits per vertex id in packed keys
     int64_t isolated = 0;
     int32_t max_out = 0;
-    uint64_t probe_work = 0;
+    uint64_t probe_work = 0;      // sum over oriented edges (x, y) of |N+(y)|
+    uint64_t probe_work_col = 0;  // entries column walks read under the current cuts
+    int64_t walked_columns = 0;   // the last count walked columns
 
     pgabb::DArray<int64_t> row_off;  // n + 1
     pgabb::DArray<int32_t> col;      // m'

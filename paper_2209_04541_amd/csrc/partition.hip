@@ -138,32 +138,53 @@ __device__ __forceinline__ void short_row_runs(const int32_t *__restrict__ col, 
     f(si, j, lo, e1);
 }
 
+// Long rows are cut into chunks of at most kChunk entries, listed as
+// (row << 32 | chunk index), so that a hub row of the reversed graph spreads
+// over many waves.
+constexpr int64_t kChunk = 2048;
+
 __global__ void k_collect_long(const int64_t *__restrict__ row_off, int32_t n,
-                               int32_t *__restrict__ list, unsigned int *__restrict__ count) {
-    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B)
-        if (row_off[x + 1] - row_off[x] > kLongRow) list[atomicAdd(count, 1u)] = static_cast<int32_t>(x);
+                               int64_t *__restrict__ list, unsigned int *__restrict__ count) {
+    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+        const int64_t len = row_off[x + 1] - row_off[x];
+        if (len <= kLongRow) continue;
+        const unsigned int nch = static_cast<unsigned int>((len + kChunk - 1) / kChunk);
+        const unsigned int at = atomicAdd(count, nch);
+        for (unsigned int c = 0; c < nch; ++c) list[at + c] = (x << 32) | c;
+    }
+}
+
+// Capacity of the chunk list: every long row adds one chunk plus one per
+// kChunk entries.
+inline size_t long_list_capacity(int32_t n, int64_t m) {
+    return static_cast<size_t>(n) + static_cast<size_t>(m / kChunk) + 1;
 }
 
 // Row x of launch kind LONG: short launches take every row x < n a thread
-// at a time and skip long rows; long launches take the listed rows a wave at
-// a time.  Calls g(x, e0, e1) for each row taken, uniformly across a wave in
-// long launches.
+// at a time and skip long rows; long launches take the listed chunks a wave
+// at a time.  Calls g(x, e0, e1, c0, c1) with the row's entries [e0, e1)
+// and the entries [c0, c1) this call owns (the whole row for a short row),
+// uniformly across a wave in long launches.
 template <bool LONG, class G>
 __device__ __forceinline__ void for_rows(const int64_t *__restrict__ row_off, int32_t n,
-                                         const int32_t *__restrict__ list,
+                                         const int64_t *__restrict__ list,
                                          const unsigned int *__restrict__ count, G g) {
     if (!LONG) {
         for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
             const int64_t e0 = row_off[x], e1 = row_off[x + 1];
             if (e0 == e1 || e1 - e0 > kLongRow) continue;
-            g(static_cast<int32_t>(x), e0, e1);
+            g(static_cast<int32_t>(x), e0, e1, e0, e1);
         }
     } else {
         const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
         const int64_t nl = *count;
         for (int64_t i = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; i < nl; i += nwaves) {
-            const int32_t x = list[i];
-            g(x, row_off[x], row_off[x + 1]);
+            const int64_t v = list[i];
+            const int32_t x = static_cast<int32_t>(v >> 32);
+            const int64_t e0 = row_off[x], e1 = row_off[x + 1];
+            const int64_t c0 = e0 + (v & 0xffffffffll) * kChunk;
+            const int64_t c1 = c0 + kChunk < e1 ? c0 + kChunk : e1;
+            g(x, e0, e1, c0, c1);
         }
     }
 }
@@ -174,13 +195,15 @@ __device__ __forceinline__ void for_rows(const int64_t *__restrict__ row_off, in
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ row_off,
                                                    const int32_t *__restrict__ col, int32_t n,
-                                                   CutTable ct, const int32_t *__restrict__ list,
+                                                   CutTable ct, const int64_t *__restrict__ list,
                                                    const unsigned int *__restrict__ count,
                                                    unsigned long long *__restrict__ nnz,
-                                                   unsigned int *__restrict__ items) {
+                                                   unsigned int *__restrict__ items,
+                                                   unsigned long long *__restrict__ walk) {
     __shared__ unsigned int s_nnz[kMaxP * kMaxP];
     __shared__ unsigned int s_items[kMaxP * kMaxP];
     __shared__ int32_t s_c[kMaxP + 1];
+    __shared__ unsigned long long s_walk;
     const int p = ct.p;
     const int pp = p * p;
     for (int q = threadIdx.x; q < pp; q += B) {
@@ -188,22 +211,35 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
         s_items[q] = 0;
     }
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
+    if (threadIdx.x == 0) s_walk = 0;
     __syncthreads();
+    // Walked entries when the kernel reads A_ik[x] for every entry (x, y) of
+    // A_ij and every k >= j: the run of stripe j has (hi - lo) entries, each
+    // walking the (e1 - lo) entries of stripes j and above.
+    unsigned long long my_walk = 0;
+    int64_t row_end = 0;
     auto add = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
         const int64_t cnt = hi - lo;
         if (cnt > 0) {
             atomicAdd(&s_nnz[si * p + j], static_cast<unsigned int>(cnt));
             atomicAdd(&s_items[si * p + j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
+            my_walk += static_cast<unsigned long long>(cnt) * static_cast<unsigned long long>(row_end - lo);
         }
     };
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
+        row_end = e1;
         if (LONG) {
+            if (c0 != e0) return;  // per-row counts: the first chunk only
             const RowRun r = row_run(col, e0, e1, x, s_c, p);
             add(r.si, r.j, r.lo, r.hi);
         } else {
             short_row_runs(col, e0, e1, x, s_c, p, add);
         }
     });
+    if (walk) {
+        my_walk = wave_sum(my_walk);
+        if (lane_id() == 0 && my_walk) atomicAdd(&s_walk, my_walk);
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < pp; q += B) {
         if (s_nnz[q]) {
@@ -211,6 +247,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
             atomicAdd(&items[q], s_items[q]);
         }
     }
+    if (walk && threadIdx.x == 0 && s_walk) atomicAdd(walk, s_walk);
 }
 
 // Per-row entry counts of every block the row touches, written at the row's
@@ -219,7 +256,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict__ row_off,
                                                        const int32_t *__restrict__ col, int32_t n,
-                                                       CutTable ct, const int32_t *__restrict__ list,
+                                                       CutTable ct, const int64_t *__restrict__ list,
                                                        const unsigned int *__restrict__ count,
                                                        const int64_t *__restrict__ slot_base,
                                                        uint32_t *__restrict__ slots) {
@@ -229,11 +266,12 @@ __global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
     for (int q = threadIdx.x; q < p; q += B) s_base[q] = ct.base[q];
     __syncthreads();
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
         auto put = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
             if (hi > lo) slots[slot_base[si * p + j] + (x - s_base[si])] = static_cast<uint32_t>(hi - lo);
         };
         if (LONG) {
+            if (c0 != e0) return;  // per-row counts: the first chunk only
             const RowRun r = row_run(col, e0, e1, x, s_c, p);
             put(r.si, r.j, r.lo, r.hi);
         } else {
@@ -304,7 +342,7 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row_off,
                                                  const int32_t *__restrict__ col, int32_t n,
-                                                 CutTable ct, const int32_t *__restrict__ list,
+                                                 CutTable ct, const int64_t *__restrict__ list,
                                                  const unsigned int *__restrict__ count,
                                                  const int32_t *__restrict__ blk_index,
                                                  const int64_t *__restrict__ rptr_off,
@@ -319,7 +357,7 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t c1) {
         if (!LONG) {
             short_row_runs(col, e0, e1, x, s_c, p, [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
                 if (hi <= lo) return;
@@ -336,7 +374,7 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
         }
         wave_lds_sync();
         const int32_t j0 = r.j - lane;
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+        for (int64_t e = c0 + lane; e < c1; e += kWave) {
             const int32_t y = col[e];
             const int32_t j = stripe_lds(y, s_c, p);
             arena[s_dst[w][j - j0] + e] = y - s_base[j];
@@ -349,13 +387,13 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_rev_keys(const int64_t *__restrict__ row_off,
                                                 const int32_t *__restrict__ col, int32_t n, int nb,
-                                                const int32_t *__restrict__ list,
+                                                const int64_t *__restrict__ list,
                                                 const unsigned int *__restrict__ count,
                                                 uint64_t *__restrict__ keys) {
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1) {
-        const int64_t first = LONG ? e0 + lane_id() : e0;
+    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t, int64_t, int64_t c0, int64_t c1) {
+        const int64_t first = LONG ? c0 + lane_id() : c0;
         const int64_t step = LONG ? kWave : 1;
-        for (int64_t e = first; e < e1; e += step)
+        for (int64_t e = first; e < c1; e += step)
             keys[e] = (static_cast<uint64_t>(col[e]) << nb) | static_cast<uint64_t>(x);
     });
 }
@@ -401,8 +439,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         DArray<int32_t> dc(static_cast<size_t>(p) + 1, s);
         k_nnz_cuts<<<grid_for(p + 1, B), B, 0, s>>>(g->row_off.get(), n, g->m, p, dc.get());
         PGABB_HIP(hipGetLastError());
-        PGABB_HIP(hipMemcpyAsync(cuts.data(), dc.get(), sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s));
+        Staged<int32_t> hc(static_cast<size_t>(p) + 1, s);
+        PGABB_HIP(hipMemcpyAsync(hc.get(), dc.get(), hc.bytes(), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        std::copy(hc.get(), hc.get() + p + 1, cuts.begin());
     }
 
     // Ranks below `lowest` own no edge (isolated vertices rank first under the
@@ -429,6 +469,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
     g->cuts = cuts;
     g->base = base;
     g->arena_words = 0;
+    g->probe_work_col = 0;
 
     if (g->m > 0) {
         const size_t pp = static_cast<size_t>(p) * p;
@@ -436,7 +477,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         constexpr unsigned kLongGrid = 1024;  // workgroups of a long-row launch
 
         // rows longer than kLongRow, of the forward and the reversed graph
-        DArray<int32_t> long_f(static_cast<size_t>(n) + 1, s), long_r(static_cast<size_t>(n) + 1, s);
+        DArray<int64_t> long_f(long_list_capacity(n, g->m), s), long_r(long_list_capacity(n, g->m), s);
         DArray<unsigned int> nlong(2, s);
         PGABB_HIP(hipMemsetAsync(nlong.get(), 0, 2 * sizeof(unsigned int), s));
         k_collect_long<<<lgrid, B, 0, s>>>(g->row_off.get(), n, long_f.get(), nlong.get());
@@ -453,8 +494,10 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             k_rev_keys<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, long_f.get(),
                                                      nlong.get(), k0.get());
             PGABB_HIP(hipGetLastError());
+            // keys come in CSR order, already ascending in x within each y, so
+            // a stable sort on the y bits alone orders them by (y, x)
             uint64_t *kk = k0.get();
-            if (radix_sort_u64_bits(k0.get(), k1.get(), nullptr, nullptr, g->m, 0, 2 * g->nb, s)) kk = k1.get();
+            if (radix_sort_u64_bits(k0.get(), k1.get(), nullptr, nullptr, g->m, g->nb, 2 * g->nb, s)) kk = k1.get();
             DArray<int32_t> cnt(static_cast<size_t>(n), s);
             PGABB_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * n, s));
             k_rev_counts_cols<<<cap_grid(g->m), B, 0, s>>>(kk, g->m, g->nb, cnt.get(), rev_col.get());
@@ -467,27 +510,29 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         PGABB_HIP(hipGetLastError());
 
         // ---- block sizes, forward (entries, row items) and reversed (column items)
-        DArray<unsigned long long> dnnz(pp, s), dnnz_r(pp, s);
-        DArray<unsigned int> ditems(pp, s), ditems_r(pp, s);
-        PGABB_HIP(hipMemsetAsync(dnnz.get(), 0, pp * sizeof(unsigned long long), s));
-        PGABB_HIP(hipMemsetAsync(dnnz_r.get(), 0, pp * sizeof(unsigned long long), s));
-        PGABB_HIP(hipMemsetAsync(ditems.get(), 0, pp * sizeof(unsigned int), s));
-        PGABB_HIP(hipMemsetAsync(ditems_r.get(), 0, pp * sizeof(unsigned int), s));
+        // one buffer, one clear, one copy back: nnz[pp] nnz_r[pp] (u64) |
+        // items[pp] items_r[pp] (u32) | walked entries of column walks (u64)
+        const size_t nsz = 3 * pp + 1;
+        DArray<unsigned long long> dsz(nsz, s);
+        PGABB_HIP(hipMemsetAsync(dsz.get(), 0, nsz * sizeof(unsigned long long), s));
+        unsigned long long *dnnz = dsz.get(), *dnnz_r = dnnz + pp, *dwalk = dsz.get() + 3 * pp;
+        unsigned int *ditems = reinterpret_cast<unsigned int *>(dnnz_r + pp), *ditems_r = ditems + pp;
         k_block_sizes<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
-                                                  dnnz.get(), ditems.get());
+                                                  dnnz, ditems, dwalk);
         k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
-                                                     dnnz.get(), ditems.get());
+                                                     dnnz, ditems, dwalk);
         k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(), nlong.get() + 1,
-                                                  dnnz_r.get(), ditems_r.get());
+                                                  dnnz_r, ditems_r, nullptr);
         k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(),
-                                                     nlong.get() + 1, dnnz_r.get(), ditems_r.get());
+                                                     nlong.get() + 1, dnnz_r, ditems_r, nullptr);
         PGABB_HIP(hipGetLastError());
-        std::vector<unsigned long long> hnnz(pp);
-        std::vector<unsigned int> hitems(pp), hitems_r(pp);
-        PGABB_HIP(hipMemcpyAsync(hnnz.data(), dnnz.get(), pp * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipMemcpyAsync(hitems.data(), ditems.get(), pp * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipMemcpyAsync(hitems_r.data(), ditems_r.get(), pp * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        Staged<unsigned long long> hsz(nsz, s);
+        PGABB_HIP(hipMemcpyAsync(hsz.get(), dsz.get(), hsz.bytes(), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        const unsigned long long *hnnz = hsz.get();
+        const unsigned int *hitems = reinterpret_cast<const unsigned int *>(hsz.get() + 2 * pp);
+        const unsigned int *hitems_r = hitems + pp;
+        g->probe_work_col = hsz[3 * pp];
 
         // ---- block table (row-major block order) and chunk layout
         for (int32_t i = 0; i < p; ++i) {
@@ -516,14 +561,24 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         // Both passes run the same machinery: per-row run counts at dense
         // slots, one scan (row offsets), per-row item counts, one scan (item
         // lists), then the entries.  The reversed pass fills the transposes.
+        // Per-block tables of each pass travel in one pinned host buffer
+        // (int64 tables, then int32 tables) and one copy.
         for (int pass = 0; pass < 2; ++pass) {
             const bool rev = pass == 1;
             const int64_t *off = rev ? rev_off.get() : g->row_off.get();
             const int32_t *cl = rev ? rev_col.get() : g->col.get();
-            const int32_t *lst = rev ? long_r.get() : long_f.get();
+            const int64_t *lst = rev ? long_r.get() : long_f.get();
             const unsigned int *nl = nlong.get() + (rev ? 1 : 0);
-            std::vector<int64_t> sb_pp(pp, -1), sb_dense(nblk), rptr_off(nblk), items_off(nblk), col_off(nblk);
-            std::vector<int32_t> width(nblk), bidx(pp, -1);
+            // layout: sb_pp[pp] sb_dense[nblk] rptr_off[nblk] items_off[nblk]
+            // col_off[nblk] | width[nblk] bidx[pp] (int32)
+            const size_t n64 = pp + 4 * static_cast<size_t>(nblk);
+            const size_t n32 = static_cast<size_t>(nblk) + pp;
+            Staged<int64_t> tab(n64 + (n32 + 1) / 2, s);
+            int64_t *sb_pp = tab.get(), *sb_dense = sb_pp + pp, *rptr_off = sb_dense + nblk;
+            int64_t *items_off = rptr_off + nblk, *col_off = items_off + nblk;
+            int32_t *width = reinterpret_cast<int32_t *>(tab.get() + n64), *bidx = width + nblk;
+            std::fill(sb_pp, sb_pp + pp, int64_t(-1));
+            std::fill(bidx, bidx + pp, -1);
             int64_t nslots = 0;
             for (int32_t b = 0; b < nblk; ++b) {
                 const BlockInfo &bi = g->blocks[b];
@@ -539,37 +594,32 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 col_off[b] = rev ? bi.off_crow() : bi.off_col();
                 nslots += static_cast<int64_t>(width[b]) + 1;
             }
-            DArray<int64_t> d_sb_pp(pp, s), d_sb(nblk, s), d_ro(nblk, s), d_io(nblk, s), d_co(nblk, s);
-            DArray<int32_t> d_w(nblk, s), d_bidx(pp, s);
-            PGABB_HIP(hipMemcpyAsync(d_sb_pp.get(), sb_pp.data(), pp * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_sb.get(), sb_dense.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_ro.get(), rptr_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_io.get(), items_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_co.get(), col_off.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_w.get(), width.data(), nblk * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            PGABB_HIP(hipMemcpyAsync(d_bidx.get(), bidx.data(), pp * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DArray<int64_t> dtab(tab.size(), s);
+            PGABB_HIP(hipMemcpyAsync(dtab.get(), tab.get(), tab.bytes(), hipMemcpyHostToDevice, s));
+            const int64_t *d_sb_pp = dtab.get(), *d_sb = d_sb_pp + pp, *d_ro = d_sb + nblk, *d_io = d_ro + nblk;
+            const int64_t *d_co = d_io + nblk;
+            const int32_t *d_w = reinterpret_cast<const int32_t *>(dtab.get() + n64), *d_bidx = d_w + nblk;
 
             DArray<uint32_t> slots(static_cast<size_t>(nslots) + 1, s), flags(static_cast<size_t>(nslots) + 1, s);
             PGABB_HIP(hipMemsetAsync(slots.get(), 0, (nslots + 1) * sizeof(uint32_t), s));
-            k_row_slot_counts<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp.get(), slots.get());
-            k_row_slot_counts<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp.get(), slots.get());
+            k_row_slot_counts<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp, slots.get());
+            k_row_slot_counts<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp, slots.get());
             PGABB_HIP(hipGetLastError());
             scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
             const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
-            k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb.get(), d_ro.get(), d_w.get(), nblk,
+            k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb, d_ro, d_w, nblk,
                                                          g->arena.get(), flags.get());
             PGABB_HIP(hipGetLastError());
             PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
             scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // slots now item positions
-            k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb.get(), d_io.get(),
+            k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb, d_io,
                                                           nblk, g->arena.get());
             PGABB_HIP(hipGetLastError());
-            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx.get(), d_ro.get(), d_co.get(),
+            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx, d_ro, d_co,
                                                    g->arena.get());
-            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx.get(), d_ro.get(), d_co.get(),
+            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx, d_ro, d_co,
                                                       g->arena.get());
             PGABB_HIP(hipGetLastError());
-            PGABB_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
         }
 
         // ---- tasks: i <= j <= k with three non-empty blocks

@@ -12,6 +12,7 @@
 // memory frees up, are built while the previous launch runs, and join the
 // next launch: their device work overlaps, and each result is the same as
 // when counted alone (integer sums do not depend on the batch).
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -189,7 +190,7 @@ static void counter_loop(pgabb_server *s) {
             pgabb_graph *g = r->g;
             for (const Task &t : g->tasks) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
-                pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt)));
+                pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt, nullptr)));
                 max_wk = std::max(max_wk, td.back().width_k);
             }
             max_out = std::max(max_out, g->max_out);
@@ -210,8 +211,13 @@ static void counter_loop(pgabb_server *s) {
             if (T > 0) {
                 if (dtd.size() < static_cast<size_t>(T)) dtd.reset(std::max<size_t>(2 * T, 256), cs);
                 if (dpre.size() < static_cast<size_t>(T) + 1) dpre.reset(std::max<size_t>(2 * T + 2, 256), cs);
-                PGABB_HIP(hipMemcpyAsync(dtd.get(), td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, cs));
-                PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, cs));
+                // staged through pinned blocks so the copies do not stall the host
+                Staged<TaskDesc> htd(T, cs);
+                Staged<int64_t> hpre(static_cast<size_t>(T) + 1, cs);
+                std::copy(td.begin(), td.end(), htd.get());
+                std::copy(pre.begin(), pre.end(), hpre.get());
+                PGABB_HIP(hipMemcpyAsync(dtd.get(), htd.get(), htd.bytes(), hipMemcpyHostToDevice, cs));
+                PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, cs));
             }
             PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + kQueueWords), cs));
             if (T > 0) {
@@ -220,7 +226,7 @@ static void counter_loop(pgabb_server *s) {
                 a.item_pre = dpre.get();
                 a.ntasks = T;
                 a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back());
-                a.orient = orient_of_option(s->opt);
+                a.orient = orient_of_option(s->opt, nullptr);
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;

@@ -141,7 +141,8 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     for (int32_t t = 0; t < T; ++t) max_wk = std::max(max_wk, g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k]);
     const int mode = mode_of_option(opt.kernel);
     const int words = choose_lds_words(mode, g->max_out, max_wk);
-    const int orient = orient_of_option(opt);
+    const int orient = orient_of_option(opt, g);
+    g->walked_columns = orient == kOrientCol;
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     const int grab_opt = opt.rows_per_grab;
     // A window is cut when its blocks would exceed the cap or when it would

@@ -32,7 +32,11 @@ def record(n, s, d):
     t = oracle.count_csr(n, row_off, col)
     t2 = time.time()
     od = np.diff(row_off)
+    extra = {}
+    if len(col) < 10 ** 8:  # the pair-by-pair definition is quadratic per row
+        extra["probe_work_col_p1"] = oracle.probe_work_col(n, row_off, col, [0, n])
     return {
+        **extra,
         "n": int(n),
         "m_input": int(len(s)),
         "m": int(len(keys)),

@@ -84,7 +84,9 @@ def test_task_counts_equal_oracle_blocks(p):
             total = g.count()
             cuts = g.cuts()
             ijk, cnt = g.task_counts()
+            walk = g.info()["probe_work_col"]
         B = oracle.block_counts(n, row_off, col, cuts)
+        assert walk == oracle.probe_work_col(n, row_off, col, cuts), (p, mode)
         got = np.zeros_like(B)
         for (i, j, k), c in zip(ijk, cnt):
             got[i, j, k] += c
@@ -101,6 +103,7 @@ def test_explicit_cuts_with_empty_stripes():
         g.partition(len(cuts) - 1, cuts=cuts)
         assert g.count() == want
         ijk, cnt = g.task_counts()
+        assert g.info()["probe_work_col"] == oracle.probe_work_col(n, row_off, col, cuts)
     B = oracle.block_counts(n, row_off, col, cuts)
     got = np.zeros_like(B)
     for (i, j, k), c in zip(ijk, cnt):
@@ -129,6 +132,7 @@ def test_orientations_task_counts(by_rows):
     with P.Graph(n, s, d) as g:
         g.partition(6)
         total = g.count(by_rows=by_rows)
+        assert g.info()["walked_columns"] == (0 if by_rows else 1)
         cuts = g.cuts()
         ijk, cnt = g.task_counts()
     B = oracle.block_counts(n, row_off, col, cuts)
@@ -218,6 +222,9 @@ def test_plain_workload():
         assert g.count() == gold["triangles"]
         info = g.info()
     assert info["m"] == gold["m"] and info["probe_work"] == gold["probe_work"]
+    assert info["probe_work_col"] == gold["probe_work_col_p1"]
+    # row walks read fewer entries on this graph, so the default takes them
+    assert gold["probe_work"] < gold["probe_work_col_p1"] and info["walked_columns"] == 0
 
 
 @pytest.mark.parametrize("p", [1, 8])
@@ -232,3 +239,26 @@ def test_block_workload(p):
         info = g.info()
     for k in ("m", "isolated", "max_out_degree", "probe_work"):
         assert info[k] == gold[k], k
+    if p == 1:  # one stripe: the sum of squared out-degrees
+        assert info["probe_work_col"] == gold["probe_work_col_p1"]
+    assert info["walked_columns"] == (1 if info["probe_work_col"] <= info["probe_work"] else 0)
+
+
+def test_cached_blocks_across_streams():
+    """Freed blocks are reused by later graphs on other streams (the reuse
+    waits for the free's event); releasing the cache between graphs changes
+    nothing."""
+    import torch
+    n, s, d = gen.rmat(13, 16, gen.seed(98, 1))
+    want = oracle.tc(n, s, d)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for rep in range(6):
+        with torch.cuda.stream(streams[rep % 3]):
+            ds = torch.from_numpy(s).cuda()
+            dd = torch.from_numpy(d).cuda()
+            with P.Graph(n, ds, dd) as g:
+                g.partition(1 + rep)
+                assert g.count() == want, rep
+        if rep == 3:
+            P.release_cached_memory()
+    torch.cuda.synchronize()

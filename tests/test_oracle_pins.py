@@ -155,6 +155,26 @@ def test_probe_work_against_numpy():
     assert oracle.probe_work(n, row_off, col) == int(od[col].sum())
 
 
+def test_probe_work_col_pins():
+    """W_col: p = 1 gives the sum of squared out-degrees; one stripe per
+    vertex gives sum d(d+1)/2 (the i-th smallest out-neighbour of x has
+    d - i entries at or above it); random cuts against a numpy count."""
+    n, s, d = gen.rmat(10, 8, gen.seed(91, 3))
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    od = np.diff(row_off).astype(np.int64)
+    assert oracle.probe_work_col(n, row_off, col, [0, n]) == int((od * od).sum())
+    assert oracle.probe_work_col(n, row_off, col, np.arange(n + 1)) == int((od * (od + 1) // 2).sum())
+    rng = np.random.default_rng(5)
+    for p in (2, 3, 7):
+        cuts = np.concatenate([[0], np.sort(rng.integers(0, n + 1, p - 1)), [n]])
+        stripe = np.minimum(np.searchsorted(cuts, np.arange(n), side="right") - 1, p - 1)
+        want = 0
+        for x in range(n):
+            st = stripe[col[row_off[x]:row_off[x + 1]]]
+            want += int((st[None, :] >= st[:, None]).sum())
+        assert oracle.probe_work_col(n, row_off, col, cuts) == want, p
+
+
 def _triangles_by_stripe(n, s, d, rk, cuts):
     """Enumerate triangles with networkx and bin them by the stripes of their
     ranked vertices."""
