@@ -95,8 +95,9 @@ typedef struct pgabb_tc_options {
     uint32_t flags;            /* PGABB_OPT_* */
     int32_t waves_per_block;   /* 2, 4 or 8 waves per workgroup (0 = default) */
     int32_t rows_per_grab;     /* rows a wave takes per work-counter update (0 = default) */
-    int32_t unroll;            /* 64-element row chunks each wave loads ahead of
-                                  probing: 1, 2, 4 or 8 (0 = default) */
+    int32_t unroll;            /* 64-element chunks of walked lists per load
+                                  batch (the next batch loads while one is
+                                  probed): 1, 2, 4 or 8 (0 = 2) */
     int32_t reserved;          /* must be 0 */
 } pgabb_tc_options;
 

@@ -57,6 +57,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
             int32_t t = __builtin_amdgcn_readfirstlane(lo);
             int64_t t_begin = a.item_pre[t], t_end = a.item_pre[t + 1];
             uint32_t cnt = 0;
+            // item g's record (x, b, e): row (or column) x of A_ij and its
+            // entries [b, e); the next item's record of the same task is
+            // loaded one item ahead
+            auto record = [&](const TaskDesc &T, int64_t g) {
+                const int32_t *items = ORIENT == kOrientRow ? T.ij.items : T.ij.citems;
+                const int64_t n = ORIENT == kOrientRow ? T.ij.nitems : T.ij.ncitems;
+                return as_global(items) + kItemWords * (n - 1 - (g - t_begin));
+            };
+            int32_t nx = 0, nb = 0, ne = 0;
+            bool have_next = false;
             for (int64_t g = g0; g < g1; ++g) {
                 while (g >= t_end) {
                     const unsigned long long sum = wave_sum(static_cast<unsigned long long>(cnt));
@@ -65,25 +75,33 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                     ++t;
                     t_begin = t_end;
                     t_end = a.item_pre[t + 1];
+                    have_next = false;
                 }
                 const TaskDesc &T = a.tasks[t];
-                if (ORIENT == kOrientRow) {
-                    const int64_t it = T.ij.nitems - 1 - (g - t_begin);
-                    const int32_t u = T.ij.items[2 * it];
-                    const int32_t piece = T.ij.items[2 * it + 1];
-                    const int32_t rb = T.ij.rptr[u] + piece * kSplitV;
-                    const int32_t re = min(rb + kSplitV, T.ij.rptr[u + 1]);
-                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.ik.rptr, T.ik.col, u, T.jk.rptr, T.jk.col,
-                                                            T.ij.col, rb, re, T.width_k, lds);
+                int32_t x, b, e;
+                if (have_next) {
+                    x = nx;
+                    b = nb;
+                    e = ne;
                 } else {
-                    const int64_t it = T.ij.ncitems - 1 - (g - t_begin);
-                    const int32_t v = T.ij.citems[2 * it];
-                    const int32_t piece = T.ij.citems[2 * it + 1];
-                    const int32_t cb = T.ij.cptr[v] + piece * kSplitV;
-                    const int32_t ce = min(cb + kSplitV, T.ij.cptr[v + 1]);
-                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.jk.rptr, T.jk.col, v, T.ik.rptr, T.ik.col,
-                                                            T.ij.crow, cb, ce, T.width_k, lds);
+                    const gptr<int32_t> r = record(T, g);
+                    x = r[0];
+                    b = r[1];
+                    e = r[2];
                 }
+                have_next = g + 1 < g1 && g + 1 < t_end;
+                if (have_next) {
+                    const gptr<int32_t> r = record(T, g + 1);
+                    nx = r[0];
+                    nb = r[1];
+                    ne = r[2];
+                }
+                if (ORIENT == kOrientRow)
+                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.ik.rptr, T.ik.col, x, T.jk.rptr, T.jk.col,
+                                                            T.ij.col, b, e, T.width_k, lds);
+                else
+                    cnt += tc_item<MODE, LDS_WORDS, UNROLL>(T.jk.rptr, T.jk.col, x, T.ik.rptr, T.ik.col,
+                                                            T.ij.crow, b, e, T.width_k, lds);
             }
             const unsigned long long sum = wave_sum(static_cast<unsigned long long>(cnt));
             if (lane == 0 && sum) atomicAdd(&a.counts[a.tasks[t].slot], sum);
@@ -163,11 +181,14 @@ int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
                      int grid_override, int unroll) {
     if (a.total <= 0) return;
+    // default 2: with the next batch loading while one is probed, two chunks
+    // per batch keep four loads in flight per wave within 64 VGPRs (eight
+    // waves per SIMD)
     switch (unroll) {
         case 1: launch_mode<1>(a, mode, lds_words, waves, s, grid_override); break;
-        case 2: launch_mode<2>(a, mode, lds_words, waves, s, grid_override); break;
+        case 4: launch_mode<4>(a, mode, lds_words, waves, s, grid_override); break;
         case 8: launch_mode<8>(a, mode, lds_words, waves, s, grid_override); break;
-        default: launch_mode<4>(a, mode, lds_words, waves, s, grid_override); break;
+        default: launch_mode<2>(a, mode, lds_words, waves, s, grid_override); break;
     }
 }
 

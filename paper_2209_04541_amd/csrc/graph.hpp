@@ -13,12 +13,14 @@ namespace pgabb {
 // the block and its transpose:
 //   [ rptr   : width + 1    ]  dense row offsets over stripe i's row range,
 //                              relative to the start of `col`
-//   [ items  : 2 * nitems   ]  row work items (u, c): local row u and c, the
-//                              index of a run of at most kSplitV entries of u
+//   [ items  : 3 * nitems   ]  row work items (u, b, e): local row u and the
+//                              run [b, e) of at most kSplitV of its entries,
+//                              as offsets into `col`
 //   [ col    : nnz          ]  local column ids (rank - base of stripe j)
 //   [ cptr   : cwidth + 1   ]  dense column offsets over stripe j's range,
 //                              relative to the start of `crow`
-//   [ citems : 2 * ncitems  ]  column work items (v, c), as above per column
+//   [ citems : 3 * ncitems  ]  column work items (v, b, e), as above per
+//                              column, offsets into `crow`
 //   [ crow   : nnz          ]  local row ids of each column's entries
 // Local ids are rank - base_s, where base_s is stripe s's first rank that
 // can own an edge (isolated vertices rank lowest and own none).  One chunk is
@@ -26,6 +28,7 @@ namespace pgabb {
 // the block plays A_ij in a task (rows when the row of A_ik is staged,
 // columns when the row of A_jk is staged).
 constexpr int32_t kSplitV = 32;
+constexpr int32_t kItemWords = 3;
 
 struct BlockInfo {
     int32_t i = 0, j = 0;
@@ -37,10 +40,10 @@ struct BlockInfo {
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
     int64_t off_items() const { return chunk_off + width + 1; }
-    int64_t off_col() const { return off_items() + 2 * static_cast<int64_t>(nitems); }
+    int64_t off_col() const { return off_items() + kItemWords * static_cast<int64_t>(nitems); }
     int64_t off_cptr() const { return off_col() + nnz; }
     int64_t off_citems() const { return off_cptr() + cwidth + 1; }
-    int64_t off_crow() const { return off_citems() + 2 * static_cast<int64_t>(ncitems); }
+    int64_t off_crow() const { return off_citems() + kItemWords * static_cast<int64_t>(ncitems); }
     int64_t end() const { return off_crow() + nnz; }
 };
 

@@ -317,6 +317,7 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
                                                   const uint32_t *__restrict__ pos, int64_t nslots,
                                                   const int64_t *__restrict__ slot_base_dense,
                                                   const int64_t *__restrict__ items_off,
+                                                  const int64_t *__restrict__ rptr_off,
                                                   int32_t nblk, int32_t *__restrict__ arena) {
     extern __shared__ int64_t s_sb[];
     for (int q = threadIdx.x; q < nblk; q += B) s_sb[q] = slot_base_dense[q];
@@ -327,10 +328,15 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
         const int32_t b = block_of_slot(q, s_sb, nblk);
         const int64_t r = q - s_sb[b];
         const uint32_t at = pos[q] - pos[s_sb[b]];
-        int32_t *it = arena + items_off[b] + 2 * static_cast<int64_t>(at);
+        // the row's entries [start, end) (its dense offsets, written by
+        // k_fill_rptr), cut into runs of at most kSplitV
+        const int32_t start = arena[rptr_off[b] + r], end = arena[rptr_off[b] + r + 1];
+        int32_t *it = arena + items_off[b] + kItemWords * static_cast<int64_t>(at);
         for (uint32_t c = 0; c < f; ++c) {
-            it[2 * c] = static_cast<int32_t>(r);
-            it[2 * c + 1] = static_cast<int32_t>(c);
+            const int32_t rb = start + static_cast<int32_t>(c) * kSplitV;
+            it[kItemWords * c] = static_cast<int32_t>(r);
+            it[kItemWords * c + 1] = rb;
+            it[kItemWords * c + 2] = min(rb + kSplitV, end);
         }
     }
 }
@@ -612,7 +618,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             PGABB_HIP(hipGetLastError());
             PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
             scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // slots now item positions
-            k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb, d_io,
+            k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb, d_io, d_ro,
                                                           nblk, g->arena.get());
             PGABB_HIP(hipGetLastError());
             k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx, d_ro, d_co,

@@ -28,8 +28,7 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t w, int shift) {
 }
 
 // Membership of w in the sorted list a[lo, hi) by binary search.
-__device__ __forceinline__ uint32_t sorted_contains(const int32_t *__restrict__ a, int32_t lo,
-                                                    int32_t hi, int32_t w) {
+__device__ __forceinline__ uint32_t sorted_contains(gptr<int32_t> a, int32_t lo, int32_t hi, int32_t w) {
     const int32_t end = hi;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
@@ -56,6 +55,39 @@ __device__ __forceinline__ uint32_t filter_slot(int32_t w, int fshift) {
     return (static_cast<uint32_t>(w) * 0x85EBCA77u) >> fshift;
 }
 
+// Loads elements base + q*64 + lane (q < UNROLL) of the flattened walk over
+// the lists of one group of up to 64 ids, or -1 past its end.  Lane l of the
+// group holds its list's start pb and its prefix pre; each lane tracks the
+// lane sg whose list holds its element.  Element numbers only grow from call
+// to call, so sg only moves forward.
+template <int UNROLL>
+__device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, int32_t total,
+                                          int32_t pre, int32_t pb, int &sg, gptr<int32_t> wk_col,
+                                          int lane) {
+#pragma unroll
+    for (int q = 0; q < UNROLL; ++q) {
+        w[q] = -1;
+        if (base + q * kWave < total) {  // uniform across the wave
+            const int32_t e = base + q * kWave + lane;
+            const int32_t es = e < total ? e : total - 1;
+            // advance to the largest lane whose list starts at or before es.
+            // The shuffle runs on every lane before any test (a shuffle under
+            // a partial mask does not read the masked lanes' values), and the
+            // exit test is a wave-wide ballot.  At most 63 steps.
+            for (int step = 0; step < kWave - 1; ++step) {
+                const int nx = sg < kWave - 1 ? sg + 1 : sg;
+                const int32_t pn = __shfl(pre, nx);
+                const bool adv = (sg < kWave - 1) & (pn <= es);
+                sg += adv ? 1 : 0;
+                if (__ballot(adv) == 0) break;
+            }
+            const int32_t spre = __shfl(pre, sg);
+            const int32_t spb = __shfl(pb, sg);
+            if (e < total) w[q] = wk_col[spb + (e - spre)];
+        }
+    }
+}
+
 // One work item of a block-list: the staged list S = st_col[st_rptr[srow] ..
 // st_rptr[srow + 1]) and the walked lists L_x = wk_col[wk_rptr[x] ..
 // wk_rptr[x + 1]) for the ids x in ids[ib .. ie).  Returns, per lane, part of
@@ -70,21 +102,32 @@ __device__ __forceinline__ uint32_t filter_slot(int32_t w, int fshift) {
 // a bit filter with about eight bits per entry; a probe reads the filter
 // first, so most misses -- nine in ten probes on skewed graphs -- cost one
 // LDS read.
-template <int MODE, int LDS_WORDS, int UNROLL = 4>
-__device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
-                                            const int32_t *__restrict__ st_col, int32_t srow,
-                                            const int32_t *__restrict__ wk_rptr,
-                                            const int32_t *__restrict__ wk_col,
-                                            const int32_t *__restrict__ ids, int32_t ib,
+//
+// The work is latency bound (each step's addresses come from the previous
+// step's loads), so independent loads are issued together: the ids of the
+// walked lists with the bounds of S, the first chunks of the walk before S is
+// staged, and every later chunk before the previous one is probed.
+template <int MODE, int LDS_WORDS, int UNROLL = 2>
+__device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_,
+                                            const int32_t *__restrict__ st_col_, int32_t srow,
+                                            const int32_t *__restrict__ wk_rptr_,
+                                            const int32_t *__restrict__ wk_col_,
+                                            const int32_t *__restrict__ ids_, int32_t ib,
                                             int32_t ie, int32_t width_k,
                                             int32_t *__restrict__ lds, int32_t wbase = 0) {
     const int lane = lane_id();
+    if (ib >= ie) return 0u;
+    const gptr<int32_t> st_rptr = as_global(st_rptr_), st_col = as_global(st_col_);
+    const gptr<int32_t> wk_rptr = as_global(wk_rptr_), wk_col = as_global(wk_col_);
+    const gptr<int32_t> ids = as_global(ids_);
+    int32_t g0 = ib;
+    int32_t gn = min(ie - g0, kWave);
+    int32_t id = lane < gn ? ids[g0 + lane] : 0;
     const int32_t sb = st_rptr[srow], se = st_rptr[srow + 1];
     const int32_t slen = se - sb;
-    if (slen == 0 || ib >= ie) return 0u;
-    const int32_t vb = ib, ve = ie;
+    if (slen == 0) return 0u;
 
-    // ---- stage S
+    // ---- choose how S is held
     int mode = MODE;
     int shift = 0, fshift = 0;
     uint32_t tmask = 0;
@@ -113,69 +156,50 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
             table = lds + FC;
         }
     }
-    if (mode == kModeHash) {
-        for (int q = lane; q < words; q += kWave) table[q] = -1;
-        for (int q = lane; q < fwords; q += kWave) lds[q] = 0;
-        wave_lds_sync();
-        for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-            const int32_t w = st_col[idx];
-            const uint32_t f = filter_slot(w, fshift);
-            atomicOr(reinterpret_cast<uint32_t *>(&lds[f >> 5]), 1u << (f & 31));
-            uint32_t h = hash_slot(w, shift);
-            while (atomicCAS(&table[h], -1, w) != -1) h = (h + 1) & tmask;
-        }
-        wave_lds_sync();
-    } else if (mode == kModeBitmap) {
-        for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-            const int32_t w = st_col[idx] - wbase;
-            atomicOr(reinterpret_cast<uint32_t *>(&lds[w >> 5]), 1u << (w & 31));
-        }
-        wave_lds_sync();
-    }
 
-    // ---- flattened walk over the lists L_x, x in ids[ib, ie).  UNROLL
-    // chunks of 64 elements are located and loaded before any is probed, so
-    // each wave keeps UNROLL independent row loads in flight.  Each lane
-    // tracks the lane sg holding the row of its element; element numbers only
-    // grow, so sg only moves forward.
     uint32_t cnt = 0;
-    for (int32_t b0 = vb; b0 < ve; b0 += kWave) {
-        const int32_t idx = b0 + lane;
+    bool staged = false;
+    for (;;) {  // groups of up to 64 walked lists
         int32_t pb = 0, len = 0;
-        if (idx < ve) {
-            const int32_t v = ids[idx];
-            pb = wk_rptr[v];
-            len = wk_rptr[v + 1] - pb;
+        if (lane < gn) {
+            pb = wk_rptr[id];
+            len = wk_rptr[id + 1] - pb;
         }
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t pre = incl - len;
-        const int32_t total = __shfl(incl, kWave - 1);
+        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
         int sg = 0;
-        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
-            int32_t w[UNROLL];
-#pragma unroll
-            for (int q = 0; q < UNROLL; ++q) {
-                w[q] = -1;
-                if (base + q * kWave < total) {  // uniform across the wave
-                    const int32_t e = base + q * kWave + lane;
-                    const int32_t es = e < total ? e : total - 1;
-                    // advance to the largest lane whose list starts at or before
-                    // es.  The shuffle runs on every lane before any test (a
-                    // shuffle under a partial mask does not read the masked
-                    // lanes' values), and the exit test is a wave-wide ballot.
-                    // At most 63 steps.
-                    for (int step = 0; step < kWave - 1; ++step) {
-                        const int nx = sg < kWave - 1 ? sg + 1 : sg;
-                        const int32_t pn = __shfl(pre, nx);
-                        const bool adv = (sg < kWave - 1) & (pn <= es);
-                        sg += adv ? 1 : 0;
-                        if (__ballot(adv) == 0) break;
-                    }
-                    const int32_t spre = __shfl(pre, sg);
-                    const int32_t spb = __shfl(pb, sg);
-                    if (e < total) w[q] = wk_col[spb + (e - spre)];
+        int32_t w[UNROLL];
+        walk_load<UNROLL>(w, 0, total, pre, pb, sg, wk_col, lane);
+
+        // ---- stage S while the first chunks are in flight
+        if (!staged) {
+            staged = true;
+            if (mode == kModeHash) {
+                for (int q = lane; q < words; q += kWave) table[q] = -1;
+                for (int q = lane; q < fwords; q += kWave) lds[q] = 0;
+                wave_lds_sync();
+                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
+                    const int32_t x = st_col[idx];
+                    const uint32_t f = filter_slot(x, fshift);
+                    atomicOr(reinterpret_cast<uint32_t *>(&lds[f >> 5]), 1u << (f & 31));
+                    uint32_t h = hash_slot(x, shift);
+                    while (atomicCAS(&table[h], -1, x) != -1) h = (h + 1) & tmask;
                 }
+                wave_lds_sync();
+            } else if (mode == kModeBitmap) {
+                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
+                    const int32_t x = st_col[idx] - wbase;
+                    atomicOr(reinterpret_cast<uint32_t *>(&lds[x >> 5]), 1u << (x & 31));
+                }
+                wave_lds_sync();
             }
+        }
+
+        // ---- probe chunk batch b while batch b + 1 loads
+        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
+            int32_t wn[UNROLL];
+            walk_load<UNROLL>(wn, base + UNROLL * kWave, total, pre, pb, sg, wk_col, lane);
 #pragma unroll
             for (int q = 0; q < UNROLL; ++q) {
                 const int32_t wq = w[q];
@@ -201,7 +225,14 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
                     cnt += sorted_contains(st_col, sb, se, wq);
                 }
             }
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) w[q] = wn[q];
         }
+
+        g0 += kWave;
+        if (g0 >= ie) break;
+        gn = min(ie - g0, kWave);
+        id = lane < gn ? ids[g0 + lane] : 0;
     }
 
     // ---- leave the LDS clean for the next row of this wave

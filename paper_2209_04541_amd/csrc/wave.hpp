@@ -49,16 +49,47 @@ __device__ __forceinline__ T shfl_t(T v, int src) {
     }
 }
 
+// Inclusive prefix sum of 32-bit values across the 64 lanes of a wave (all
+// lanes active), with DPP lane moves only (no LDS traffic): shifts by 1, 2, 4
+// and 8 within each row of 16 lanes, then lane 15 of rows 0 and 2 into rows
+// 1 and 3, then lane 31 into rows 2 and 3.  A lane whose shifted source lies
+// outside its row adds 0.
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave (all lanes active).
 template <class T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
-    const int lane = lane_id();
+    if constexpr (sizeof(T) == 4) {
+        return static_cast<T>(wave_scan_dpp(static_cast<uint32_t>(x)));
+    } else {
+        const int lane = lane_id();
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const T y = shfl_up_t(x, d);
-        if (lane >= d) x += y;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const T y = shfl_up_t(x, d);
+            if (lane >= d) x += y;
+        }
+        return x;
     }
-    return x;
+}
+
+// Pointers that reach a kernel through structs in memory are generic to the
+// compiler, and loads through generic pointers are flat loads, which count
+// against the LDS counter too: every LDS access or lane shuffle after them
+// would wait for them.  Loads through these views are global loads.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)(p);
 }
 
 // Sum across the wave, returned to every lane.
