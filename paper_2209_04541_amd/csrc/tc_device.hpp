@@ -23,8 +23,18 @@ namespace pgabb {
 
 enum RowMode : int { kModeHash = 0, kModeSearch = 1, kModeBitmap = 2 };
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t w, int shift) {
-    return (static_cast<uint32_t>(w) * 0x9E3779B1u) >> shift;
+// Hash and filter slots: Fibonacci hashing modulo 2^24.  A 24-bit multiply
+// (full rate on CDNA, where 32-bit integer multiplies are quarter rate) by
+// an odd constant near 0.618 * 2^24, keeping the top lg of its low 24 bits:
+// slot = floor(frac(w * C / 2^24) * 2^lg).  Ids at or above 2^24 only
+// collide more often (the table compares whole values).  __umul24 returns
+// int here, so the product is taken as unsigned before the shift.
+__device__ __forceinline__ uint32_t hash_slot(int32_t w, int shift, uint32_t mask) {
+    return (static_cast<uint32_t>(__umul24(static_cast<uint32_t>(w), 0x9E3779u)) >> shift) & mask;
+}
+
+__device__ __forceinline__ uint32_t filter_slot(int32_t w, int fshift, uint32_t fmask) {
+    return (static_cast<uint32_t>(__umul24(static_cast<uint32_t>(w), 0xC13FA9u)) >> fshift) & fmask;
 }
 
 // Membership of w in the sorted list a[lo, hi) by binary search.
@@ -51,41 +61,146 @@ struct HashLds {
     static constexpr int kFilterCap = LDS_WORDS - kTableCap;  // words
 };
 
-__device__ __forceinline__ uint32_t filter_slot(int32_t w, int fshift) {
-    return (static_cast<uint32_t>(w) * 0x85EBCA77u) >> fshift;
-}
+// How one item's staged list S is held, fixed before the walk.
+struct Staging {
+    int shift = 0, fshift = 0;  // hash and filter slot shifts (24 - lg)
+    uint32_t tmask = 0;         // table size - 1
+    uint32_t fmask = 0;         // filter bits - 1
+    int words = 0, fwords = 0;  // table (or bitmap) and filter words
+    int32_t *table = nullptr;   // hash table, after the filter
+};
 
 // Loads elements base + q*64 + lane (q < UNROLL) of the flattened walk over
-// the lists of one group of up to 64 ids, or -1 past its end.  Lane l of the
-// group holds its list's start pb and its prefix pre; each lane tracks the
-// lane sg whose list holds its element.  Element numbers only grow from call
-// to call, so sg only moves forward.
+// the lists of one group of up to 64 ids; past the group's end a lane gets
+// -1.  Lane l of the group holds its list's start pb and its prefix pre;
+// each lane tracks the lane sg whose list holds its element.  Element
+// numbers only grow from call to call, so sg only moves forward.  Every call
+// issues exactly UNROLL loads (past the end, of element 0 of wk_col, which
+// exists whenever a walk does), so the compiler can wait for one batch while
+// the next is in flight.
 template <int UNROLL>
 __device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, int32_t total,
                                           int32_t pre, int32_t pb, int &sg, gptr<int32_t> wk_col,
                                           int lane) {
 #pragma unroll
     for (int q = 0; q < UNROLL; ++q) {
-        w[q] = -1;
-        if (base + q * kWave < total) {  // uniform across the wave
-            const int32_t e = base + q * kWave + lane;
-            const int32_t es = e < total ? e : total - 1;
-            // advance to the largest lane whose list starts at or before es.
-            // The shuffle runs on every lane before any test (a shuffle under
-            // a partial mask does not read the masked lanes' values), and the
-            // exit test is a wave-wide ballot.  At most 63 steps.
-            for (int step = 0; step < kWave - 1; ++step) {
-                const int nx = sg < kWave - 1 ? sg + 1 : sg;
-                const int32_t pn = __shfl(pre, nx);
-                const bool adv = (sg < kWave - 1) & (pn <= es);
-                sg += adv ? 1 : 0;
-                if (__ballot(adv) == 0) break;
+        const int32_t e = base + q * kWave + lane;
+        const bool inb = e < total;
+        const int32_t es = inb ? e : total - 1;
+        // advance to the largest lane whose list starts at or before es.  The
+        // shuffle runs on every lane (a shuffle under a partial mask does not
+        // read the masked lanes' values) and the exit test is wave-wide.  A
+        // lane below its target always advances, so the loop ends after at
+        // most 63 advancing rounds.
+        for (;;) {
+            const int nx = sg < kWave - 1 ? sg + 1 : sg;
+            const int32_t pn = __shfl(pre, nx);
+            const bool adv = (sg < kWave - 1) & (pn <= es);
+            sg += adv ? 1 : 0;
+            if (__ballot(adv) == 0) break;
+        }
+        const int32_t off = __shfl(pb - pre, sg);  // element e of the walk is wk_col[off + e]
+        const int32_t x = wk_col[inb ? off + e : 0];
+        w[q] = inb ? x : -1;
+    }
+}
+
+// Adds to cnt the hits of the UNROLL elements in w (-1 = none) against S.
+// Hash probes are predicated: a wave-uniform loop runs while any lane is
+// still searching, with no per-lane branches.
+template <int PM, int UNROLL>
+__device__ __forceinline__ void probe_batch(const int32_t (&w)[UNROLL], uint32_t &cnt,
+                                            const int32_t *__restrict__ lds, const Staging &sg,
+                                            gptr<int32_t> st_col, int32_t sb, int32_t se,
+                                            int32_t wbase) {
+#pragma unroll
+    for (int q = 0; q < UNROLL; ++q) {
+        const int32_t wq = w[q];
+        if (PM == kModeHash) {
+            const uint32_t f = filter_slot(wq, sg.fshift, sg.fmask);  // in range for any wq
+            const uint32_t bit = (static_cast<uint32_t>(lds[f >> 5]) >> (f & 31)) & 1u;
+            bool go = (wq >= 0) & (bit != 0u);
+            uint32_t h = hash_slot(wq, sg.shift, sg.tmask);
+            uint32_t hit = 0;
+            while (__ballot(go) != 0) {
+                const int32_t sv = sg.table[h];
+                hit |= (go && sv == wq) ? 1u : 0u;
+                go = go && sv >= 0 && sv != wq;
+                h = (h + 1) & sg.tmask;
             }
-            const int32_t spre = __shfl(pre, sg);
-            const int32_t spb = __shfl(pb, sg);
-            if (e < total) w[q] = wk_col[spb + (e - spre)];
+            cnt += hit;
+        } else if (PM == kModeBitmap) {
+            if (wq >= 0) {
+                const int32_t wl = wq - wbase;
+                cnt += (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
+            }
+        } else {
+            if (wq >= 0) cnt += sorted_contains(st_col, sb, se, wq);
         }
     }
+}
+
+// The walk of one item once the staging kind PM is known: groups of up to 64
+// walked lists; for the first group the first chunk batch is loaded before S
+// is staged, and every later batch loads while the previous one is probed.
+template <int PM, int UNROLL>
+__device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col, int32_t sb,
+                                              int32_t se, gptr<int32_t> wk_rptr,
+                                              gptr<int32_t> wk_col, gptr<int32_t> ids, int32_t ib,
+                                              int32_t ie, int32_t g0, int32_t gn, int32_t id,
+                                              int32_t *__restrict__ lds, int32_t wbase, int lane) {
+    uint32_t cnt = 0;
+    bool staged = false;
+    for (;;) {  // groups of up to 64 walked lists
+        int32_t pb = 0, len = 0;
+        if (lane < gn) {
+            pb = wk_rptr[id];
+            len = wk_rptr[id + 1] - pb;
+        }
+        const int32_t incl = wave_inclusive_scan(len);
+        const int32_t pre = incl - len;
+        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        int sgl = 0;
+        int32_t w[UNROLL];
+        walk_load<UNROLL>(w, 0, total, pre, pb, sgl, wk_col, lane);
+
+        if (!staged) {
+            staged = true;
+            if (PM == kModeHash) {
+                for (int q = lane; q < stg.words; q += kWave) stg.table[q] = -1;
+                for (int q = lane; q < stg.fwords; q += kWave) lds[q] = 0;
+                wave_lds_sync();
+                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
+                    const int32_t x = st_col[idx];
+                    const uint32_t f = filter_slot(x, stg.fshift, stg.fmask);
+                    atomicOr(reinterpret_cast<uint32_t *>(&lds[f >> 5]), 1u << (f & 31));
+                    uint32_t h = hash_slot(x, stg.shift, stg.tmask);
+                    while (atomicCAS(&stg.table[h], -1, x) != -1) h = (h + 1) & stg.tmask;
+                }
+                wave_lds_sync();
+            } else if (PM == kModeBitmap) {
+                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
+                    const int32_t x = st_col[idx] - wbase;
+                    atomicOr(reinterpret_cast<uint32_t *>(&lds[x >> 5]), 1u << (x & 31));
+                }
+                wave_lds_sync();
+            }
+        }
+
+        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
+            int32_t wn[UNROLL];
+            walk_load<UNROLL>(wn, base + UNROLL * kWave, total, pre, pb, sgl, wk_col, lane);
+            probe_batch<PM, UNROLL>(w, cnt, lds, stg, st_col, sb, se, wbase);
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) w[q] = wn[q];
+        }
+
+        g0 += kWave;
+        if (g0 >= ie) break;
+        gn = min(ie - g0, kWave);
+        id = lane < gn ? ids[g0 + lane] : 0;
+    }
+    return cnt;
 }
 
 // One work item of a block-list: the staged list S = st_col[st_rptr[srow] ..
@@ -103,10 +218,14 @@ __device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, in
 // first, so most misses -- nine in ten probes on skewed graphs -- cost one
 // LDS read.
 //
-// The work is latency bound (each step's addresses come from the previous
-// step's loads), so independent loads are issued together: the ids of the
-// walked lists with the bounds of S, the first chunks of the walk before S is
-// staged, and every later chunk before the previous one is probed.
+// The walk issues many instructions per element, so its code keeps the
+// instruction count low: the staging kind is fixed per item outside the
+// element loop, hash probes are predicated, and loads go through global
+// views.  It is also latency bound per item (each step's addresses come from
+// the previous step's loads), so independent loads are issued together: the
+// ids of the walked lists with the bounds of S, the first chunks of the walk
+// before S is staged, and every later chunk before the previous one is
+// probed.
 template <int MODE, int LDS_WORDS, int UNROLL = 2>
 __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_,
                                             const int32_t *__restrict__ st_col_, int32_t srow,
@@ -120,22 +239,18 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_
     const gptr<int32_t> st_rptr = as_global(st_rptr_), st_col = as_global(st_col_);
     const gptr<int32_t> wk_rptr = as_global(wk_rptr_), wk_col = as_global(wk_col_);
     const gptr<int32_t> ids = as_global(ids_);
-    int32_t g0 = ib;
-    int32_t gn = min(ie - g0, kWave);
-    int32_t id = lane < gn ? ids[g0 + lane] : 0;
+    const int32_t gn = min(ie - ib, kWave);
+    const int32_t id = lane < gn ? ids[ib + lane] : 0;
     const int32_t sb = st_rptr[srow], se = st_rptr[srow + 1];
     const int32_t slen = se - sb;
     if (slen == 0) return 0u;
 
     // ---- choose how S is held
     int mode = MODE;
-    int shift = 0, fshift = 0;
-    uint32_t tmask = 0;
-    int words = 0, fwords = 0;
-    int32_t *table = lds;
+    Staging stg;
     if (mode == kModeBitmap) {
-        words = (width_k + 31) >> 5;
-        if (words > LDS_WORDS) mode = kModeHash;
+        stg.words = (width_k + 31) >> 5;
+        if (stg.words > LDS_WORDS) mode = kModeHash;
     }
     if (mode == kModeHash) {
         constexpr int TC = HashLds<LDS_WORDS>::kTableCap;
@@ -145,95 +260,29 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_
         if ((1 << lg) > TC || FC < 2) {
             mode = kModeSearch;
         } else {
-            words = 1 << lg;
-            shift = 32 - lg;
-            tmask = static_cast<uint32_t>(words - 1);
+            stg.words = 1 << lg;
+            stg.shift = 24 - lg;
+            stg.tmask = static_cast<uint32_t>(stg.words - 1);
             int flg = 8;  // filter bits: a power of two >= 8 * slen, >= 256
             while ((1 << flg) < 8 * slen && (1 << flg) < 32 * FC) ++flg;
             while ((1 << flg) > 32 * FC) --flg;
-            fwords = (1 << flg) >> 5;
-            fshift = 32 - flg;
-            table = lds + FC;
+            stg.fwords = (1 << flg) >> 5;
+            stg.fshift = 24 - flg;
+            stg.fmask = static_cast<uint32_t>((1 << flg) - 1);
+            stg.table = lds + FC;
         }
     }
 
-    uint32_t cnt = 0;
-    bool staged = false;
-    for (;;) {  // groups of up to 64 walked lists
-        int32_t pb = 0, len = 0;
-        if (lane < gn) {
-            pb = wk_rptr[id];
-            len = wk_rptr[id + 1] - pb;
-        }
-        const int32_t incl = wave_inclusive_scan(len);
-        const int32_t pre = incl - len;
-        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-        int sg = 0;
-        int32_t w[UNROLL];
-        walk_load<UNROLL>(w, 0, total, pre, pb, sg, wk_col, lane);
-
-        // ---- stage S while the first chunks are in flight
-        if (!staged) {
-            staged = true;
-            if (mode == kModeHash) {
-                for (int q = lane; q < words; q += kWave) table[q] = -1;
-                for (int q = lane; q < fwords; q += kWave) lds[q] = 0;
-                wave_lds_sync();
-                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-                    const int32_t x = st_col[idx];
-                    const uint32_t f = filter_slot(x, fshift);
-                    atomicOr(reinterpret_cast<uint32_t *>(&lds[f >> 5]), 1u << (f & 31));
-                    uint32_t h = hash_slot(x, shift);
-                    while (atomicCAS(&table[h], -1, x) != -1) h = (h + 1) & tmask;
-                }
-                wave_lds_sync();
-            } else if (mode == kModeBitmap) {
-                for (int32_t idx = sb + lane; idx < se; idx += kWave) {
-                    const int32_t x = st_col[idx] - wbase;
-                    atomicOr(reinterpret_cast<uint32_t *>(&lds[x >> 5]), 1u << (x & 31));
-                }
-                wave_lds_sync();
-            }
-        }
-
-        // ---- probe chunk batch b while batch b + 1 loads
-        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
-            int32_t wn[UNROLL];
-            walk_load<UNROLL>(wn, base + UNROLL * kWave, total, pre, pb, sg, wk_col, lane);
-#pragma unroll
-            for (int q = 0; q < UNROLL; ++q) {
-                const int32_t wq = w[q];
-                if (wq < 0) continue;
-                if (mode == kModeHash) {
-                    const uint32_t f = filter_slot(wq, fshift);
-                    if ((static_cast<uint32_t>(lds[f >> 5]) >> (f & 31)) & 1u) {
-                        uint32_t h = hash_slot(wq, shift);
-                        for (;;) {
-                            const int32_t sv = table[h];
-                            if (sv == wq) {
-                                ++cnt;
-                                break;
-                            }
-                            if (sv < 0) break;
-                            h = (h + 1) & tmask;
-                        }
-                    }
-                } else if (mode == kModeBitmap) {
-                    const int32_t wl = wq - wbase;
-                    cnt += (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
-                } else {
-                    cnt += sorted_contains(st_col, sb, se, wq);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < UNROLL; ++q) w[q] = wn[q];
-        }
-
-        g0 += kWave;
-        if (g0 >= ie) break;
-        gn = min(ie - g0, kWave);
-        id = lane < gn ? ids[g0 + lane] : 0;
-    }
+    uint32_t cnt;
+    if (mode == kModeHash)
+        cnt = walk_item<kModeHash, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
+                                           lds, wbase, lane);
+    else if (mode == kModeBitmap)
+        cnt = walk_item<kModeBitmap, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
+                                             lds, wbase, lane);
+    else
+        cnt = walk_item<kModeSearch, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
+                                             lds, wbase, lane);
 
     // ---- leave the LDS clean for the next row of this wave
     if (mode == kModeBitmap) {
@@ -245,7 +294,7 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_
         if (MODE == kModeBitmap) {
             // a bitmap kernel expects zeroed LDS between rows
             constexpr int FC = HashLds<LDS_WORDS>::kFilterCap;
-            for (int q = lane; q < FC + words; q += kWave) lds[q] = 0;
+            for (int q = lane; q < FC + stg.words; q += kWave) lds[q] = 0;
             wave_lds_sync();
         }
     }
