@@ -200,11 +200,23 @@ int default_grab(int64_t total_items) {
     return static_cast<int>(std::max<int64_t>(2, std::min<int64_t>(g, 64)));
 }
 
-int mode_of_option(int32_t kernel) {
+LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk) {
     switch (kernel) {
-        case PGABB_KERNEL_BITMAP: return kModeBitmap;
-        case PGABB_KERNEL_SEARCH: return kModeSearch;
-        default: return kModeHash;
+        case PGABB_KERNEL_BITMAP:
+            return LaunchKind{kModeBitmap, choose_lds_words(kModeBitmap, max_out, max_wk)};
+        case PGABB_KERNEL_SEARCH:
+            return LaunchKind{kModeSearch, 320};
+        case PGABB_KERNEL_HASH:
+            return LaunchKind{kModeHash, choose_lds_words(kModeHash, max_out, max_wk)};
+        default: {
+            // LDS sized for hash tables of the longest staged list; where a
+            // stripe's bitmap fits in that region (narrow stripes: the
+            // high-degree end under nnz-balanced cuts), items stage a bitmap
+            // and probe it with one read; elsewhere they hash.
+            const int words = choose_lds_words(kModeHash, max_out, max_wk);
+            const bool some_fit = (static_cast<int64_t>(min_wk) + 31) / 32 <= words;
+            return LaunchKind{some_fit ? kModeBitmap : kModeHash, words};
+        }
     }
 }
 
@@ -254,11 +266,12 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     Staged<TaskDesc> td(T, s);
     Staged<int64_t> pre(static_cast<size_t>(T) + 1, s);
     pre[0] = 0;
-    int32_t max_wk = 0;
+    int32_t max_wk = 0, min_wk = INT32_MAX;
     for (int32_t t = 0; t < T; ++t) {
         td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
         pre[t + 1] = pre[t] + task_items(g, g->tasks[t], orient);
         max_wk = std::max(max_wk, td[t].width_k);
+        min_wk = std::min(min_wk, td[t].width_k);
     }
     DArray<TaskDesc> dtd(T, s);
     DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
@@ -276,12 +289,11 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     a.next = dcnt.get() + T;
     a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T]);
     a.orient = orient;
-    const int mode = mode_of_option(opt.kernel);
-    const int words = choose_lds_words(mode, g->max_out, max_wk);
+    const LaunchKind lk = launch_kind(opt.kernel, g->max_out, max_wk, min_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     StreamTimer tm;
     tm.start(s);
-    launch_tc_tasks(a, mode, words, waves, s, 0, opt.unroll);
+    launch_tc_tasks(a, lk.mode, lk.words, waves, s, 0, opt.unroll);
     tm.stop(s);
 
     Staged<unsigned long long> hcnt(T, s);

@@ -25,7 +25,14 @@ struct CountArgs {
 };
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
-int mode_of_option(int32_t kernel);
+// Kernel template (staging kind) and LDS words per wave of a counting launch,
+// from the kernel option, the longest staged list and the widths of stripe k
+// over the launch's tasks.
+struct LaunchKind {
+    int mode;
+    int words;
+};
+LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk);
 int default_grab(int64_t total_items);
 // kOrientRow or kOrientCol for a count of graph g (g = nullptr: a launch
 // over several graphs, which walks columns unless told otherwise).

@@ -179,7 +179,7 @@ static void counter_loop(pgabb_server *s) {
         std::vector<TaskDesc> td;
         std::vector<int64_t> pre(1, 0);
         std::vector<Request *> live;
-        int32_t max_out = 0, max_wk = 0;
+        int32_t max_out = 0, max_wk = 0, min_wk = INT32_MAX;
         for (Request *r : batch) {
             if (r->status != PGABB_OK || !r->g) {
                 finish(s, r);
@@ -192,6 +192,7 @@ static void counter_loop(pgabb_server *s) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
                 pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt, nullptr)));
                 max_wk = std::max(max_wk, td.back().width_k);
+                min_wk = std::min(min_wk, td.back().width_k);
             }
             max_out = std::max(max_out, g->max_out);
         }
@@ -230,9 +231,9 @@ static void counter_loop(pgabb_server *s) {
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;
-                const int mode = mode_of_option(s->opt.kernel);
-                launch_tc_tasks(a, mode, choose_lds_words(mode, max_out, max_wk),
-                                s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0, s->opt.unroll);
+                const LaunchKind lk = launch_kind(s->opt.kernel, max_out, max_wk, min_wk);
+                launch_tc_tasks(a, lk.mode, lk.words, s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs,
+                                0, s->opt.unroll);
             }
             PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, cs));
             PGABB_HIP(hipStreamSynchronize(cs));

@@ -137,10 +137,14 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     std::vector<hipEvent_t> copied;
     std::vector<hipEvent_t> kstart, kstop;            // per window launch timing
 
-    int32_t max_wk = 0;
-    for (int32_t t = 0; t < T; ++t) max_wk = std::max(max_wk, g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k]);
-    const int mode = mode_of_option(opt.kernel);
-    const int words = choose_lds_words(mode, g->max_out, max_wk);
+    int32_t max_wk = 0, min_wk = INT32_MAX;
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t wk = g->cuts[g->tasks[t].k + 1] - g->base[g->tasks[t].k];
+        max_wk = std::max(max_wk, wk);
+        min_wk = std::min(min_wk, wk);
+    }
+    const LaunchKind lk = launch_kind(opt.kernel, g->max_out, max_wk, min_wk);
+    const int mode = lk.mode, words = lk.words;
     const int orient = orient_of_option(opt, g);
     g->walked_columns = orient == kOrientCol;
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;

@@ -130,10 +130,10 @@ __device__ __forceinline__ void probe_batch(const int32_t (&w)[UNROLL], uint32_t
             }
             cnt += hit;
         } else if (PM == kModeBitmap) {
-            if (wq >= 0) {
-                const int32_t wl = wq - wbase;
-                cnt += (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
-            }
+            const bool ok = wq >= 0;
+            const int32_t wl = ok ? wq - wbase : 0;
+            const uint32_t bit = (static_cast<uint32_t>(lds[wl >> 5]) >> (wl & 31)) & 1u;
+            cnt += ok ? bit : 0u;
         } else {
             if (wq >= 0) cnt += sorted_contains(st_col, sb, se, wq);
         }
@@ -292,9 +292,11 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_
     } else if (mode == kModeHash) {
         wave_lds_sync();
         if (MODE == kModeBitmap) {
-            // a bitmap kernel expects zeroed LDS between rows
+            // a bitmap kernel expects zeroed LDS between rows: clear the
+            // filter and table words this item used
             constexpr int FC = HashLds<LDS_WORDS>::kFilterCap;
-            for (int q = lane; q < FC + stg.words; q += kWave) lds[q] = 0;
+            for (int q = lane; q < stg.fwords; q += kWave) lds[q] = 0;
+            for (int q = lane; q < stg.words; q += kWave) lds[FC + q] = 0;
             wave_lds_sync();
         }
     }
