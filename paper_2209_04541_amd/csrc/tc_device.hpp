@@ -203,8 +203,8 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
     return cnt;
 }
 
-// One work item of a block-list: the staged list S = st_col[st_rptr[srow] ..
-// st_rptr[srow + 1]) and the walked lists L_x = wk_col[wk_rptr[x] ..
+// One work item of a block-list: the staged list S = st_col[sb .. se) (the
+// row srow of the staging block) and the walked lists L_x = wk_col[wk_rptr[x] ..
 // wk_rptr[x + 1]) for the ids x in ids[ib .. ie).  Returns, per lane, part of
 // sum_x |S & L_x| (the sum over lanes is the item's count).  With the edge
 // block walked by rows this is S = A_ik[u], L_v = A_jk[v] for v in A_ij[u];
@@ -227,21 +227,19 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
 // before S is staged, and every later chunk before the previous one is
 // probed.
 template <int MODE, int LDS_WORDS, int UNROLL = 2>
-__device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_,
-                                            const int32_t *__restrict__ st_col_, int32_t srow,
-                                            const int32_t *__restrict__ wk_rptr_,
-                                            const int32_t *__restrict__ wk_col_,
-                                            const int32_t *__restrict__ ids_, int32_t ib,
-                                            int32_t ie, int32_t width_k,
-                                            int32_t *__restrict__ lds, int32_t wbase = 0) {
+__device__ __forceinline__ uint32_t tc_item_core(const int32_t *__restrict__ st_col_, int32_t sb, int32_t se,
+                                                 const int32_t *__restrict__ wk_rptr_,
+                                                 const int32_t *__restrict__ wk_col_,
+                                                 const int32_t *__restrict__ ids_, int32_t ib, int32_t ie,
+                                                 int32_t width_k, int32_t *__restrict__ lds,
+                                                 int32_t wbase = 0) {
     const int lane = lane_id();
     if (ib >= ie) return 0u;
-    const gptr<int32_t> st_rptr = as_global(st_rptr_), st_col = as_global(st_col_);
+    const gptr<int32_t> st_col = as_global(st_col_);
     const gptr<int32_t> wk_rptr = as_global(wk_rptr_), wk_col = as_global(wk_col_);
     const gptr<int32_t> ids = as_global(ids_);
     const int32_t gn = min(ie - ib, kWave);
     const int32_t id = lane < gn ? ids[ib + lane] : 0;
-    const int32_t sb = st_rptr[srow], se = st_rptr[srow + 1];
     const int32_t slen = se - sb;
     if (slen == 0) return 0u;
 
@@ -301,6 +299,20 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr_
         }
     }
     return cnt;
+}
+
+// The same with the staged list given by its row: S = st_col[st_rptr[srow]
+// .. st_rptr[srow + 1]).
+template <int MODE, int LDS_WORDS, int UNROLL = 2>
+__device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
+                                            const int32_t *__restrict__ st_col, int32_t srow,
+                                            const int32_t *__restrict__ wk_rptr,
+                                            const int32_t *__restrict__ wk_col,
+                                            const int32_t *__restrict__ ids, int32_t ib, int32_t ie,
+                                            int32_t width_k, int32_t *__restrict__ lds, int32_t wbase = 0) {
+    const gptr<int32_t> rp = as_global(st_rptr);
+    return tc_item_core<MODE, LDS_WORDS, UNROLL>(st_col, rp[srow], rp[srow + 1], wk_rptr, wk_col, ids, ib, ie,
+                                                 width_k, lds, wbase);
 }
 
 }  // namespace pgabb
