@@ -352,7 +352,7 @@ def bench_served(args):
         return t_start
 
     # continuous batching
-    with P.Server(args.budget_gb << 30, borrow=True) as srv:
+    with P.Server(args.budget_gb << 30, borrow=True, num_streams=args.builders) as srv:
         tickets = [None] * len(arrivals)
         sub_t = [0.0] * len(arrivals)
         clock0 = srv.now()
@@ -393,8 +393,8 @@ def bench_served(args):
     edges = sum(len(reqs[i][1]) for i in range(len(arrivals)))
     out = base_line(args, len(arrivals) / span, "requests/s", span * 1e3 / max(1, len(arrivals)), {
         "workload": "Poisson arrivals at %.0f req/s for %.1f s; request r: R-MAT scale ~ U{10..22}, "
-                    "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget"
-                    % (rate, args.duration, pool_size, args.budget_gb),
+                    "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget, %d builders"
+                    % (rate, args.duration, pool_size, args.budget_gb, args.builders),
         "requests": len(arrivals), "pool": pool_size})
     out.update({
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "input_pairs_per_s": edges / span,
@@ -461,6 +461,7 @@ def main():
     ap.add_argument("--duration", type=float, default=0.25)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gb", type=int, default=64)
+    ap.add_argument("--builders", type=int, default=4)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

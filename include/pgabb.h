@@ -255,8 +255,11 @@ pgabb_status pgabb_server_create(uint64_t device_budget_bytes, const pgabb_tc_op
 /*
  * Queue one request; host arrays are copied before the call returns (or
  * borrowed until it finishes, with PGABB_SERVER_BORROW in the server's
- * options).  *ticket receives an id for pgabb_server_poll.  EINVAL for an id
- * outside [0, n); EBUDGET if the request can never fit the budget.
+ * options).  *ticket receives an id for pgabb_server_poll.  EINVAL for NULL
+ * arrays or n < 0, m < 0; EBUDGET if the request can never fit the budget.
+ * Ids are checked on the device when the request is built: a request with an
+ * id outside [0, n) finishes with status EINVAL (pgabb_server_poll returns
+ * it).
  */
 pgabb_status pgabb_server_submit(pgabb_server *s, int32_t n, int64_t m, const int32_t *src,
                                  const int32_t *dst, uint64_t *ticket);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                 const int32_t el = __builtin_amdgcn_readlane(e, l);
                 const int32_t sbl = __builtin_amdgcn_readlane(sb, l);
                 const int32_t sel = __builtin_amdgcn_readlane(se, l);
-                const TaskDesc &T = tasks[t];
+                const auto &T = tasks[t];
                 if (ORIENT == kOrientRow)
                     cnt += tc_item_core<MODE, LDS_WORDS, UNROLL>(T.ik.col, sbl, sel, T.jk.rptr, T.jk.col, T.ij.col,
                                                                  bl, el, T.width_k, lds);

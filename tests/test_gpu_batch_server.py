@@ -124,9 +124,13 @@ def test_server_small_budget_and_rejection():
         with pytest.raises(P.PgabbError) as ei:
             srv.submit(n, s, d)
         assert ei.value.status == P.EBUDGET
+        # ids are checked when the request is built: the failure shows at poll
+        bad = srv.submit(4, np.array([0], np.int32), np.array([7], np.int32))
         with pytest.raises(P.PgabbError) as ei:
-            srv.submit(4, np.array([0], np.int32), np.array([7], np.int32))
+            _wait(srv, [bad])
         assert ei.value.status == P.EINVAL
+        # and the server keeps serving
+        assert _wait(srv, [srv.submit(*reqs[0])]) == want[:1]
 
 
 def test_batch_rows_longer_than_a_wave():
