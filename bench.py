@@ -461,7 +461,7 @@ def main():
     ap.add_argument("--duration", type=float, default=0.25)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gb", type=int, default=64)
-    ap.add_argument("--builders", type=int, default=4)
+    ap.add_argument("--builders", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
