@@ -117,7 +117,8 @@ typedef struct pgabb_graph_info {
     uint64_t block_bytes;   /* bytes of all block storage */
     uint64_t h2d_bytes;     /* bytes copied host->device by the last count */
     double t_build_ms;      /* device time of the last build phase */
-    double t_partition_ms;  /* device time of the last partition */
+    double t_partition_ms;  /* device time of the last partition (from its
+                               first to its last device operation) */
     double t_count_ms;      /* time of the last count (incl. transfers) */
     double t_kernel_ms;     /* device time of the last count's kernels */
     int64_t kernel_launches; /* counting launches of the last count */
@@ -171,7 +172,12 @@ uint64_t pgabb_tc_count(pgabb_graph *g);
 /* Triangle count with options (NULL = defaults); result in *count. */
 pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
 
-/* Sizes and timings of the graph. */
+/*
+ * Sizes and timings of the graph.  pgabb_partition returns before its last
+ * kernels have run (later calls on the graph's stream are ordered after
+ * them); this call waits for them when it is the first to read the
+ * partition's timing.
+ */
 pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info);
 
 /*

@@ -223,6 +223,14 @@ PGABB_API uint64_t pgabb_tc_count(pgabb_graph *g) {
 
 PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info) {
     if (!g || !info) return set_err(PGABB_EINVAL, "NULL argument");
+    if (g->part_time_pending) {
+        // the last partition's device time, once its last kernels have run
+        PGABB_TRY
+        pgabb_graph *gm = const_cast<pgabb_graph *>(g);
+        gm->t_partition_ms = gm->part_timer->ms();
+        gm->part_time_pending = false;
+        PGABB_CATCH
+    }
     info->n = g->n;
     info->m_input = g->m_input;
     info->m = g->m;

@@ -182,10 +182,12 @@ int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
         return kClass[4];
     }
     if (mode == kModeHash) {
-        // table of at least 1.5 x the longest staged row (load <= 2/3)
+        // table of at least 1.5 x the longest staged row (load <= 2/3); at
+        // least 1280 words, the most that still keeps eight waves per SIMD
+        // (32 waves x 1280 words = 160 KB of LDS per CU)
         const int64_t need = (3 * static_cast<int64_t>(max_stage_len) + 1) / 2;
         for (int c = 0; c < 5; ++c)
-            if (need <= kTable[c]) return kClass[c];
+            if (need <= kTable[c]) return std::max(kClass[c], 1280);
         return kClass[4];  // longer rows fall back to in-place search
     }
     return 320;
@@ -268,6 +270,10 @@ int orient_of_option(const pgabb_tc_options &opt, const pgabb_graph *g) {
     return kOrientCol;
 }
 
+int32_t staged_max(const pgabb_graph *g, const Task &t, int orient) {
+    return g->blocks[orient == kOrientCol ? t.bjk : t.bik].max_row;
+}
+
 int64_t task_items(const pgabb_graph *g, const Task &t, int orient) {
     const BlockInfo &b = g->blocks[t.bij];
     return orient == kOrientCol ? b.ncitems : b.nitems;
@@ -281,12 +287,13 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     Staged<TaskDesc> td(T, s);
     Staged<int64_t> pre(static_cast<size_t>(T) + 1, s);
     pre[0] = 0;
-    int32_t max_wk = 0, min_wk = INT32_MAX;
+    int32_t max_wk = 0, min_wk = INT32_MAX, max_st = 0;
     for (int32_t t = 0; t < T; ++t) {
         td[t] = make_desc(g, g->arena.get(), g->tasks[t], t, nullptr);
         pre[t + 1] = pre[t] + task_items(g, g->tasks[t], orient);
         max_wk = std::max(max_wk, td[t].width_k);
         min_wk = std::min(min_wk, td[t].width_k);
+        max_st = std::max(max_st, staged_max(g, g->tasks[t], orient));
     }
     DArray<TaskDesc> dtd(T, s);
     DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
@@ -304,7 +311,7 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     a.next = dcnt.get() + T;
     a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T]);
     a.orient = orient;
-    const LaunchKind lk = launch_kind(opt.kernel, g->max_out, max_wk, min_wk);
+    const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     StreamTimer tm;
     tm.start(s);

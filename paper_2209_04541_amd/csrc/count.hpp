@@ -38,6 +38,9 @@ int default_grab(int64_t total_items);
 // over several graphs, which walks columns unless told otherwise).
 int orient_of_option(const pgabb_tc_options &opt, const pgabb_graph *g);
 int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
+// Longest list a task stages (a row of A_jk for column walks, of A_ik for row
+// walks).
+int32_t staged_max(const pgabb_graph *g, const Task &t, int orient);
 void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
                      int grid_override, int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,

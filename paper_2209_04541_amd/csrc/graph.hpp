@@ -36,6 +36,7 @@ struct BlockInfo {
     int32_t cwidth = 0;   // columns of the dense range of stripe j
     int32_t nitems = 0;   // row work items
     int32_t ncitems = 0;  // column work items
+    int32_t max_row = 0;  // longest row of the block
     int64_t nnz = 0;
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
@@ -114,6 +115,10 @@ struct pgabb_graph {
     std::vector<uint64_t> task_counts;
 
     double t_build_ms = 0, t_partition_ms = 0, t_count_ms = 0, t_kernel_ms = 0;
+    // events around the last partition; t_partition_ms is read from them
+    // once they have passed (partitioning returns before its last kernels)
+    std::unique_ptr<pgabb::StreamTimer> part_timer;
+    bool part_time_pending = false;
     int64_t kernel_launches = 0;
     uint64_t h2d_bytes = 0;
 };

@@ -35,32 +35,36 @@ struct CutTable {
     int32_t base[kMaxP];
 };
 
-__device__ __forceinline__ int32_t stripe_of(int32_t x, const CutTable &ct) {
-    int32_t lo = 0, hi = ct.p - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (ct.c[mid] <= x) lo = mid;
-        else hi = mid - 1;
+// The cut table of nnz-balanced cuts, built on the device (one workgroup):
+// cut s is the first row x whose CSR offset reaches s * m' / p, and stripe
+// s's dense row range starts at max(cut s, lowest) (clamped to the stripe).
+__global__ __launch_bounds__(B) void k_nnz_cut_table(const int64_t *__restrict__ row_off, int32_t n,
+                                                     int64_t m, int32_t p, int32_t lowest,
+                                                     CutTable *__restrict__ ct) {
+    __shared__ int32_t s_c[kMaxP + 1];
+    for (int32_t s = threadIdx.x; s <= p; s += B) {
+        int32_t c;
+        if (s == 0) {
+            c = 0;
+        } else if (s == p) {
+            c = n;
+        } else {
+            // smallest x in [0, n] with row_off[x] * p >= s * m
+            int64_t lo = 0, hi = n;
+            const int64_t target = static_cast<int64_t>(s) * m;  // < 2^38 for m' < 2^32
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (row_off[mid] * p >= target) hi = mid;
+                else lo = mid + 1;
+            }
+            c = static_cast<int32_t>(lo);
+        }
+        s_c[s] = c;
+        ct->c[s] = c;
     }
-    return lo;
-}
-
-// nnz-balanced cut s: first row x whose CSR offset reaches s * m' / p.
-__global__ void k_nnz_cuts(const int64_t *__restrict__ row_off, int32_t n, int64_t m, int32_t p,
-                           int32_t *__restrict__ cuts) {
-    const int32_t s = static_cast<int32_t>(blockIdx.x * B + threadIdx.x);
-    if (s > p) return;
-    if (s == 0) { cuts[0] = 0; return; }
-    if (s == p) { cuts[p] = n; return; }
-    // smallest x in [0, n] with row_off[x] * p >= s * m
-    int64_t lo = 0, hi = n;
-    const int64_t target = static_cast<int64_t>(s) * m;  // < 2^38 for m' < 2^32
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (row_off[mid] * p >= target) hi = mid;
-        else lo = mid + 1;
-    }
-    cuts[s] = static_cast<int32_t>(lo);
+    __syncthreads();
+    for (int32_t s = threadIdx.x; s < p; s += B) ct->base[s] = min(max(s_c[s], lowest), s_c[s + 1]);
+    if (threadIdx.x == 0) ct->p = p;
 }
 
 // The row walks below give each row to one wavefront: rows of the reversed
@@ -195,22 +199,25 @@ __device__ __forceinline__ void for_rows(const int64_t *__restrict__ row_off, in
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ row_off,
                                                    const int32_t *__restrict__ col, int32_t n,
-                                                   CutTable ct, const int64_t *__restrict__ list,
+                                                   const CutTable *__restrict__ ctp, const int64_t *__restrict__ list,
                                                    const unsigned int *__restrict__ count,
                                                    unsigned long long *__restrict__ nnz,
                                                    unsigned int *__restrict__ items,
-                                                   unsigned long long *__restrict__ walk) {
+                                                   unsigned long long *__restrict__ walk,
+                                                   unsigned int *__restrict__ maxrun) {
     __shared__ unsigned int s_nnz[kMaxP * kMaxP];
     __shared__ unsigned int s_items[kMaxP * kMaxP];
+    __shared__ unsigned int s_max[kMaxP * kMaxP];
     __shared__ int32_t s_c[kMaxP + 1];
     __shared__ unsigned long long s_walk;
-    const int p = ct.p;
+    const int p = ctp->p;
     const int pp = p * p;
     for (int q = threadIdx.x; q < pp; q += B) {
         s_nnz[q] = 0;
         s_items[q] = 0;
+        s_max[q] = 0;
     }
-    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ctp->c[q];
     if (threadIdx.x == 0) s_walk = 0;
     __syncthreads();
     // Walked entries when the kernel reads A_ik[x] for every entry (x, y) of
@@ -223,6 +230,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
         if (cnt > 0) {
             atomicAdd(&s_nnz[si * p + j], static_cast<unsigned int>(cnt));
             atomicAdd(&s_items[si * p + j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
+            atomicMax(&s_max[si * p + j], static_cast<unsigned int>(cnt));
             my_walk += static_cast<unsigned long long>(cnt) * static_cast<unsigned long long>(row_end - lo);
         }
     };
@@ -245,6 +253,7 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
         if (s_nnz[q]) {
             atomicAdd(&nnz[q], static_cast<unsigned long long>(s_nnz[q]));
             atomicAdd(&items[q], s_items[q]);
+            if (maxrun) atomicMax(&maxrun[q], s_max[q]);
         }
     }
     if (walk && threadIdx.x == 0 && s_walk) atomicAdd(walk, s_walk);
@@ -256,15 +265,15 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict__ row_off,
                                                        const int32_t *__restrict__ col, int32_t n,
-                                                       CutTable ct, const int64_t *__restrict__ list,
+                                                       const CutTable *__restrict__ ctp, const int64_t *__restrict__ list,
                                                        const unsigned int *__restrict__ count,
                                                        const int64_t *__restrict__ slot_base,
                                                        uint32_t *__restrict__ slots) {
     __shared__ int32_t s_c[kMaxP + 1];
     __shared__ int32_t s_base[kMaxP];
-    const int p = ct.p;
-    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
-    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ct.base[q];
+    const int p = ctp->p;
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ctp->c[q];
+    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ctp->base[q];
     __syncthreads();
     for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
         auto put = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row_off,
                                                  const int32_t *__restrict__ col, int32_t n,
-                                                 CutTable ct, const int64_t *__restrict__ list,
+                                                 const CutTable *__restrict__ ctp, const int64_t *__restrict__ list,
                                                  const unsigned int *__restrict__ count,
                                                  const int32_t *__restrict__ blk_index,
                                                  const int64_t *__restrict__ rptr_off,
@@ -357,9 +366,9 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
     __shared__ int32_t s_c[kMaxP + 1];
     __shared__ int32_t s_base[kMaxP];
     __shared__ int64_t s_dst[B / 64][kMaxP];
-    const int p = ct.p;
-    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ct.c[q];
-    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ct.base[q];
+    const int p = ctp->p;
+    for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ctp->c[q];
+    for (int q = threadIdx.x; q < p; q += B) s_base[q] = ctp->base[q];
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
@@ -432,36 +441,36 @@ unsigned cap_grid(int64_t work) {
 void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t *cuts_host) {
     hipStream_t s = g->stream;
     const int32_t n = g->n;
-    auto t0 = std::chrono::steady_clock::now();
+    if (!g->part_timer) g->part_timer = std::make_unique<StreamTimer>();
+    g->part_timer->start(s);
 
-    // ---- cut vector
-    std::vector<int32_t> cuts(static_cast<size_t>(p) + 1);
-    if (cuts_host) {
-        std::copy(cuts_host, cuts_host + p + 1, cuts.begin());
-    } else if (cut_mode == PGABB_CUT_UNIFORM) {
-        for (int32_t s_ = 0; s_ <= p; ++s_)
-            cuts[s_] = static_cast<int32_t>((static_cast<int64_t>(s_) * n) / p);
-    } else {
-        DArray<int32_t> dc(static_cast<size_t>(p) + 1, s);
-        k_nnz_cuts<<<grid_for(p + 1, B), B, 0, s>>>(g->row_off.get(), n, g->m, p, dc.get());
-        PGABB_HIP(hipGetLastError());
-        Staged<int32_t> hc(static_cast<size_t>(p) + 1, s);
-        PGABB_HIP(hipMemcpyAsync(hc.get(), dc.get(), hc.bytes(), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipStreamSynchronize(s));
-        std::copy(hc.get(), hc.get() + p + 1, cuts.begin());
-    }
-
-    // Ranks below `lowest` own no edge (isolated vertices rank first under the
-    // degree order), so each stripe's dense row range starts at or after it.
+    // ---- cut table, on the device.  Ranks below `lowest` own no edge
+    // (isolated vertices rank first under the degree order), so each
+    // stripe's dense row range starts at or after it.  The host reads the
+    // table back with the block sizes, in one round trip.
     const int32_t lowest = (g->flags & PGABB_ORDER_BY_ID) ? 0 : static_cast<int32_t>(g->isolated);
-    CutTable ct{};
-    ct.p = p;
-    std::vector<int32_t> base(p);
-    for (int32_t i = 0; i <= p; ++i) ct.c[i] = cuts[i];
-    for (int32_t i = 0; i < p; ++i) {
-        base[i] = std::min(std::max(cuts[i], lowest), cuts[i + 1]);
-        ct.base[i] = base[i];
+    DArray<CutTable> dct(1, s);
+    if (cuts_host || cut_mode == PGABB_CUT_UNIFORM) {
+        Staged<CutTable> hct(1, s);
+        CutTable &ct = hct[0];
+        ct = CutTable{};
+        ct.p = p;
+        for (int32_t i = 0; i <= p; ++i)
+            ct.c[i] = cuts_host ? cuts_host[i] : static_cast<int32_t>((static_cast<int64_t>(i) * n) / p);
+        for (int32_t i = 0; i < p; ++i) ct.base[i] = std::min(std::max(ct.c[i], lowest), ct.c[i + 1]);
+        PGABB_HIP(hipMemcpyAsync(dct.get(), hct.get(), sizeof(CutTable), hipMemcpyHostToDevice, s));
+    } else {
+        k_nnz_cut_table<<<1, B, 0, s>>>(g->row_off.get(), n, g->m, p, lowest, dct.get());
+        PGABB_HIP(hipGetLastError());
     }
+    const CutTable *ctp = dct.get();
+    Staged<CutTable> hct(1, s);
+    auto take_cuts = [&]() {
+        // after the round trip: the host copy of the cut table
+        std::vector<int32_t> cuts(hct[0].c, hct[0].c + p + 1), base(hct[0].base, hct[0].base + p);
+        g->cuts = cuts;
+        g->base = base;
+    };
 
     // drop any previous partition
     g->arena.release();
@@ -472,8 +481,6 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
     g->task_counts.clear();
     g->block_of.assign(static_cast<size_t>(p) * p, -1);
     g->p = p;
-    g->cuts = cuts;
-    g->base = base;
     g->arena_words = 0;
     g->probe_work_col = 0;
 
@@ -517,27 +524,33 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
 
         // ---- block sizes, forward (entries, row items) and reversed (column items)
         // one buffer, one clear, one copy back: nnz[pp] nnz_r[pp] (u64) |
-        // items[pp] items_r[pp] (u32) | walked entries of column walks (u64)
-        const size_t nsz = 3 * pp + 1;
+        // items[pp] items_r[pp] (u32) | walked entries of column walks (u64) |
+        // longest row run per block (u32)
+        const size_t nsz = 3 * pp + 1 + (pp + 1) / 2;
         DArray<unsigned long long> dsz(nsz, s);
         PGABB_HIP(hipMemsetAsync(dsz.get(), 0, nsz * sizeof(unsigned long long), s));
         unsigned long long *dnnz = dsz.get(), *dnnz_r = dnnz + pp, *dwalk = dsz.get() + 3 * pp;
         unsigned int *ditems = reinterpret_cast<unsigned int *>(dnnz_r + pp), *ditems_r = ditems + pp;
-        k_block_sizes<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
-                                                  dnnz, ditems, dwalk);
-        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ct, long_f.get(), nlong.get(),
-                                                     dnnz, ditems, dwalk);
-        k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(), nlong.get() + 1,
-                                                  dnnz_r, ditems_r, nullptr);
-        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ct, long_r.get(),
-                                                     nlong.get() + 1, dnnz_r, ditems_r, nullptr);
+        unsigned int *dmax = reinterpret_cast<unsigned int *>(dwalk + 1);
+        k_block_sizes<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ctp, long_f.get(), nlong.get(),
+                                                  dnnz, ditems, dwalk, dmax);
+        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ctp, long_f.get(), nlong.get(),
+                                                     dnnz, ditems, dwalk, dmax);
+        k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ctp, long_r.get(), nlong.get() + 1,
+                                                  dnnz_r, ditems_r, nullptr, nullptr);
+        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ctp, long_r.get(),
+                                                     nlong.get() + 1, dnnz_r, ditems_r, nullptr, nullptr);
         PGABB_HIP(hipGetLastError());
         Staged<unsigned long long> hsz(nsz, s);
         PGABB_HIP(hipMemcpyAsync(hsz.get(), dsz.get(), hsz.bytes(), hipMemcpyDeviceToHost, s));
+        PGABB_HIP(hipMemcpyAsync(hct.get(), dct.get(), sizeof(CutTable), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        take_cuts();
+        const std::vector<int32_t> &cuts = g->cuts, &base = g->base;
         const unsigned long long *hnnz = hsz.get();
         const unsigned int *hitems = reinterpret_cast<const unsigned int *>(hsz.get() + 2 * pp);
         const unsigned int *hitems_r = hitems + pp;
+        const unsigned int *hmax = reinterpret_cast<const unsigned int *>(hsz.get() + 3 * pp + 1);
         g->probe_work_col = hsz[3 * pp];
 
         // ---- block table (row-major block order) and chunk layout
@@ -554,6 +567,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 bi.nitems = static_cast<int32_t>(hitems[q]);
                 bi.ncitems = static_cast<int32_t>(hitems_r[static_cast<size_t>(j) * p + i]);
                 bi.nnz = static_cast<int64_t>(hnnz[q]);
+                bi.max_row = static_cast<int32_t>(hmax[q]);
                 bi.chunk_off = g->arena_words;
                 bi.chunk_len = bi.end() - bi.chunk_off;
                 g->arena_words += bi.chunk_len;
@@ -608,8 +622,8 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
 
             DArray<uint32_t> slots(static_cast<size_t>(nslots) + 1, s), flags(static_cast<size_t>(nslots) + 1, s);
             PGABB_HIP(hipMemsetAsync(slots.get(), 0, (nslots + 1) * sizeof(uint32_t), s));
-            k_row_slot_counts<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp, slots.get());
-            k_row_slot_counts<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_sb_pp, slots.get());
+            k_row_slot_counts<false><<<lgrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_sb_pp, slots.get());
+            k_row_slot_counts<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_sb_pp, slots.get());
             PGABB_HIP(hipGetLastError());
             scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
             const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
@@ -621,9 +635,9 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb, d_io, d_ro,
                                                           nblk, g->arena.get());
             PGABB_HIP(hipGetLastError());
-            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx, d_ro, d_co,
+            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co,
                                                    g->arena.get());
-            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ct, lst, nl, d_bidx, d_ro, d_co,
+            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co,
                                                       g->arena.get());
             PGABB_HIP(hipGetLastError());
         }
@@ -644,11 +658,17 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             }
         std::stable_sort(g->tasks.begin(), g->tasks.end(),
                          [](const Task &a, const Task &b) { return a.weight > b.weight; });
+        // no wait here: the fills run on while the caller goes on; later
+        // work on the stream is ordered after them, and the scratch freed
+        // above is reused only after its free's event
+    } else {
+        PGABB_HIP(hipMemcpyAsync(hct.get(), dct.get(), sizeof(CutTable), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        take_cuts();
     }
     g->task_counts.assign(g->tasks.size(), 0);
-    g->t_partition_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    g->part_timer->stop(s);
+    g->part_time_pending = true;
 }
 
 }  // namespace pgabb

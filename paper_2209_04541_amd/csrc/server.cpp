@@ -193,8 +193,8 @@ static void counter_loop(pgabb_server *s) {
                 pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt, nullptr)));
                 max_wk = std::max(max_wk, td.back().width_k);
                 min_wk = std::min(min_wk, td.back().width_k);
+                max_out = std::max(max_out, staged_max(g, t, orient_of_option(s->opt, nullptr)));
             }
-            max_out = std::max(max_out, g->max_out);
         }
         if (live.empty()) {
             s->cv_build.notify_all();

@@ -143,9 +143,11 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         max_wk = std::max(max_wk, wk);
         min_wk = std::min(min_wk, wk);
     }
-    const LaunchKind lk = launch_kind(opt.kernel, g->max_out, max_wk, min_wk);
-    const int mode = lk.mode, words = lk.words;
     const int orient = orient_of_option(opt, g);
+    int32_t max_st = 0;
+    for (int32_t t = 0; t < T; ++t) max_st = std::max(max_st, staged_max(g, g->tasks[t], orient));
+    const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
+    const int mode = lk.mode, words = lk.words;
     g->walked_columns = orient == kOrientCol;
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     const int grab_opt = opt.rows_per_grab;
