@@ -25,8 +25,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "TC edges/sec at 1 MI355X (% HBM roofline); batched graphs/sec; p50/p99 latency"
-KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_amd/csrc/count.hip",
-                  "paper_2209_04541_amd/csrc/count.hpp"]
+# device code of the counting kernel: a stored traffic measurement is used
+# only while these files are unchanged
+KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_amd/csrc/tc_kernel.hpp",
+                  "paper_2209_04541_amd/csrc/wave.hpp", "paper_2209_04541_amd/csrc/count.hpp"]
 
 
 def kernel_digest():
