@@ -143,14 +143,17 @@ __device__ __forceinline__ void probe_batch(const int32_t (&w)[UNROLL], uint32_t
 // The walk of one item once the staging kind PM is known: groups of up to 64
 // walked lists; for the first group the first chunk batch is loaded before S
 // is staged, and every later batch loads while the previous one is probed.
+// S is staged when the first non-empty group comes (`staged` tells the
+// caller whether it was), so an item whose lists are all empty stages
+// nothing.
 template <int PM, int UNROLL>
 __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col, int32_t sb,
                                               int32_t se, gptr<int32_t> wk_rptr,
                                               gptr<int32_t> wk_col, gptr<int32_t> ids, int32_t ib,
                                               int32_t ie, int32_t g0, int32_t gn, int32_t id,
-                                              int32_t *__restrict__ lds, int32_t wbase, int lane) {
+                                              int32_t *__restrict__ lds, int32_t wbase, int lane,
+                                              bool &staged) {
     uint32_t cnt = 0;
-    bool staged = false;
     for (;;) {  // groups of up to 64 walked lists
         int32_t pb = 0, len = 0;
         if (lane < gn) {
@@ -164,7 +167,7 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
         int32_t w[UNROLL];
         walk_load<UNROLL>(w, 0, total, pre, pb, sgl, wk_col, lane);
 
-        if (!staged) {
+        if (!staged && total > 0) {
             staged = true;
             if (PM == kModeHash) {
                 for (int q = lane; q < stg.words; q += kWave) stg.table[q] = -1;
@@ -272,17 +275,19 @@ __device__ __forceinline__ uint32_t tc_item_core(const int32_t *__restrict__ st_
     }
 
     uint32_t cnt;
+    bool staged = false;
     if (mode == kModeHash)
         cnt = walk_item<kModeHash, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                           lds, wbase, lane);
+                                           lds, wbase, lane, staged);
     else if (mode == kModeBitmap)
         cnt = walk_item<kModeBitmap, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                             lds, wbase, lane);
+                                             lds, wbase, lane, staged);
     else
         cnt = walk_item<kModeSearch, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                             lds, wbase, lane);
+                                             lds, wbase, lane, staged);
 
     // ---- leave the LDS clean for the next row of this wave
+    if (!staged) return cnt;
     if (mode == kModeBitmap) {
         wave_lds_sync();
         for (int32_t idx = sb + lane; idx < se; idx += kWave) lds[(st_col[idx] - wbase) >> 5] = 0;

@@ -117,3 +117,31 @@ def test_allocator_hook_failure_and_restore():
         assert L.pgabb_set_allocator(None, None, None) == P.OK
         torch.cuda.synchronize()
     assert gpu_count(n, s, d, 3) == want
+
+
+def test_dense_graphs_task_counts():
+    """Dense random graphs (rows of hundreds of entries) under random cut
+    vectors: per-task counts of row and column walks match the oracle's
+    block counts, for the automatic, hash and search staging."""
+    rng = np.random.default_rng(11)
+    for case in range(12):
+        n = int(rng.integers(150, 420))
+        m = int(rng.integers(n * n // 8, n * n // 3))
+        s = rng.integers(0, n, m).astype(np.int32)
+        d = rng.integers(0, n, m).astype(np.int32)
+        _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+        p = int(rng.integers(1, 6))
+        cuts = np.concatenate([[0], np.sort(rng.integers(0, n + 1, p - 1)), [n]]).astype(np.int32)
+        B = oracle.block_counts(n, row_off, col, cuts)
+        kernel = int([P.KERNEL_AUTO, P.KERNEL_HASH, P.KERNEL_SEARCH][case % 3])
+        for by_rows in (False, True):
+            with P.Graph(n, s, d) as g:
+                g.partition(p, cuts=cuts)
+                total = g.count(by_rows=by_rows, kernel=kernel)
+                ijk, cnt = g.task_counts()
+            got = np.zeros_like(B)
+            for (i, j, k), c in zip(ijk, cnt):
+                got[i, j, k] += c
+            say("dense case", case, n, m, p, by_rows, kernel, total)
+            assert np.array_equal(got, B), (case, by_rows)
+            assert total == int(B.sum())
