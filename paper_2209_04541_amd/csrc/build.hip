@@ -127,6 +127,16 @@ __global__ void k_row_counts_and_cols(const uint64_t *__restrict__ okeys, int64_
     }
 }
 
+// indeg[rank v] = deg[v] - outdeg[rank v]: the edges of v whose other end
+// ranks lower
+__global__ void k_indeg(const int32_t *__restrict__ deg, const int32_t *__restrict__ rank,
+                        const int32_t *__restrict__ outdeg, int32_t n, int32_t *__restrict__ indeg) {
+    for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B) {
+        const int32_t r = rank[v];
+        indeg[r] = deg[v] - outdeg[r];
+    }
+}
+
 __global__ void k_widen(const int32_t *__restrict__ in, int32_t n, int64_t *__restrict__ out) {
     for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B)
         out[v] = in[v];
@@ -201,6 +211,7 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
 
     g->rank.reset(static_cast<size_t>(n), s);
     g->outdeg.reset(static_cast<size_t>(n), s);
+    g->indeg.reset(static_cast<size_t>(n), s);
     g->row_off.reset(static_cast<size_t>(n) + 1, s);
     if (n > 0) PGABB_HIP(hipMemsetAsync(g->outdeg.get(), 0, sizeof(int32_t) * n, s));
     PGABB_HIP(hipMemsetAsync(g->row_off.get(), 0, sizeof(int64_t) * (static_cast<size_t>(n) + 1), s));
@@ -290,7 +301,10 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
     // statistics for sizing kernels and stating algorithmic bytes
     DArray<Stats> st(1, s);
     PGABB_HIP(hipMemsetAsync(st.get(), 0, sizeof(Stats), s));
-    if (n > 0) k_vertex_stats<<<std::min(cap_grid(n), 1024u), B, 0, s>>>(deg.get(), g->outdeg.get(), n, st.get());
+    if (n > 0) {
+        k_vertex_stats<<<std::min(cap_grid(n), 1024u), B, 0, s>>>(deg.get(), g->outdeg.get(), n, st.get());
+        k_indeg<<<cap_grid(n), B, 0, s>>>(deg.get(), g->rank.get(), g->outdeg.get(), n, g->indeg.get());
+    }
     if (g->m > 0)
         k_probe_work<<<std::min(cap_grid(g->m), 2048u), B, 0, s>>>(g->col.get(), g->m, g->outdeg.get(), st.get());
     PGABB_HIP(hipGetLastError());

@@ -100,6 +100,7 @@ struct pgabb_graph {
     pgabb::DArray<int32_t> col;      // m'
     pgabb::DArray<int32_t> rank;     // n: rank of input id
     pgabb::DArray<int32_t> outdeg;   // n: oriented row lengths (by rank)
+    pgabb::DArray<int32_t> indeg;    // n: oriented column lengths (by rank)
 
     // partition
     int32_t p = 0;

@@ -21,9 +21,6 @@
 
 namespace pgabb {
 
-bool radix_sort_u64_bits(uint64_t *keys, uint64_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
-                         int64_t n, int lo_bit, int hi_bit, hipStream_t s);
-
 namespace {
 
 constexpr int B = 256;
@@ -398,32 +395,21 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
     });
 }
 
-// Reversed oriented graph: key = y << nb | x for every entry (x, y).
+// Reversed oriented graph: for every entry (x, y), the key y and the value x.
 template <bool LONG>
-__global__ __launch_bounds__(B) void k_rev_keys(const int64_t *__restrict__ row_off,
-                                                const int32_t *__restrict__ col, int32_t n, int nb,
-                                                const int64_t *__restrict__ list,
-                                                const unsigned int *__restrict__ count,
-                                                uint64_t *__restrict__ keys) {
+__global__ __launch_bounds__(B) void k_rev_pairs(const int64_t *__restrict__ row_off,
+                                                 const int32_t *__restrict__ col, int32_t n,
+                                                 const int64_t *__restrict__ list,
+                                                 const unsigned int *__restrict__ count,
+                                                 uint32_t *__restrict__ ky, uint32_t *__restrict__ vx) {
     for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t, int64_t, int64_t c0, int64_t c1) {
         const int64_t first = LONG ? c0 + lane_id() : c0;
         const int64_t step = LONG ? kWave : 1;
-        for (int64_t e = first; e < c1; e += step)
-            keys[e] = (static_cast<uint64_t>(col[e]) << nb) | static_cast<uint64_t>(x);
+        for (int64_t e = first; e < c1; e += step) {
+            ky[e] = static_cast<uint32_t>(col[e]);
+            vx[e] = static_cast<uint32_t>(x);
+        }
     });
-}
-
-__global__ void k_rev_counts_cols(const uint64_t *__restrict__ keys, int64_t m, int nb,
-                                  int32_t *__restrict__ cnt, int32_t *__restrict__ rcol) {
-    const uint64_t mask = (1ull << nb) - 1;
-    const int64_t stride = int64_t(gridDim.x) * B;
-    for (int64_t base = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); base < m; base += stride) {
-        const int64_t e = base + lane_id();
-        const bool valid = e < m;
-        const uint64_t k = valid ? keys[e] : 0ull;
-        add_run_lengths(valid, static_cast<int64_t>(k >> nb), cnt);
-        if (valid) rcol[e] = static_cast<int32_t>(k & mask);
-    }
 }
 
 __global__ void k_widen32(const int32_t *__restrict__ in, int32_t n, int64_t *__restrict__ out) {
@@ -498,24 +484,24 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
 
         // ---- reversed oriented graph (in-edges, sorted by (y, x)): its blocks
         // are the transposes of the forward blocks
+        // (row offsets: the scanned in-degrees from the build)
         DArray<int64_t> rev_off(static_cast<size_t>(n) + 1, s);
-        DArray<int32_t> rev_col(static_cast<size_t>(g->m), s);
+        DArray<uint32_t> vx(g->m, s), vx_alt(g->m, s);
+        const int32_t *rev_col = nullptr;
         {
-            DArray<uint64_t> k0(g->m, s), k1(g->m, s);
-            k_rev_keys<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, long_f.get(),
-                                                  nlong.get(), k0.get());
-            k_rev_keys<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, g->nb, long_f.get(),
-                                                     nlong.get(), k0.get());
+            DArray<uint32_t> ky(g->m, s), ky_alt(g->m, s);
+            k_rev_pairs<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, long_f.get(), nlong.get(),
+                                                   ky.get(), vx.get());
+            k_rev_pairs<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, long_f.get(), nlong.get(),
+                                                      ky.get(), vx.get());
             PGABB_HIP(hipGetLastError());
-            // keys come in CSR order, already ascending in x within each y, so
-            // a stable sort on the y bits alone orders them by (y, x)
-            uint64_t *kk = k0.get();
-            if (radix_sort_u64_bits(k0.get(), k1.get(), nullptr, nullptr, g->m, g->nb, 2 * g->nb, s)) kk = k1.get();
-            DArray<int32_t> cnt(static_cast<size_t>(n), s);
-            PGABB_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * n, s));
-            k_rev_counts_cols<<<cap_grid(g->m), B, 0, s>>>(kk, g->m, g->nb, cnt.get(), rev_col.get());
+            // pairs come in CSR order, ascending in x within each y, so a
+            // stable sort on y orders them by (y, x)
+            const bool alt = radix_sort_u32(ky.get(), ky_alt.get(), vx.get(), vx_alt.get(), g->m, g->nb, s);
+            rev_col = reinterpret_cast<const int32_t *>(alt ? vx_alt.get() : vx.get());
+            (alt ? vx : vx_alt).release();
             DArray<int64_t> wide(static_cast<size_t>(n), s);
-            k_widen32<<<lgrid, B, 0, s>>>(cnt.get(), n, wide.get());
+            k_widen32<<<lgrid, B, 0, s>>>(g->indeg.get(), n, wide.get());
             PGABB_HIP(hipGetLastError());
             scan_exclusive_i64(wide.get(), rev_off.get(), n, rev_off.get() + n, s);
         }
@@ -536,9 +522,9 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                                                   dnnz, ditems, dwalk, dmax);
         k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ctp, long_f.get(), nlong.get(),
                                                      dnnz, ditems, dwalk, dmax);
-        k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ctp, long_r.get(), nlong.get() + 1,
+        k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col, n, ctp, long_r.get(), nlong.get() + 1,
                                                   dnnz_r, ditems_r, nullptr, nullptr);
-        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col.get(), n, ctp, long_r.get(),
+        k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col, n, ctp, long_r.get(),
                                                      nlong.get() + 1, dnnz_r, ditems_r, nullptr, nullptr);
         PGABB_HIP(hipGetLastError());
         Staged<unsigned long long> hsz(nsz, s);
@@ -586,7 +572,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         for (int pass = 0; pass < 2; ++pass) {
             const bool rev = pass == 1;
             const int64_t *off = rev ? rev_off.get() : g->row_off.get();
-            const int32_t *cl = rev ? rev_col.get() : g->col.get();
+            const int32_t *cl = rev ? rev_col : g->col.get();
             const int64_t *lst = rev ? long_r.get() : long_f.get();
             const unsigned int *nl = nlong.get() + (rev ? 1 : 0);
             // layout: sb_pp[pp] sb_dense[nblk] rptr_off[nblk] items_off[nblk]
