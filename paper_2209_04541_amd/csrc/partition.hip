@@ -97,18 +97,40 @@ struct RowRun {
     int64_t lo, hi;  // this lane's run [lo, hi) (empty when lo == hi)
 };
 
-// Row x's run in stripe j0 + lane.  Every lane calls it for the same x.
+// Row x's run in stripe j0 + lane (a long row: more than 64 entries).
+// Every lane calls it for the same x.  Each lane finds where its stripe
+// starts; its run ends where the next lane's starts.  The search is first
+// narrowed by 64 evenly spaced samples of the row, read in one load: lane
+// j counts the samples below c[j] with one ballot per stripe of the row.
 __device__ __forceinline__ RowRun row_run(const int32_t *__restrict__ col, int64_t e0, int64_t e1,
                                           int32_t x, const int32_t *c, int32_t p) {
     RowRun r;
+    const int lane = lane_id();
     r.si = stripe_lds(x, c, p);
     const int32_t j0 = stripe_lds(col[e0], c, p);
     const int32_t j1 = stripe_lds(col[e1 - 1], c, p);
-    r.j = j0 + lane_id();
+    r.j = j0 + lane;
+    const int64_t len = e1 - e0;
+    auto sample_at = [&](int q) { return e0 + ((static_cast<int64_t>(q) * len) >> 6); };
+    const int32_t sv = col[sample_at(lane)];
+    int below = 0;  // samples whose column is below c[r.j]
+    for (int32_t k = 1; k <= j1 - j0; ++k) {
+        const uint64_t m = __ballot(sv < c[j0 + k]);
+        if (lane == k) below = __popcll(m);
+    }
+    int64_t start = e0;
+    if (lane >= 1 && r.j <= j1) {
+        // samples 0 .. below-1 lie below c[r.j] (sample 0 is e0, in stripe
+        // j0 < r.j, so below >= 1) and sample `below` (or e1) does not
+        const int64_t lo = sample_at(below - 1) + 1;
+        const int64_t hi = below < 64 ? sample_at(below) : e1;
+        start = first_at_least(col, lo, hi, c[r.j]);
+    }
+    const int64_t next = __shfl(start, lane < 63 ? lane + 1 : 63);
     r.lo = r.hi = 0;
     if (r.j <= j1) {
-        r.lo = r.j == j0 ? e0 : first_at_least(col, e0, e1, c[r.j]);
-        r.hi = r.j == j1 ? e1 : first_at_least(col, e0, e1, c[r.j + 1]);
+        r.lo = start;
+        r.hi = r.j == j1 ? e1 : next;
     }
     return r;
 }
