@@ -136,9 +136,10 @@ __device__ __forceinline__ RowRun row_run(const int32_t *__restrict__ col, int64
 }
 
 // Rows are walked in two kinds of launch: short rows (at most kLongRow
-// entries) by one thread each, with a stripe pointer that moves forward as
-// the sorted row is read; long rows, collected into a device list first, by
-// one wave each, lane l finding the run of stripe j0 + l by binary search.
+// entries) a thread each, or 64 at a time per wave with their entries
+// flattened over the lanes; long rows, collected into a device list first,
+// by one wave each, lane l finding the run of stripe j0 + l by binary
+// search.
 constexpr int64_t kLongRow = 64;
 
 // Calls f(si, j, lo, hi) for every non-empty run [lo, hi) of row x (a short
@@ -159,6 +160,84 @@ __device__ __forceinline__ void short_row_runs(const int32_t *__restrict__ col, 
         }
     }
     f(si, j, lo, e1);
+}
+
+// The short rows, a thread each: calls g(x, e0, e1) for every non-empty row
+// x of at most kLongRow entries.
+template <class G>
+__device__ __forceinline__ void for_short_rows(const int64_t *__restrict__ row_off, int32_t n, G g) {
+    for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
+        const int64_t e0 = row_off[x], e1 = row_off[x + 1];
+        if (e0 == e1 || e1 - e0 > kLongRow) continue;
+        g(static_cast<int32_t>(x), e0, e1);
+    }
+}
+
+// Counting kernels, which act once per run, walk each short row with one
+// thread (a run needs one comparison per entry); kernels that write every
+// entry take the rows' entries flattened instead:
+//
+// The short rows (at most kLongRow entries) of all rows, 64 consecutive rows
+// per wave, their entries flattened: the wave's short rows are numbered
+// through by a scan of their lengths (long rows count as empty), and lane l
+// takes flattened entry 64 k + l, finding its row by a search of the
+// prefix sums in LDS and the start of its run (row x, column stripe j) from
+// the run starts of the chunk (one ballot) or, for a run begun in an
+// earlier chunk, the carried start.  Calls f(x, si, j, e, y, lo) for every
+// entry e = (x, y) of a short row, lo being the first entry of its run.
+// Every lane of the workgroup must call it.  Without RUNS, only x, e and y
+// are meaningful (no stripes are looked up).
+template <bool RUNS = true, class F>
+__device__ __forceinline__ void flat_short_rows(const int64_t *__restrict__ row_off,
+                                                const int32_t *__restrict__ col, int32_t n,
+                                                const int32_t *c, int32_t p, F f) {
+    __shared__ int32_t s_pre[B / 64][65];  // flattened start of each row, then the total
+    __shared__ int64_t s_e0[B / 64][64];   // first entry of each row
+    __shared__ int32_t s_si[B / 64][64];   // row stripes
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t le_mask = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int64_t stride = int64_t(gridDim.x) * B;
+    for (int64_t x0 = blockIdx.x * int64_t(B) + (threadIdx.x & ~63); x0 < n; x0 += stride) {
+        const int64_t x = x0 + lane;
+        const int64_t e0 = x < n ? row_off[x] : 0;
+        const int64_t e1 = x < n ? row_off[x + 1] : 0;
+        const int32_t len = (e1 - e0 <= kLongRow) ? static_cast<int32_t>(e1 - e0) : 0;
+        const int32_t incl = wave_inclusive_scan(len);
+        s_pre[w][lane] = incl - len;
+        if (lane == 63) s_pre[w][64] = incl;
+        s_e0[w][lane] = e0;
+        s_si[w][lane] = (RUNS && x < n) ? stripe_lds(static_cast<int32_t>(x), c, p) : 0;
+        wave_lds_sync();
+        const int32_t total = s_pre[w][64];
+        int64_t carry = 0;
+        for (int32_t base = 0; base < total; base += kWave) {
+            const int32_t t = base + lane;
+            const bool valid = t < total;
+            int r = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+                if (s_pre[w][r + step] <= t) r += step;
+            const int64_t rs = s_e0[w][r];
+            const int64_t e = rs + (t - s_pre[w][r]);
+            const int32_t y = valid ? col[e] : 0;
+            int32_t j = 0;
+            int64_t lo = 0;
+            if (RUNS) {
+                j = stripe_lds(y, c, p);
+                const bool is_start = valid && (e == rs || col[e > rs ? e - 1 : rs] < c[j]);
+                const uint64_t starts = __ballot(is_start);
+                const uint64_t mine = starts & le_mask;
+                // entry number of the lane's run start: runs never cross rows,
+                // so the flattened distance back to the start is e - lo
+                const int32_t back = mine ? lane - (63 - __clzll(mine)) : lane + 1 + static_cast<int32_t>(carry);
+                lo = e - back;
+                if (starts) carry = 63 - (63 - __clzll(starts));
+                else carry += kWave;
+            }
+            if (valid) f(static_cast<int32_t>(x0 + r), s_si[w][r], j, e, y, lo);
+        }
+        wave_lds_sync();
+    }
 }
 
 // Long rows are cut into chunks of at most kChunk entries, listed as
@@ -183,32 +262,22 @@ inline size_t long_list_capacity(int32_t n, int64_t m) {
     return static_cast<size_t>(n) + static_cast<size_t>(m / kChunk) + 1;
 }
 
-// Row x of launch kind LONG: short launches take every row x < n a thread
-// at a time and skip long rows; long launches take the listed chunks a wave
-// at a time.  Calls g(x, e0, e1, c0, c1) with the row's entries [e0, e1)
-// and the entries [c0, c1) this call owns (the whole row for a short row),
-// uniformly across a wave in long launches.
-template <bool LONG, class G>
-__device__ __forceinline__ void for_rows(const int64_t *__restrict__ row_off, int32_t n,
-                                         const int64_t *__restrict__ list,
-                                         const unsigned int *__restrict__ count, G g) {
-    if (!LONG) {
-        for (int64_t x = blockIdx.x * int64_t(B) + threadIdx.x; x < n; x += int64_t(gridDim.x) * B) {
-            const int64_t e0 = row_off[x], e1 = row_off[x + 1];
-            if (e0 == e1 || e1 - e0 > kLongRow) continue;
-            g(static_cast<int32_t>(x), e0, e1, e0, e1);
-        }
-    } else {
-        const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
-        const int64_t nl = *count;
-        for (int64_t i = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; i < nl; i += nwaves) {
-            const int64_t v = list[i];
-            const int32_t x = static_cast<int32_t>(v >> 32);
-            const int64_t e0 = row_off[x], e1 = row_off[x + 1];
-            const int64_t c0 = e0 + (v & 0xffffffffll) * kChunk;
-            const int64_t c1 = c0 + kChunk < e1 ? c0 + kChunk : e1;
-            g(x, e0, e1, c0, c1);
-        }
+// The listed chunks of long rows, a wave at a time.  Calls g(x, e0, e1, c0,
+// c1) with the row's entries [e0, e1) and the entries [c0, c1) this call
+// owns, uniformly across the wave.
+template <class G>
+__device__ __forceinline__ void for_long_rows(const int64_t *__restrict__ row_off,
+                                              const int64_t *__restrict__ list,
+                                              const unsigned int *__restrict__ count, G g) {
+    const int64_t nwaves = (int64_t(gridDim.x) * B) >> 6;
+    const int64_t nl = *count;
+    for (int64_t i = (blockIdx.x * int64_t(B) + threadIdx.x) >> 6; i < nl; i += nwaves) {
+        const int64_t v = list[i];
+        const int32_t x = static_cast<int32_t>(v >> 32);
+        const int64_t e0 = row_off[x], e1 = row_off[x + 1];
+        const int64_t c0 = e0 + (v & 0xffffffffll) * kChunk;
+        const int64_t c1 = c0 + kChunk < e1 ? c0 + kChunk : e1;
+        g(x, e0, e1, c0, c1);
     }
 }
 
@@ -253,16 +322,19 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
             my_walk += static_cast<unsigned long long>(cnt) * static_cast<unsigned long long>(row_end - lo);
         }
     };
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
-        row_end = e1;
-        if (LONG) {
+    if (LONG) {
+        for_long_rows(row_off, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
+            row_end = e1;
             if (c0 != e0) return;  // per-row counts: the first chunk only
             const RowRun r = row_run(col, e0, e1, x, s_c, p);
             add(r.si, r.j, r.lo, r.hi);
-        } else {
+        });
+    } else {
+        for_short_rows(row_off, n, [&](int32_t x, int64_t e0, int64_t e1) {
+            row_end = e1;
             short_row_runs(col, e0, e1, x, s_c, p, add);
-        }
-    });
+        });
+    }
     if (walk) {
         my_walk = wave_sum(my_walk);
         if (lane_id() == 0 && my_walk) atomicAdd(&s_walk, my_walk);
@@ -294,18 +366,21 @@ __global__ __launch_bounds__(B) void k_row_slot_counts(const int64_t *__restrict
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ctp->c[q];
     for (int q = threadIdx.x; q < p; q += B) s_base[q] = ctp->base[q];
     __syncthreads();
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
-        auto put = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
-            if (hi > lo) slots[slot_base[si * p + j] + (x - s_base[si])] = static_cast<uint32_t>(hi - lo);
-        };
-        if (LONG) {
+    auto put = [&](int32_t x, int32_t si, int32_t j, int64_t lo, int64_t hi) {
+        if (hi > lo) slots[slot_base[si * p + j] + (x - s_base[si])] = static_cast<uint32_t>(hi - lo);
+    };
+    if (LONG) {
+        for_long_rows(row_off, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t) {
             if (c0 != e0) return;  // per-row counts: the first chunk only
             const RowRun r = row_run(col, e0, e1, x, s_c, p);
-            put(r.si, r.j, r.lo, r.hi);
-        } else {
-            short_row_runs(col, e0, e1, x, s_c, p, put);
-        }
-    });
+            put(x, r.si, r.j, r.lo, r.hi);
+        });
+    } else {
+        for_short_rows(row_off, n, [&](int32_t x, int64_t e0, int64_t e1) {
+            short_row_runs(col, e0, e1, x, s_c, p,
+                           [&](int32_t si, int32_t j, int64_t lo, int64_t hi) { put(x, si, j, lo, hi); });
+        });
+    }
 }
 
 // Block of slot q: the last block whose slot range starts at or before q.
@@ -391,16 +466,15 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t c1) {
-        if (!LONG) {
-            short_row_runs(col, e0, e1, x, s_c, p, [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
-                if (hi <= lo) return;
-                const int32_t b = blk_index[si * p + j];
-                int32_t *dst = arena + col_off[b] + arena[rptr_off[b] + (x - s_base[si])];
-                for (int64_t e = lo; e < hi; ++e) *dst++ = col[e] - s_base[j];
-            });
-            return;
-        }
+    if (!LONG) {
+        flat_short_rows(row_off, col, n, s_c, p,
+                        [&](int32_t x, int32_t si, int32_t j, int64_t e, int32_t y, int64_t lo) {
+                            const int32_t b = blk_index[si * p + j];
+                            arena[col_off[b] + arena[rptr_off[b] + (x - s_base[si])] + (e - lo)] = y - s_base[j];
+                        });
+        return;
+    }
+    for_long_rows(row_off, list, count, [&](int32_t x, int64_t e0, int64_t e1, int64_t c0, int64_t c1) {
         const RowRun r = row_run(col, e0, e1, x, s_c, p);
         if (r.hi > r.lo) {
             const int32_t b = blk_index[r.si * p + r.j];
@@ -424,10 +498,16 @@ __global__ __launch_bounds__(B) void k_rev_pairs(const int64_t *__restrict__ row
                                                  const int64_t *__restrict__ list,
                                                  const unsigned int *__restrict__ count,
                                                  uint32_t *__restrict__ ky, uint32_t *__restrict__ vx) {
-    for_rows<LONG>(row_off, n, list, count, [&](int32_t x, int64_t, int64_t, int64_t c0, int64_t c1) {
-        const int64_t first = LONG ? c0 + lane_id() : c0;
-        const int64_t step = LONG ? kWave : 1;
-        for (int64_t e = first; e < c1; e += step) {
+    if (!LONG) {
+        flat_short_rows<false>(row_off, col, n, nullptr, 0,
+                               [&](int32_t x, int32_t, int32_t, int64_t e, int32_t y, int64_t) {
+                                   ky[e] = static_cast<uint32_t>(y);
+                                   vx[e] = static_cast<uint32_t>(x);
+                               });
+        return;
+    }
+    for_long_rows(row_off, list, count, [&](int32_t x, int64_t, int64_t, int64_t c0, int64_t c1) {
+        for (int64_t e = c0 + lane_id(); e < c1; e += kWave) {
             ky[e] = static_cast<uint32_t>(col[e]);
             vx[e] = static_cast<uint32_t>(x);
         }
