@@ -127,16 +127,6 @@ __global__ void k_row_counts_and_cols(const uint64_t *__restrict__ okeys, int64_
     }
 }
 
-// indeg[rank v] = deg[v] - outdeg[rank v]: the edges of v whose other end
-// ranks lower
-__global__ void k_indeg(const int32_t *__restrict__ deg, const int32_t *__restrict__ rank,
-                        const int32_t *__restrict__ outdeg, int32_t n, int32_t *__restrict__ indeg) {
-    for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B) {
-        const int32_t r = rank[v];
-        indeg[r] = deg[v] - outdeg[r];
-    }
-}
-
 __global__ void k_widen(const int32_t *__restrict__ in, int32_t n, int64_t *__restrict__ out) {
     for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B)
         out[v] = in[v];
@@ -149,48 +139,45 @@ struct Stats {
     unsigned long long probe_work;
 };
 
-// Workgroup reductions, one atomic per workgroup (launched with a small grid).
+// Per vertex v (rank r): indeg[r] = deg[v] - outdeg[r], the edges of v
+// whose other end ranks lower; and the statistics, reduced per workgroup
+// (one atomic each; launched with a small grid): the longest oriented row,
+// the isolated vertices and the probe work W = sum over oriented edges
+// (x, y) of outdeg[y] = sum over y of indeg[y] outdeg[y].
 __global__ __launch_bounds__(B) void k_vertex_stats(const int32_t *__restrict__ deg,
+                                                    const int32_t *__restrict__ rank,
                                                     const int32_t *__restrict__ outdeg, int32_t n,
-                                                    Stats *st) {
+                                                    int32_t *__restrict__ indeg, Stats *st) {
     __shared__ int32_t s_mx[B / 64];
-    __shared__ unsigned long long s_iso[B / 64];
+    __shared__ unsigned long long s_iso[B / 64], s_w[B / 64];
     int32_t mx = 0;
-    unsigned long long iso = 0;
+    unsigned long long iso = 0, w = 0;
     for (int64_t v = blockIdx.x * int64_t(B) + threadIdx.x; v < n; v += int64_t(gridDim.x) * B) {
-        mx = max(mx, outdeg[v]);
+        const int32_t r = rank[v];
+        const int32_t o = outdeg[r], i = deg[v] - o;
+        indeg[r] = i;
+        mx = max(mx, o);
         iso += deg[v] == 0;
+        w += static_cast<unsigned long long>(i) * static_cast<unsigned long long>(o);
     }
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) mx = max(mx, __shfl_xor(mx, d));
     iso = wave_sum(iso);
+    w = wave_sum(w);
     if (lane_id() == 0) {
         s_mx[threadIdx.x >> 6] = mx;
         s_iso[threadIdx.x >> 6] = iso;
+        s_w[threadIdx.x >> 6] = w;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < B / 64; ++w) {
-            mx = max(mx, s_mx[w]);
-            iso += s_iso[w];
+        for (int q = 1; q < B / 64; ++q) {
+            mx = max(mx, s_mx[q]);
+            iso += s_iso[q];
+            w += s_w[q];
         }
         atomicMax(&st->max_out, mx);
         atomicAdd(&st->isolated, iso);
-    }
-}
-
-// probe work W = sum over oriented edges (x, y) of outdeg[y]
-__global__ __launch_bounds__(B) void k_probe_work(const int32_t *__restrict__ col, int64_t m,
-                                                  const int32_t *__restrict__ outdeg, Stats *st) {
-    __shared__ unsigned long long s_w[B / 64];
-    unsigned long long w = 0;
-    for (int64_t e = blockIdx.x * int64_t(B) + threadIdx.x; e < m; e += int64_t(gridDim.x) * B)
-        w += static_cast<unsigned long long>(outdeg[col[e]]);
-    w = wave_sum(w);
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < B / 64; ++q) w += s_w[q];
         atomicAdd(&st->probe_work, w);
     }
 }
@@ -302,11 +289,9 @@ void build_graph(pgabb_graph *g, const int32_t *src, const int32_t *dst, int64_t
     DArray<Stats> st(1, s);
     PGABB_HIP(hipMemsetAsync(st.get(), 0, sizeof(Stats), s));
     if (n > 0) {
-        k_vertex_stats<<<std::min(cap_grid(n), 1024u), B, 0, s>>>(deg.get(), g->outdeg.get(), n, st.get());
-        k_indeg<<<cap_grid(n), B, 0, s>>>(deg.get(), g->rank.get(), g->outdeg.get(), n, g->indeg.get());
+        k_vertex_stats<<<std::min(cap_grid(n), 1024u), B, 0, s>>>(deg.get(), g->rank.get(), g->outdeg.get(), n,
+                                                                  g->indeg.get(), st.get());
     }
-    if (g->m > 0)
-        k_probe_work<<<std::min(cap_grid(g->m), 2048u), B, 0, s>>>(g->col.get(), g->m, g->outdeg.get(), st.get());
     PGABB_HIP(hipGetLastError());
     Staged<Stats> hs(1, s);
     PGABB_HIP(hipMemcpyAsync(hs.get(), st.get(), sizeof(Stats), hipMemcpyDeviceToHost, s));
