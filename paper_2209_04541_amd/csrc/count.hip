@@ -23,10 +23,10 @@ namespace pgabb {
 
 namespace {
 
-template <int MODE, int LDS_WORDS, int WAVES, int UNROLL>
+template <int MODE, int LDS_WORDS, int WAVES, int UNROLL, bool FILTER = false>
 void launch_one(const CountArgs &a, hipStream_t s, int grid_override) {
-    auto kern = a.orient == kOrientCol ? k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientCol>
-                                       : k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientRow>;
+    auto kern = a.orient == kOrientCol ? k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientCol, FILTER>
+                                       : k_tc_tasks<MODE, LDS_WORDS, WAVES, UNROLL, kOrientRow, FILTER>;
     int per_cu = 0;
     PGABB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WAVES * 64, 0));
     if (per_cu < 1) per_cu = 1;
@@ -73,6 +73,10 @@ void launch_mode(const CountArgs &a, int mode, int lds_words, int waves, hipStre
 
 }  // namespace
 
+// The hash class that keeps eight waves per SIMD, and its table capacity.
+constexpr int kSmallWords = 1280;
+constexpr int kSmallTable = 1024;
+
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
     static const int kClass[] = {320, 640, 1280, 2304, 4352};
     static const int kTable[] = {256, 512, 1024, 2048, 4096};
@@ -94,11 +98,24 @@ int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
     return 320;
 }
 
-void launch_tc_tasks(const CountArgs &args, int mode, int lds_words, int waves, hipStream_t s,
-                     int grid_override, int unroll) {
-    if (args.total <= 0) return;
-    CountArgs a = args;
-    a.grab = std::max(1, std::min(a.grab, kWave));  // a grab's items fit one wave's lanes
+namespace {
+
+// A launch of a split pair: the default shape (four waves, two chunks per
+// batch), items filtered by staged list length.
+void launch_filtered(const CountArgs &a, int mode, int lds_words, hipStream_t s, int grid_override) {
+    if (mode == kModeBitmap) {
+        if (lds_words <= 1280) launch_one<kModeBitmap, 1280, 4, 2, true>(a, s, grid_override);
+        else if (lds_words <= 2304) launch_one<kModeBitmap, 2304, 4, 2, true>(a, s, grid_override);
+        else launch_one<kModeBitmap, 4352, 4, 2, true>(a, s, grid_override);
+    } else {
+        if (lds_words <= 1280) launch_one<kModeHash, 1280, 4, 2, true>(a, s, grid_override);
+        else if (lds_words <= 2304) launch_one<kModeHash, 2304, 4, 2, true>(a, s, grid_override);
+        else launch_one<kModeHash, 4352, 4, 2, true>(a, s, grid_override);
+    }
+}
+
+void launch_one(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s, int grid_override,
+                int unroll) {
     // default 2: with the next batch loading while one is probed, two chunks
     // per batch keep four loads in flight per wave within 64 VGPRs (eight
     // waves per SIMD)
@@ -110,6 +127,28 @@ void launch_tc_tasks(const CountArgs &args, int mode, int lds_words, int waves, 
     }
 }
 
+}  // namespace
+
+void launch_tc_tasks(const CountArgs &args, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
+                     int unroll) {
+    if (args.total <= 0) return;
+    CountArgs a = args;
+    a.grab = std::max(1, std::min(a.grab, kWave));  // a grab's items fit one wave's lanes
+    if (lk.split == INT32_MAX) {
+        launch_one(a, lk.mode, lk.words, waves, s, grid_override, unroll);
+        return;
+    }
+    // a split pair runs at the default shape (waves and unroll options apply
+    // to single launches)
+    a.stage_lo = 0;
+    a.stage_hi = lk.split;
+    launch_filtered(a, lk.mode, lk.words, s, grid_override);
+    PGABB_HIP(hipMemsetAsync(a.next, 0, sizeof(unsigned long long) * kQueueWords, s));
+    a.stage_lo = lk.split;
+    a.stage_hi = INT32_MAX;
+    launch_filtered(a, lk.mode2, lk.words2, s, grid_override);
+}
+
 int default_grab(int64_t total_items) {
     // at most ~32K counter updates per queue: device-scope atomics on one
     // address serialise, and items are small enough that a few per grab
@@ -119,23 +158,37 @@ int default_grab(int64_t total_items) {
 }
 
 LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk) {
+    LaunchKind lk;
     switch (kernel) {
         case PGABB_KERNEL_BITMAP:
-            return LaunchKind{kModeBitmap, choose_lds_words(kModeBitmap, max_out, max_wk)};
+            lk.mode = kModeBitmap;
+            lk.words = choose_lds_words(kModeBitmap, max_out, max_wk);
+            return lk;
         case PGABB_KERNEL_SEARCH:
-            return LaunchKind{kModeSearch, 320};
-        case PGABB_KERNEL_HASH:
-            return LaunchKind{kModeHash, choose_lds_words(kModeHash, max_out, max_wk)};
-        default: {
-            // LDS sized for hash tables of the longest staged list; where a
-            // stripe's bitmap fits in that region (narrow stripes: the
-            // high-degree end under nnz-balanced cuts), items stage a bitmap
-            // and probe it with one read; elsewhere they hash.
-            const int words = choose_lds_words(kModeHash, max_out, max_wk);
-            const bool some_fit = (static_cast<int64_t>(min_wk) + 31) / 32 <= words;
-            return LaunchKind{some_fit ? kModeBitmap : kModeHash, words};
-        }
+            lk.mode = kModeSearch;
+            lk.words = 320;
+            return lk;
+        default: break;
     }
+    // Hash staging, LDS sized for tables of the longest staged list.  With
+    // the automatic kernel, where a stripe's bitmap fits in that region
+    // (narrow stripes: the high-degree end under nnz-balanced cuts), items
+    // stage a bitmap and probe it with one read; elsewhere they hash.
+    auto kind = [&](int32_t longest, int &mode, int &words) {
+        words = choose_lds_words(kModeHash, longest, max_wk);
+        const bool some_fit = (static_cast<int64_t>(min_wk) + 31) / 32 <= words;
+        mode = (kernel != PGABB_KERNEL_HASH && some_fit) ? kModeBitmap : kModeHash;
+    };
+    kind(max_out, lk.mode, lk.words);
+    if (lk.words > kSmallWords) {
+        // lists up to the small region's table capacity (load <= 2/3) stay
+        // in a launch of full occupancy; the longer ones get their own
+        lk.split = kSmallTable * 2 / 3;
+        lk.mode2 = lk.mode;
+        lk.words2 = lk.words;
+        kind(lk.split, lk.mode, lk.words);
+    }
+    return lk;
 }
 
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
@@ -216,7 +269,7 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     StreamTimer tm;
     tm.start(s);
-    launch_tc_tasks(a, lk.mode, lk.words, waves, s, 0, opt.unroll);
+    launch_tc_tasks(a, lk, waves, s, 0, opt.unroll);
     tm.stop(s);
 
     Staged<unsigned long long> hcnt(T, s);
@@ -224,7 +277,7 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     PGABB_HIP(hipStreamSynchronize(s));
     g->task_counts.assign(hcnt.get(), hcnt.get() + T);
     g->t_kernel_ms = tm.ms();
-    g->kernel_launches = 1;
+    g->kernel_launches = lk.split == INT32_MAX ? 1 : 2;
     uint64_t total = 0;
     for (uint64_t c : g->task_counts) total += c;
     return total;

@@ -22,15 +22,23 @@ struct CountArgs {
     unsigned long long *counts;  // device, indexed by TaskDesc::slot
     unsigned long long *next;    // device, kQueueWords (zero before launch); queue q at q * kQueueStride
     int32_t orient;              // kOrientRow or kOrientCol (which item lists)
+    int32_t stage_lo = 0;        // items whose staged list has more than stage_lo
+    int32_t stage_hi = INT32_MAX;  // and at most stage_hi entries
 };
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 // Kernel template (staging kind) and LDS words per wave of a counting launch,
 // from the kernel option, the longest staged list and the widths of stripe k
-// over the launch's tasks.
+// over the launch's tasks.  When the longest staged list needs a larger
+// hash table than kSmallWords holds, the items with staged lists longer
+// than `split` go to a second launch (mode2, words2): a wave region sized
+// for a few long lists would otherwise cut the waves per CU for all items.
 struct LaunchKind {
     int mode;
     int words;
+    int32_t split = INT32_MAX;
+    int mode2 = 0;
+    int words2 = 0;
 };
 LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk);
 int default_grab(int64_t total_items);
@@ -41,8 +49,10 @@ int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 // Longest list a task stages (a row of A_jk for column walks, of A_ik for row
 // walks).
 int32_t staged_max(const pgabb_graph *g, const Task &t, int orient);
-void launch_tc_tasks(const CountArgs &a, int mode, int lds_words, int waves, hipStream_t s,
-                     int grid_override, int unroll);
+// One or two launches (see LaunchKind); a.next is cleared again between
+// them, so it must not be captured into a graph.
+void launch_tc_tasks(const CountArgs &a, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
+                     int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
                    const int64_t *chunk_dev_off);
 uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt);

@@ -232,8 +232,8 @@ static void counter_loop(pgabb_server *s) {
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;
                 const LaunchKind lk = launch_kind(s->opt.kernel, max_out, max_wk, min_wk);
-                launch_tc_tasks(a, lk.mode, lk.words, s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs,
-                                0, s->opt.unroll);
+                launch_tc_tasks(a, lk, s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0,
+                                s->opt.unroll);
             }
             PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, cs));
             PGABB_HIP(hipStreamSynchronize(cs));

@@ -147,7 +147,6 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     int32_t max_st = 0;
     for (int32_t t = 0; t < T; ++t) max_st = std::max(max_st, staged_max(g, g->tasks[t], orient));
     const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
-    const int mode = lk.mode, words = lk.words;
     g->walked_columns = orient == kOrientCol;
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     const int grab_opt = opt.rows_per_grab;
@@ -294,7 +293,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             a.counts = dcnt.get();
             a.next = dcnt.get() + T + static_cast<size_t>(win) * kQueueWords;
             PGABB_HIP(hipEventRecord(k0, st));
-            launch_tc_tasks(a, mode, words, waves, st, 0, opt.unroll);
+            launch_tc_tasks(a, lk, waves, st, 0, opt.unroll);
             PGABB_HIP(hipEventRecord(k1, st));
             PGABB_HIP(hipEventRecord(de, st));
             for (int32_t ti : wtasks)
@@ -332,7 +331,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     for (auto x : cs) (void)hipStreamDestroy(x);
     (void)hipStreamDestroy(copy_s);
     g->h2d_bytes = h2d;
-    g->kernel_launches = win;
+    g->kernel_launches = static_cast<int64_t>(win) * (lk.split == INT32_MAX ? 1 : 2);
     uint64_t total = 0;
     for (uint64_t c : g->task_counts) total += c;
     return total;

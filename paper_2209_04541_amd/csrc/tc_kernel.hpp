@@ -18,7 +18,10 @@ namespace pgabb {
 // whole grab arrive in two round trips; items whose staged list is empty
 // (common when p is large) are dropped by one ballot, and the wave then
 // walks the others one after another.
-template <int MODE, int LDS_WORDS, int WAVES, int UNROLL, int ORIENT>
+//
+// With FILTER, only the items whose staged list length lies in
+// (a.stage_lo, a.stage_hi] are counted (a launch split by list length).
+template <int MODE, int LDS_WORDS, int WAVES, int UNROLL, int ORIENT, bool FILTER = false>
 __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
     __shared__ int32_t lds_all[WAVES][LDS_WORDS];
     const int w = threadIdx.x >> 6;
@@ -72,7 +75,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                 sb = srp[x];
                 se = srp[x + 1];
             }
-            uint64_t todo = __ballot(lv && se > sb && e > b);
+            bool take = lv && se > sb && e > b;
+            if (FILTER) take = take && se - sb > a.stage_lo && se - sb <= a.stage_hi;
+            uint64_t todo = __ballot(take);
 
             // ---- walk the non-empty items; counts go to each item's task
             int32_t cur = -1;

@@ -2,6 +2,7 @@
 oracle, through the C ABI.  Counts are integers: the bar is exact equality.
 """
 import json
+import math
 import os
 import sys
 
@@ -262,3 +263,49 @@ def test_cached_blocks_across_streams():
         if rep == 3:
             P.release_cached_memory()
     torch.cuda.synchronize()
+
+
+def test_long_staged_lists_split_launch():
+    """Staged lists longer than the small hash table holds go to a second
+    launch with a larger LDS region.  On K_n (ranks follow ids, so row x
+    holds x+1 .. n-1) the total is C(n, 3) and task (i, j, k) counts the
+    triples a < b < c with a, b, c in stripes i, j, k; in core and
+    streamed, for every staging kind and both walks."""
+    n = 1100
+    s, d = np.triu_indices(n, 1)
+    s, d = s.astype(np.int32), d.astype(np.int32)
+    want = math.comb(n, 3)
+    for p in (1, 3):
+        with P.Graph(n, s, d) as g:
+            g.partition(p)
+            cuts = np.asarray(g.cuts(), dtype=np.int64)
+            size = np.diff(cuts)
+            B = np.zeros((p, p, p), dtype=np.int64)
+            for i in range(p):
+                for j in range(i, p):
+                    for k in range(j, p):
+                        if i == j == k:
+                            B[i, j, k] = math.comb(int(size[i]), 3)
+                        elif i == j:
+                            B[i, j, k] = math.comb(int(size[i]), 2) * size[k]
+                        elif j == k:
+                            B[i, j, k] = size[i] * math.comb(int(size[j]), 2)
+                        else:
+                            B[i, j, k] = size[i] * size[j] * size[k]
+            assert B.sum() == want
+            for kernel in (P.KERNEL_AUTO, P.KERNEL_HASH, P.KERNEL_SEARCH):
+                for by_rows in (False, True):
+                    say("split", p, kernel, by_rows)
+                    assert g.count(kernel=int(kernel), by_rows=by_rows) == want
+                    ijk, cnt = g.task_counts()
+                    got = np.zeros_like(B)
+                    for (i, j, k), c in zip(ijk, cnt):
+                        got[i, j, k] += c
+                    assert np.array_equal(got, B)
+                    if p == 1 and kernel != P.KERNEL_SEARCH:
+                        assert g.info()["kernel_launches"] == 2
+            info = g.info()
+            assert g.count(stream_blocks=True, device_cap_bytes=info["block_bytes"] + (1 << 20)) == want
+            # one window; at p = 1 its rows need the second launch
+            assert g.info()["kernel_launches"] == (2 if p == 1 else 1)
+            assert g.info()["h2d_bytes"] >= info["block_bytes"]
