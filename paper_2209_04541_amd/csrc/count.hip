@@ -73,9 +73,8 @@ void launch_mode(const CountArgs &a, int mode, int lds_words, int waves, hipStre
 
 }  // namespace
 
-// The hash class that keeps eight waves per SIMD, and its table capacity.
+// The hash class that keeps eight waves per SIMD.
 constexpr int kSmallWords = 1280;
-constexpr int kSmallTable = 1024;
 
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k) {
     static const int kClass[] = {320, 640, 1280, 2304, 4352};
@@ -134,19 +133,18 @@ void launch_tc_tasks(const CountArgs &args, const LaunchKind &lk, int waves, hip
     if (args.total <= 0) return;
     CountArgs a = args;
     a.grab = std::max(1, std::min(a.grab, kWave));  // a grab's items fit one wave's lanes
-    if (lk.split == INT32_MAX) {
+    if (lk.nparts == 1) {
         launch_one(a, lk.mode, lk.words, waves, s, grid_override, unroll);
         return;
     }
-    // a split pair runs at the default shape (waves and unroll options apply
-    // to single launches)
-    a.stage_lo = 0;
-    a.stage_hi = lk.split;
-    launch_filtered(a, lk.mode, lk.words, s, grid_override);
-    PGABB_HIP(hipMemsetAsync(a.next, 0, sizeof(unsigned long long) * kQueueWords, s));
-    a.stage_lo = lk.split;
-    a.stage_hi = INT32_MAX;
-    launch_filtered(a, lk.mode2, lk.words2, s, grid_override);
+    // the parts of a split launch run at the default shape (waves and unroll
+    // options apply to single launches)
+    for (int q = 0; q < lk.nparts; ++q) {
+        if (q > 0) PGABB_HIP(hipMemsetAsync(a.next, 0, sizeof(unsigned long long) * kQueueWords, s));
+        a.stage_lo = q == 0 ? 0 : lk.hi[q - 1];
+        a.stage_hi = lk.hi[q];
+        launch_filtered(a, lk.pmode[q], lk.pwords[q], s, grid_override);
+    }
 }
 
 int default_grab(int64_t total_items) {
@@ -181,12 +179,20 @@ LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t 
     };
     kind(max_out, lk.mode, lk.words);
     if (lk.words > kSmallWords) {
-        // lists up to the small region's table capacity (load <= 2/3) stay
-        // in a launch of full occupancy; the longer ones get their own
-        lk.split = kSmallTable * 2 / 3;
-        lk.mode2 = lk.mode;
-        lk.words2 = lk.words;
-        kind(lk.split, lk.mode, lk.words);
+        // one part per class from 1280 words up: lists up to a class's table
+        // capacity (load <= 2/3) run with that class's region
+        static const int32_t kCap[3] = {1024 * 2 / 3, 2048 * 2 / 3, INT32_MAX};
+        lk.nparts = 0;
+        for (int q = 0; q < 3; ++q) {
+            const int32_t longest = std::min(max_out, kCap[q]);
+            kind(longest, lk.pmode[q], lk.pwords[q]);
+            lk.hi[q] = kCap[q];
+            ++lk.nparts;
+            if (max_out <= kCap[q]) break;
+        }
+        lk.hi[lk.nparts - 1] = INT32_MAX;
+        lk.mode = lk.pmode[0];
+        lk.words = lk.pwords[0];
     }
     return lk;
 }
@@ -277,7 +283,7 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     PGABB_HIP(hipStreamSynchronize(s));
     g->task_counts.assign(hcnt.get(), hcnt.get() + T);
     g->t_kernel_ms = tm.ms();
-    g->kernel_launches = lk.split == INT32_MAX ? 1 : 2;
+    g->kernel_launches = lk.nparts;
     uint64_t total = 0;
     for (uint64_t c : g->task_counts) total += c;
     return total;

@@ -30,15 +30,18 @@ int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 // Kernel template (staging kind) and LDS words per wave of a counting launch,
 // from the kernel option, the longest staged list and the widths of stripe k
 // over the launch's tasks.  When the longest staged list needs a larger
-// hash table than kSmallWords holds, the items with staged lists longer
-// than `split` go to a second launch (mode2, words2): a wave region sized
-// for a few long lists would otherwise cut the waves per CU for all items.
+// hash table than the 1280-word region holds, the launch is split by staged
+// list length into one launch per LDS class: part q takes the items whose
+// staged list has more than hi[q - 1] (0 for q = 0) and at most hi[q]
+// entries.  A wave region sized for a few long lists would otherwise cut
+// the waves per CU for all items.
 struct LaunchKind {
-    int mode;
+    int mode;    // part 0 (the only part when nparts == 1)
     int words;
-    int32_t split = INT32_MAX;
-    int mode2 = 0;
-    int words2 = 0;
+    int nparts = 1;
+    int32_t hi[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    int pmode[3] = {0, 0, 0};
+    int pwords[3] = {0, 0, 0};
 };
 LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk);
 int default_grab(int64_t total_items);
@@ -49,8 +52,8 @@ int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 // Longest list a task stages (a row of A_jk for column walks, of A_ik for row
 // walks).
 int32_t staged_max(const pgabb_graph *g, const Task &t, int orient);
-// One or two launches (see LaunchKind); a.next is cleared again between
-// them, so it must not be captured into a graph.
+// One launch per part (see LaunchKind); a.next is cleared again between
+// them, so a split launch must not be captured into a graph.
 void launch_tc_tasks(const CountArgs &a, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
                      int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,

@@ -331,7 +331,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     for (auto x : cs) (void)hipStreamDestroy(x);
     (void)hipStreamDestroy(copy_s);
     g->h2d_bytes = h2d;
-    g->kernel_launches = static_cast<int64_t>(win) * (lk.split == INT32_MAX ? 1 : 2);
+    g->kernel_launches = static_cast<int64_t>(win) * lk.nparts;
     uint64_t total = 0;
     for (uint64_t c : g->task_counts) total += c;
     return total;

@@ -265,13 +265,14 @@ def test_cached_blocks_across_streams():
     torch.cuda.synchronize()
 
 
-def test_long_staged_lists_split_launch():
-    """Staged lists longer than the small hash table holds go to a second
-    launch with a larger LDS region.  On K_n (ranks follow ids, so row x
-    holds x+1 .. n-1) the total is C(n, 3) and task (i, j, k) counts the
-    triples a < b < c with a, b, c in stripes i, j, k; in core and
-    streamed, for every staging kind and both walks."""
-    n = 1100
+@pytest.mark.parametrize("n,parts", [(1100, 2), (1500, 3)])
+def test_long_staged_lists_split_launch(n, parts):
+    """Staged lists longer than the 1280-word region's hash table holds go to
+    further launches, one per larger LDS class (rows up to 1099 entries: two
+    launches; up to 1499: three).  On K_n (ranks follow ids, so row x holds
+    x+1 .. n-1) the total is C(n, 3) and task (i, j, k) counts the triples
+    a < b < c with a, b, c in stripes i, j, k; in core and streamed, for
+    every staging kind and both walks."""
     s, d = np.triu_indices(n, 1)
     s, d = s.astype(np.int32), d.astype(np.int32)
     want = math.comb(n, 3)
@@ -303,9 +304,10 @@ def test_long_staged_lists_split_launch():
                         got[i, j, k] += c
                     assert np.array_equal(got, B)
                     if p == 1 and kernel != P.KERNEL_SEARCH:
-                        assert g.info()["kernel_launches"] == 2
+                        assert g.info()["kernel_launches"] == parts
+            assert g.count() == want
             info = g.info()
             assert g.count(stream_blocks=True, device_cap_bytes=info["block_bytes"] + (1 << 20)) == want
-            # one window; at p = 1 its rows need the second launch
-            assert g.info()["kernel_launches"] == (2 if p == 1 else 1)
+            # one window, split as the in-core launch
+            assert g.info()["kernel_launches"] == info["kernel_launches"]
             assert g.info()["h2d_bytes"] >= info["block_bytes"]
