@@ -84,7 +84,7 @@ typedef enum pgabb_status {
                                     row of A_jk, probe the rows of A_ik.  With
                                     neither flag a graph count takes the walk
                                     that reads fewer entries (probe_work or
-                                    probe_work_col of pgabb_graph_info, columns
+                                    probe_work_col of pgabb_graph_info_t, columns
                                     on a tie) and the server walks columns;
                                     both flags are EINVAL */
 
@@ -103,7 +103,7 @@ typedef struct pgabb_tc_options {
 
 typedef struct pgabb_graph pgabb_graph;
 
-typedef struct pgabb_graph_info {
+typedef struct pgabb_graph_info_t {
     int64_t n;              /* vertices (as given) */
     int64_t m_input;        /* input pairs */
     int64_t m;              /* undirected distinct non-loop edges m' */
@@ -127,7 +127,7 @@ typedef struct pgabb_graph_info {
                                 cuts: sum over oriented edges (u,v) of
                                 |{w in N+(u): stripe(w) >= stripe(v)}| */
     int64_t walked_columns;  /* 1 if the last count walked columns, 0 rows */
-} pgabb_graph_info;
+} pgabb_graph_info_t;
 
 /*
  * Build a graph from m pairs (src[e], dst[e]), 0 <= id < n.  Cleans the pairs
@@ -173,12 +173,32 @@ uint64_t pgabb_tc_count(pgabb_graph *g);
 pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
 
 /*
+ * Count several graph objects (PGAbB Section 3.6's count, per graph):
+ * counts[q] for gs[q], q < num_graphs (host array of num_graphs entries).
+ * Each graph is counted as by pgabb_tc_count_ex with opts (NULL = defaults),
+ * in order, on its own stream.  To count thousands of small graphs in one
+ * launch, build a pgabb_batch from their edge lists instead.  EINVAL for a
+ * NULL array or graph or num_graphs < 0; on any error the counts from the
+ * failing graph on are PGABB_COUNT_ERROR.
+ */
+pgabb_status pgabb_tc_count_batch(pgabb_graph *const *gs, int64_t num_graphs, const pgabb_tc_options *opts,
+                                  uint64_t *counts);
+
+/*
  * Sizes and timings of the graph.  pgabb_partition returns before its last
  * kernels have run (later calls on the graph's stream are ordered after
  * them); this call waits for them when it is the first to read the
  * partition's timing.
  */
-pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info);
+pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info_t *info);
+
+/*
+ * The main sizes alone: vertices, undirected unique edges m' (Section 5.1's
+ * cleaned input), grid size p (0 before partitioning) and tasks
+ * (block-lists with three non-empty blocks).  Any output may be NULL.
+ */
+pgabb_status pgabb_graph_info(const pgabb_graph *g, int64_t *n, int64_t *m_undirected, int32_t *p,
+                              int64_t *num_tasks);
 
 /*
  * Copy the oriented CSR to host buffers: row_off[n + 1] (int64), col[m']

@@ -88,6 +88,9 @@ def lib():
             "pgabb_tc_count": (u64, [vp]),
             "pgabb_tc_count_ex": (st, [vp, vp, ctypes.POINTER(u64)]),
             "pgabb_graph_info_get": (st, [vp, ctypes.POINTER(GraphInfo)]),
+            "pgabb_graph_info": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i64)]),
+            "pgabb_tc_count_batch": (st, [vp, i64, vp, vp]),
             "pgabb_graph_export_csr": (st, [vp, vp, vp, vp]),
             "pgabb_graph_cuts": (st, [vp, vp]),
             "pgabb_graph_task_counts": (st, [vp, vp, vp]),
@@ -257,6 +260,25 @@ class Graph:
         _check(lib().pgabb_graph_task_counts(self._h, ctypes.c_void_p(ijk.ctypes.data),
                                              ctypes.c_void_p(cnt.ctypes.data)))
         return ijk[:t], cnt[:t]
+
+
+def graph_info(g):
+    """(n, m', p, tasks) of a Graph."""
+    n, m, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    p = ctypes.c_int32()
+    _check(lib().pgabb_graph_info(g._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(p), ctypes.byref(t)))
+    return n.value, m.value, p.value, t.value
+
+
+def tc_count_batch(graphs, opts=None, **kw):
+    """Counts of several Graph objects, one after another."""
+    if opts is None and kw:
+        opts = options(**kw)
+    hs = (ctypes.c_void_p * max(len(graphs), 1))(*[g._h for g in graphs])
+    out = np.zeros(max(len(graphs), 1), np.uint64)
+    _check(lib().pgabb_tc_count_batch(hs, len(graphs), ctypes.byref(opts) if opts is not None else None,
+                                      ctypes.c_void_p(out.ctypes.data)))
+    return [int(c) for c in out[:len(graphs)]]
 
 
 def tc_count(n, src, dst, p=1, **kw):

@@ -215,13 +215,28 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tc_count_batch(pgabb_graph *const *gs, int64_t num_graphs,
+                                            const pgabb_tc_options *opts, uint64_t *counts) {
+    if (num_graphs < 0) return set_err(PGABB_EINVAL, "num_graphs < 0");
+    if (num_graphs > 0 && (!gs || !counts)) return set_err(PGABB_EINVAL, "NULL argument");
+    for (int64_t q = 0; q < num_graphs; ++q) {
+        const pgabb_status st = gs[q] ? pgabb_tc_count_ex(gs[q], opts, &counts[q])
+                                      : set_err(PGABB_EINVAL, "graph is NULL");
+        if (st != PGABB_OK) {
+            for (int64_t r = q; r < num_graphs; ++r) counts[r] = PGABB_COUNT_ERROR;
+            return st;
+        }
+    }
+    return set_ok();
+}
+
 PGABB_API uint64_t pgabb_tc_count(pgabb_graph *g) {
     uint64_t c = PGABB_COUNT_ERROR;
     if (pgabb_tc_count_ex(g, nullptr, &c) != PGABB_OK) return PGABB_COUNT_ERROR;
     return c;
 }
 
-PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info *info) {
+PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_info_t *info) {
     if (!g || !info) return set_err(PGABB_EINVAL, "NULL argument");
     if (g->part_time_pending) {
         // the last partition's device time, once its last kernels have run
@@ -249,6 +264,16 @@ PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_in
     info->kernel_launches = g->kernel_launches;
     info->probe_work_col = g->probe_work_col;
     info->walked_columns = g->walked_columns;
+    return set_ok();
+}
+
+PGABB_API pgabb_status pgabb_graph_info(const pgabb_graph *g, int64_t *n, int64_t *m_undirected, int32_t *p,
+                                        int64_t *num_tasks) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (m_undirected) *m_undirected = g->m;
+    if (p) *p = g->p;
+    if (num_tasks) *num_tasks = static_cast<int64_t>(g->tasks.size());
     return set_ok();
 }
 

@@ -64,7 +64,7 @@ def test_struct_layouts_match_header(tmp_path):
     (checked against a C program compiled from include/pgabb.h)."""
     import os
     import subprocess
-    fields = {"pgabb_tc_options": P.TcOptions, "pgabb_graph_info": P.GraphInfo}
+    fields = {"pgabb_tc_options": P.TcOptions, "pgabb_graph_info_t": P.GraphInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pgabb.h"', "int main(void) {"]
     for cname, cls in fields.items():
         lines.append('printf("%%zu\\n", sizeof(%s));' % cname)

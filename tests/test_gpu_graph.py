@@ -311,3 +311,21 @@ def test_long_staged_lists_split_launch(n, parts):
             # one window, split as the in-core launch
             assert g.info()["kernel_launches"] == info["kernel_launches"]
             assert g.info()["h2d_bytes"] >= info["block_bytes"]
+
+
+def test_count_several_graph_objects_and_sizes():
+    gl = [gen.rmat(11, 8, gen.seed(99, k)) for k in range(3)] + [gen.er(500, 3000, gen.seed(99, 9))]
+    want = [oracle.tc(*x) for x in gl]
+    objs = [P.Graph(*x) for x in gl]
+    try:
+        objs[1].partition(4)
+        assert P.tc_count_batch(objs) == want
+        assert P.tc_count_batch(objs, kernel=int(P.KERNEL_HASH), by_rows=True) == want
+        assert P.tc_count_batch([]) == []
+        for g, x in zip(objs, gl):
+            info = g.info()
+            assert P.graph_info(g) == (info["n"], info["m"], info["p"], info["num_tasks"])
+        assert P.graph_info(objs[1])[2] == 4
+    finally:
+        for g in objs:
+            g.close()
