@@ -142,6 +142,7 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
         "h2d_bytes_per_step": infos[0]["h2d_bytes"],
         "block_bytes": infos[0]["block_bytes"],
     })
+    out["compulsory_bytes"] = 4 * m + 8 * n  # every oriented edge and row offset read once
     out["copy_probe_gbs"] = copy_probe_gbs()
     out["frac_of_copy_probe"] = roof["achieved"] / out["copy_probe_gbs"]
     if not args.no_cpu_baseline and cpu_sample is not None:
@@ -179,9 +180,19 @@ def oracle_full_pass(n, s, d, m, label):
         t0 = time.perf_counter()
         tri = oracle.tc(n, s, d)
         dt = time.perf_counter() - t0
-        return {"value": m / dt, "unit": "edges/s", "cores": oracle.threads(), "kind": "oracle",
-                "sample": "one full oracle pass (clean, rank, orient, merge count) over %s, %.1f s"
-                          % (label, dt)}, tri
+        out = {"value": m / dt, "unit": "edges/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": "one full oracle pass (clean, rank, orient, merge count) over %s, %.1f s"
+                         % (label, dt)}
+        # the merge count alone on one core and on all cores (same CSR)
+        _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+        threads = oracle.threads()
+        for t in (threads, 1):
+            oracle.set_threads(t)
+            t1 = time.perf_counter()
+            oracle.count_csr(n, row_off, col)
+            out["count_only_edges_per_s_%dcore" % t] = m / (time.perf_counter() - t1)
+        oracle.set_threads(threads)
+        return out, tri
     return run
 
 
@@ -211,7 +222,8 @@ def bench_ooc(args):
     import paper_2209_04541_amd as P
     from paper_2209_04541_amd import gen
     n, s, d = gen.rmat(24, 16, gen.seed(3, 0))
-    cap = args.cap_gb * (1 << 30)
+    cap = args.cap_mb * (1 << 20) if args.cap_mb else args.cap_gb * (1 << 30)
+    cap_label = "%d MiB" % args.cap_mb if args.cap_mb else "%d GiB" % args.cap_gb
     opts = P.options(kernel=args.kernel, device_cap_bytes=int(cap), stream_blocks=True)
 
     def cpu_sample():
@@ -239,7 +251,7 @@ def bench_ooc(args):
 
     return run_graph(args, n, s, d, 32, "ooc",
                      "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed (3,0), 32x32 "
-                     "blocks in pinned host memory, %d GiB device cap" % args.cap_gb,
+                     "blocks in pinned host memory, %s device cap" % cap_label,
                      "traffic_tc_ooc.json", opts=opts, cpu_sample=cpu_sample)
 
 
@@ -458,6 +470,7 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--cap-gb", type=int, default=8)
+    ap.add_argument("--cap-mb", type=int, default=0, help="device cap in MiB (overrides --cap-gb)")
     ap.add_argument("--graphs", type=int, default=10000)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=0.25)
