@@ -88,8 +88,13 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
 
     import paper_2209_04541_amd as P
 
-    ds = torch.from_numpy(s).cuda()
-    dd = torch.from_numpy(d).cuda()
+    if args.host_edges:
+        # edge arrays in pinned host memory: the step includes their copy
+        ds = torch.from_numpy(s).pin_memory().numpy()
+        dd = torch.from_numpy(d).pin_memory().numpy()
+    else:
+        ds = torch.from_numpy(s).cuda()
+        dd = torch.from_numpy(d).cuda()
     torch.cuda.synchronize()
     opts = opts or P.options(kernel=args.kernel)
 
@@ -471,6 +476,8 @@ def main():
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--cap-gb", type=int, default=8)
     ap.add_argument("--cap-mb", type=int, default=0, help="device cap in MiB (overrides --cap-gb)")
+    ap.add_argument("--host-edges", action="store_true",
+                    help="hand the edge list over in pinned host memory (its copy is then in the step)")
     ap.add_argument("--graphs", type=int, default=10000)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=0.25)
