@@ -9,8 +9,8 @@ uint64.  `value` is m' (the graph's distinct undirected edges) divided by the
 step time.  Other workloads (--workload plain|ooc|batch|served) print their
 own line; they are not the default.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on
+one GPU.
 """
 import argparse
 import hashlib
@@ -488,7 +488,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
