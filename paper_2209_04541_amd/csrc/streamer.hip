@@ -87,6 +87,77 @@ static void move_blocks_to_host(pgabb_graph *g) {
     g->blocks_on_host = true;
 }
 
+// Order of the tasks when the blocks do not all fit under the cap: a
+// simulated block cache of `cap` bytes (least recently used out first,
+// never a block of the task being placed) is filled task by task, and the
+// next task is always one whose blocks are missing the fewest bytes from
+// it, the heaviest among equals.  Heaviest-first alone reloads blocks many
+// times once the cache holds a small share of them; this order keeps the
+// tasks that share blocks together.  O(T^2) on the host, with per-task
+// missing bytes updated as blocks enter and leave.
+std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap) {
+    const int32_t T = static_cast<int32_t>(g->tasks.size());
+    const int32_t nblk = static_cast<int32_t>(g->blocks.size());
+    std::vector<std::vector<int32_t>> users(nblk);  // tasks reading each block (once each)
+    std::vector<uint64_t> miss(T, 0);
+    for (int32_t t = 0; t < T; ++t) {
+        const Task &k = g->tasks[t];
+        const int32_t bs[3] = {k.bij, k.bik, k.bjk};
+        for (int q = 0; q < 3; ++q) {
+            const int32_t b = bs[q];
+            if ((q >= 1 && b == bs[0]) || (q == 2 && b == bs[1])) continue;  // a block listed twice
+            users[b].push_back(t);
+            miss[t] += chunk_bytes(g->blocks[b]);
+        }
+    }
+    std::vector<char> done(T, 0), resident(nblk, 0);
+    std::list<int32_t> lru;
+    std::vector<std::list<int32_t>::iterator> pos(nblk);
+    uint64_t used = 0;
+    auto enter = [&](int32_t b) {
+        resident[b] = 1;
+        used += chunk_bytes(g->blocks[b]);
+        lru.push_back(b);
+        pos[b] = std::prev(lru.end());
+        for (int32_t t : users[b]) miss[t] -= chunk_bytes(g->blocks[b]);
+    };
+    auto leave = [&](int32_t b) {
+        resident[b] = 0;
+        used -= chunk_bytes(g->blocks[b]);
+        lru.erase(pos[b]);
+        for (int32_t t : users[b]) miss[t] += chunk_bytes(g->blocks[b]);
+    };
+    std::vector<int32_t> order;
+    order.reserve(T);
+    for (int32_t step = 0; step < T; ++step) {
+        int32_t best = -1;
+        for (int32_t t = 0; t < T; ++t) {  // tasks are heaviest first: the first minimum wins
+            if (done[t]) continue;
+            if (best < 0 || miss[t] < miss[best]) best = t;
+            if (miss[best] == 0) break;
+        }
+        done[best] = 1;
+        order.push_back(best);
+        const Task &k = g->tasks[best];
+        for (int32_t b : {k.bij, k.bik, k.bjk}) {
+            if (resident[b]) {
+                lru.erase(pos[b]);
+                lru.push_back(b);
+                pos[b] = std::prev(lru.end());
+                continue;
+            }
+            const uint64_t need = chunk_bytes(g->blocks[b]);
+            auto it = lru.begin();
+            while (used + need > cap && it != lru.end()) {
+                const int32_t v = *it++;
+                if (v != k.bij && v != k.bik && v != k.bjk) leave(v);
+            }
+            enter(b);
+        }
+    }
+    return order;
+}
+
 uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     move_blocks_to_host(g);
     hipStream_t s = g->stream;
@@ -157,8 +228,14 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     const uint64_t window_new_bytes = std::max<uint64_t>(64ull << 20, std::min<uint64_t>(cap / 4, total_bytes / 8));
 
     std::vector<int64_t> chunk_dev(nblk, 0);  // in int32 words from pool start
+    // processing order of the tasks: heaviest first when every block fits
+    // under the cap, else the locality order above
+    std::vector<int32_t> order(T);
+    for (int32_t t = 0; t < T; ++t) order[t] = t;
+    if (total_bytes > cap) order = locality_order(g, cap);
+
     uint64_t h2d = 0;
-    int32_t next_task = 0;
+    int32_t next_task = 0;  // position in `order`
     int32_t win = 0;
     int64_t pre_at = 0;
 
@@ -171,11 +248,12 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     try {
         while (next_task < T) {
             // ---- form a window: tasks whose blocks fit together
-            std::vector<int32_t> wtasks;
+            std::vector<int32_t> wtasks;  // task indices, in processing order
+            const int32_t p0 = next_task;   // the window's first position in `order`
             std::vector<char> in_window(nblk, 0);
             uint64_t pinned_bytes = 0, new_bytes = 0;
             while (next_task < T && static_cast<int>(wtasks.size()) < window_tasks) {
-                const Task &t = g->tasks[next_task];
+                const Task &t = g->tasks[order[next_task]];
                 // bytes this task adds to the window (its block ids may repeat)
                 uint64_t add = 0, add_new = 0;
                 int32_t seen[3] = {-1, -1, -1};
@@ -193,7 +271,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 for (int32_t b : {t.bij, t.bik, t.bjk}) in_window[b] = 1;
                 pinned_bytes += add;
                 new_bytes += add_new;
-                wtasks.push_back(next_task++);
+                wtasks.push_back(order[next_task++]);
             }
 
             // ---- make the window's blocks resident.  If first-fit cannot place
@@ -261,14 +339,15 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             PGABB_HIP(hipEventRecord(ce, copy_s));
 
             // ---- descriptors and launch
-            const int32_t w0 = wtasks.front();
+            // descriptors sit at the tasks' positions in `order`; each keeps its
+            // task index as its counter slot
             const int32_t W = static_cast<int32_t>(wtasks.size());
             int64_t items = 0;
             hpre[pre_at] = 0;
             for (int32_t q = 0; q < W; ++q) {
                 const int32_t ti = wtasks[q];
-                hdesc[ti] = make_desc(g, reinterpret_cast<const int32_t *>(pool.get()), g->tasks[ti], ti,
-                                      chunk_dev.data());
+                hdesc[p0 + q] = make_desc(g, reinterpret_cast<const int32_t *>(pool.get()), g->tasks[ti], ti,
+                                          chunk_dev.data());
                 items += task_items(g, g->tasks[ti], orient);
                 hpre[pre_at + q + 1] = items;
             }
@@ -279,12 +358,12 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             PGABB_HIP(hipEventCreate(&k1));
             kstart.push_back(k0);
             kstop.push_back(k1);
-            PGABB_HIP(hipMemcpyAsync(ddesc.get() + w0, hdesc.get() + w0, sizeof(TaskDesc) * W,
+            PGABB_HIP(hipMemcpyAsync(ddesc.get() + p0, hdesc.get() + p0, sizeof(TaskDesc) * W,
                                      hipMemcpyHostToDevice, st));
             PGABB_HIP(hipMemcpyAsync(dpre.get() + pre_at, hpre.get() + pre_at, sizeof(int64_t) * (W + 1),
                                      hipMemcpyHostToDevice, st));
             CountArgs a;
-            a.tasks = ddesc.get() + w0;
+            a.tasks = ddesc.get() + p0;
             a.item_pre = dpre.get() + pre_at;
             a.ntasks = W;
             a.grab = grab_opt > 0 ? grab_opt : default_grab(items);
