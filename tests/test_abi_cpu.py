@@ -48,6 +48,14 @@ def test_argument_errors_before_device_work():
     assert L.pgabb_graph_info_get(None, None) == P.EINVAL
     assert L.pgabb_graph_cuts(None, None) == P.EINVAL
     assert L.pgabb_graph_task_counts(None, None, None) == P.EINVAL
+    assert L.pgabb_graph_info(None, None, None, None, None) == P.EINVAL
+    counts = (ctypes.c_uint64 * 2)(7, 7)
+    assert L.pgabb_tc_count_batch(None, -1, None, counts) == P.EINVAL
+    assert L.pgabb_tc_count_batch(None, 2, None, counts) == P.EINVAL
+    gs = (ctypes.c_void_p * 2)(None, None)
+    assert L.pgabb_tc_count_batch(gs, 2, None, counts) == P.EINVAL
+    assert list(counts) == [P.COUNT_ERROR, P.COUNT_ERROR]
+    assert L.pgabb_tc_count_batch(None, 0, None, None) == P.OK
     L.pgabb_graph_destroy(None)  # NULL-safe
 
 
