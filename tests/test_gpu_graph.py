@@ -329,3 +329,37 @@ def test_count_several_graph_objects_and_sizes():
     finally:
         for g in objs:
             g.close()
+
+
+@pytest.mark.parametrize("n,p", [(1500, 3), (0, 6)])
+def test_streamed_under_small_caps(n, p):
+    """Caps below the blocks' total: blocks are evicted and reloaded and the
+    tasks run in the cache-locality order; counts stay exact, per task too
+    (K_1500 also splits its launches by staged list length)."""
+    if n:
+        s, d = np.triu_indices(n, 1)
+        s, d = s.astype(np.int32), d.astype(np.int32)
+        want = math.comb(n, 3)
+    else:
+        n, s, d = gen.rmat(13, 16, gen.seed(95, 11))
+        want = oracle.tc(n, s, d)
+    with P.Graph(n, s, d) as g:
+        g.partition(p)
+        assert g.count() == want
+        ijk0, cnt0 = g.task_counts()
+        total = g.info()["block_bytes"]
+        ran = 0
+        for frac in (0.35, 0.6, 0.85):
+            cap = int(total * frac)
+            try:
+                got = g.count(stream_blocks=True, device_cap_bytes=cap)
+            except P.PgabbError as e:
+                assert e.status == P.ENOMEM  # a task's three blocks exceed the cap
+                continue
+            ran += 1
+            say("small cap", n, p, frac, got)
+            assert got == want
+            ijk, cnt = g.task_counts()
+            assert sorted(zip(map(tuple, ijk), cnt)) == sorted(zip(map(tuple, ijk0), cnt0))
+            assert g.info()["h2d_bytes"] >= total
+        assert ran >= 1
