@@ -94,7 +94,11 @@ typedef struct pgabb_tc_options {
     uint64_t device_cap_bytes; /* 0 = no cap; otherwise block cache bound */
     uint32_t flags;            /* PGABB_OPT_* */
     int32_t waves_per_block;   /* 2, 4 or 8 waves per workgroup (0 = default) */
-    int32_t rows_per_grab;     /* rows a wave takes per work-counter update (0 = default) */
+    int32_t rows_per_grab;     /* work items a wave takes per work-counter
+                                  update, 1..64 (0 = chosen: about 16K walked
+                                  entries per grab for in-core graphs and
+                                  servers, from the item count when
+                                  streaming) */
     int32_t unroll;            /* 64-element chunks of walked lists per load
                                   batch (the next batch loads while one is
                                   probed): 1, 2, 4 or 8 (0 = 2) */

@@ -44,7 +44,11 @@ struct LaunchKind {
     int pwords[3] = {0, 0, 0};
 };
 LaunchKind launch_kind(int32_t kernel, int32_t max_out, int32_t max_wk, int32_t min_wk);
-int default_grab(int64_t total_items);
+// Items per grab from the launch's items and the entries their walks read
+// (walked = 0: from the item count alone).
+int default_grab(int64_t total_items, uint64_t walked);
+// Entries a walk of graph g reads in orientation `orient` (W or W_col).
+uint64_t walked_entries(const pgabb_graph *g, int orient);
 // kOrientRow or kOrientCol for a count of graph g (g = nullptr: a launch
 // over several graphs, which walks columns unless told otherwise).
 int orient_of_option(const pgabb_tc_options &opt, const pgabb_graph *g);

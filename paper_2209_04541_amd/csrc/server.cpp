@@ -180,6 +180,7 @@ static void counter_loop(pgabb_server *s) {
         std::vector<int64_t> pre(1, 0);
         std::vector<Request *> live;
         int32_t max_out = 0, max_wk = 0, min_wk = INT32_MAX;
+        uint64_t walked = 0;
         for (Request *r : batch) {
             if (r->status != PGABB_OK || !r->g) {
                 finish(s, r);
@@ -188,6 +189,7 @@ static void counter_loop(pgabb_server *s) {
             const int32_t slot = static_cast<int32_t>(live.size());
             live.push_back(r);
             pgabb_graph *g = r->g;
+            walked += walked_entries(g, orient_of_option(s->opt, nullptr));
             for (const Task &t : g->tasks) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
                 pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt, nullptr)));
@@ -226,7 +228,7 @@ static void counter_loop(pgabb_server *s) {
                 a.tasks = dtd.get();
                 a.item_pre = dpre.get();
                 a.ntasks = T;
-                a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back());
+                a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back(), walked);
                 a.orient = orient_of_option(s->opt, nullptr);
                 a.total = pre.back();
                 a.counts = dcnt.get();

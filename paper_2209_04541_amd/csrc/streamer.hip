@@ -366,7 +366,10 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             a.tasks = ddesc.get() + p0;
             a.item_pre = dpre.get() + pre_at;
             a.ntasks = W;
-            a.grab = grab_opt > 0 ? grab_opt : default_grab(items);
+            // from the window's item count alone: windows are heaviest-first
+            // slices, whose items carry more work than the graph's mean, so
+            // a grab sized from the mean would be too coarse for them
+            a.grab = grab_opt > 0 ? grab_opt : default_grab(items, 0);
             a.orient = orient;
             a.total = items;
             a.counts = dcnt.get();
