@@ -150,12 +150,58 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
     out["compulsory_bytes"] = 4 * m + 8 * n  # every oriented edge and row offset read once
     out["copy_probe_gbs"] = copy_probe_gbs()
     out["frac_of_copy_probe"] = roof["achieved"] / out["copy_probe_gbs"]
+    if args.shards:
+        out["shards"] = shard_leg(args, n, ds, dd, p, opts, counts[0])
+        out["parity"] = out["parity"] and out["shards"]["sum_equals_count"]
     if not args.no_cpu_baseline and cpu_sample is not None:
         cb, tri = cpu_sample()
         out["cpu_baseline"] = cb
         if tri is not None:
             out["parity"] = out["parity"] and tri == counts[0]
     return out
+
+
+def shard_leg(args, n, ds, dd, p, opts, triangles):
+    """One device's share of the count split by task over args.shards
+    devices, run on this one GPU: every shard counted once after a whole
+    count has put the blocks where they live (host memory when streamed, so
+    each shard's time includes copying the blocks its tasks read), then
+    shard 0 timed over the bench steps."""
+    import numpy as np
+
+    import paper_2209_04541_amd as P
+
+    S = args.shards
+    g = P.Graph(n, ds, dd)
+    g.partition(p)
+    g.count(opts)
+    of = g.task_shards(S)
+    per = []
+    for sh in range(S):
+        c = g.count_shard(sh, S, opts)
+        info = g.info()
+        per.append({"triangles": c, "tasks": int((of == sh).sum()), "t_count_ms": info["t_count_ms"],
+                    "t_kernel_ms": info["t_kernel_ms"], "kernel_launches": info["kernel_launches"],
+                    "h2d_bytes": info["h2d_bytes"]})
+    t0 = []
+    for _ in range(args.steps):
+        g.count_shard(0, S, opts)
+        t0.append(g.info()["t_count_ms"])
+    block_bytes = g.info()["block_bytes"]
+    g.close()
+    ts = [x["t_count_ms"] for x in per]
+    return {
+        "num_shards": S,
+        "deal": "tasks grouped by edge block, groups dealt heaviest first to the least loaded shard",
+        "shard0_t_count_ms_p50": pct(t0, 50),
+        "shard0_t_count_ms_min": min(t0),
+        "shard0_h2d_bytes": per[0]["h2d_bytes"],
+        "block_bytes": block_bytes,
+        "max_shard_t_count_ms": max(ts),
+        "max_over_mean_t_count": max(ts) / float(np.mean(ts)),
+        "sum_equals_count": sum(x["triangles"] for x in per) == triangles,
+        "per_shard": per,
+    }
 
 
 def copy_probe_gbs(mib=1024, reps=5):
@@ -486,6 +532,9 @@ def main():
     ap.add_argument("--builders", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shards", type=int, default=0,
+                    help="block and ooc workloads: also count each of this many task shards "
+                         "(one device's share of a count split over that many devices)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "

@@ -222,6 +222,45 @@ pgabb_status pgabb_graph_cuts(const pgabb_graph *g, int32_t *cuts);
  */
 pgabb_status pgabb_graph_task_counts(const pgabb_graph *g, int32_t *ijk, uint64_t *counts);
 
+/*
+ * Shards of the tasks when a count is split over num_shards devices (PGAbB
+ * Section 4.1: block-lists are independent tasks, so the count splits by
+ * task).  Tasks that share their edge block A_ij form one group (a device
+ * then reads each edge block it holds for all of its k); groups are dealt by
+ * longest processing time: heaviest first (ties: the group whose first task
+ * comes first in task order), each to the shard with the least weight so far
+ * (ties: lowest index).  A group weighs the sum of its tasks' estimated
+ * work under the walk a default count takes (probe_work against
+ * probe_work_col, see PGABB_OPT_COLS), each list length taken as its
+ * block's mean (non-empty rows and columns per block):
+ *   column walk: 1 + trunc(nnz(A_ij) * mean(A_ik)) + trunc(cols(A_ij) * mean(A_jk))
+ *   row walk:    1 + trunc(nnz(A_ij) * mean(A_jk)) + trunc(rows(A_ij) * mean(A_ik))
+ * with mean(A) = nnz(A) / max(rows(A), 1) in double precision.
+ *   num_shards : 1 .. 4096
+ *   shard_of   : host array of num_tasks entries (pgabb_graph_info);
+ *                shard_of[t] for task t in the order of
+ *                pgabb_graph_task_counts
+ * Errors: EINVAL (NULL, num_shards out of range), ESTATE (not partitioned).
+ */
+pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of);
+
+/*
+ * One device's share of a count split over num_shards devices: counts only
+ * the tasks pgabb_graph_task_shards deals to `shard`, as pgabb_tc_count_ex
+ * does with opts (NULL = defaults; partitions with p = 1 first if the graph
+ * was not partitioned).  *count receives their triangles; the counts of
+ * shards 0 .. num_shards - 1 sum to the graph's triangle count.  When the
+ * blocks are streamed (a device cap below their bytes, PGABB_OPT_STREAM, or
+ * blocks already moved to host memory) only the blocks the shard's tasks
+ * read are copied.  Afterwards pgabb_graph_task_counts reports the shard's
+ * tasks' counts (0 for the other tasks) and pgabb_graph_info_get the shard
+ * count's times, launches and copied bytes.
+ * Errors: as pgabb_tc_count_ex; EINVAL for num_shards outside 1 .. 4096 or
+ * shard outside [0, num_shards).
+ */
+pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_options *opts, int32_t shard,
+                                  int32_t num_shards, uint64_t *count);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 

@@ -94,6 +94,8 @@ def lib():
             "pgabb_graph_export_csr": (st, [vp, vp, vp, vp]),
             "pgabb_graph_cuts": (st, [vp, vp]),
             "pgabb_graph_task_counts": (st, [vp, vp, vp]),
+            "pgabb_graph_task_shards": (st, [vp, i32, vp]),
+            "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
             "pgabb_last_error": (ctypes.c_char_p, []),
@@ -230,6 +232,22 @@ class Graph:
         _check(lib().pgabb_tc_count_ex(self._h, ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(c)))
         return int(c.value)
+
+    def count_shard(self, shard, num_shards, opts=None, **kw):
+        """Triangles found by the tasks dealt to `shard` of `num_shards`."""
+        if opts is None and kw:
+            opts = options(**kw)
+        c = ctypes.c_uint64()
+        _check(lib().pgabb_tc_count_shard(self._h, ctypes.byref(opts) if opts is not None else None,
+                                          int(shard), int(num_shards), ctypes.byref(c)))
+        return int(c.value)
+
+    def task_shards(self, num_shards):
+        """Shard of each task (order of task_counts) for num_shards devices."""
+        t = self.info()["num_tasks"]
+        of = np.empty(max(t, 1), np.int32)
+        _check(lib().pgabb_graph_task_shards(self._h, int(num_shards), ctypes.c_void_p(of.ctypes.data)))
+        return of[:t]
 
     def info(self):
         i = GraphInfo()

@@ -191,11 +191,8 @@ static pgabb_tc_options default_options() {
     return o;
 }
 
-PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count) {
-    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
-    if (!count) return set_err(PGABB_EINVAL, "count is NULL");
-    *count = PGABB_COUNT_ERROR;
-    pgabb_tc_options o = opts ? *opts : default_options();
+// Checks the options of a count; PGABB_OK or the status already set.
+static pgabb_status check_options(const pgabb_tc_options &o) {
     if (o.kernel < PGABB_KERNEL_AUTO || o.kernel > PGABB_KERNEL_SEARCH)
         return set_err(PGABB_EINVAL, "unknown kernel");
     if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0)
@@ -209,8 +206,47 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
         return set_err(PGABB_EINVAL, "unknown option flag bits");
     if ((o.flags & PGABB_OPT_ROWS) && (o.flags & PGABB_OPT_COLS))
         return set_err(PGABB_EINVAL, "PGABB_OPT_ROWS and PGABB_OPT_COLS together");
+    return PGABB_OK;
+}
+
+PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!count) return set_err(PGABB_EINVAL, "count is NULL");
+    *count = PGABB_COUNT_ERROR;
+    const pgabb_tc_options o = opts ? *opts : default_options();
+    const pgabb_status st = check_options(o);
+    if (st != PGABB_OK) return st;
     PGABB_TRY
     *count = count_graph(g, o);
+    return set_ok();
+    PGABB_CATCH
+}
+
+static constexpr int32_t kMaxShards = 4096;
+
+PGABB_API pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of) {
+    if (!g || !shard_of) return set_err(PGABB_EINVAL, "NULL argument");
+    if (num_shards < 1 || num_shards > kMaxShards) return set_err(PGABB_EINVAL, "num_shards outside [1, 4096]");
+    if (g->p == 0) return set_err(PGABB_ESTATE, "graph is not partitioned");
+    PGABB_TRY
+    const std::vector<int32_t> of = task_shards(g, num_shards);
+    std::memcpy(shard_of, of.data(), sizeof(int32_t) * of.size());
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_options *opts, int32_t shard,
+                                            int32_t num_shards, uint64_t *count) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!count) return set_err(PGABB_EINVAL, "count is NULL");
+    *count = PGABB_COUNT_ERROR;
+    if (num_shards < 1 || num_shards > kMaxShards) return set_err(PGABB_EINVAL, "num_shards outside [1, 4096]");
+    if (shard < 0 || shard >= num_shards) return set_err(PGABB_EINVAL, "shard outside [0, num_shards)");
+    const pgabb_tc_options o = opts ? *opts : default_options();
+    const pgabb_status st = check_options(o);
+    if (st != PGABB_OK) return st;
+    PGABB_TRY
+    *count = count_shard(g, o, shard, num_shards);
     return set_ok();
     PGABB_CATCH
 }

@@ -11,6 +11,10 @@
 // Streamed path (graph blocks held in pinned host memory): see streamer.hip.
 #include <algorithm>
 #include <chrono>
+#include <cstring>
+#include <functional>
+#include <queue>
+#include <vector>
 
 #include "common.hpp"
 #include "count.hpp"
@@ -288,7 +292,9 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     a.total = pre[T];
     a.counts = dcnt.get();
     a.next = dcnt.get() + T;
-    a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T], walked_entries(g, orient));
+    // walked entries of these tasks, at the graph's mean per item
+    const uint64_t walked = static_cast<uint64_t>(static_cast<double>(walked_entries(g, orient)) * g->task_share);
+    a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T], walked);
     a.orient = orient;
     const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
@@ -324,6 +330,99 @@ uint64_t count_graph(pgabb_graph *g, const pgabb_tc_options &opt) {
         g->task_counts.clear();
     }
     g->t_count_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return total;
+}
+
+// Entries a task's walk reads plus those its items stage, estimated from
+// block sizes (a list's length taken as its block's mean): a column walk
+// reads A_ik[u] for every entry (u, v) of A_ij and stages A_jk[v] once per
+// column v; a row walk reads A_jk[v] per entry and stages A_ik[u] per row.
+int64_t task_work_estimate(const pgabb_graph *g, const Task &t, int orient) {
+    const BlockInfo &ij = g->blocks[t.bij], &ik = g->blocks[t.bik], &jk = g->blocks[t.bjk];
+    const double mean_ik = static_cast<double>(ik.nnz) / static_cast<double>(std::max(ik.nrows, 1));
+    const double mean_jk = static_cast<double>(jk.nnz) / static_cast<double>(std::max(jk.nrows, 1));
+    const double walk = static_cast<double>(ij.nnz) * (orient == kOrientCol ? mean_ik : mean_jk);
+    const double stage = orient == kOrientCol ? static_cast<double>(ij.ncols) * mean_jk
+                                              : static_cast<double>(ij.nrows) * mean_ik;
+    return 1 + static_cast<int64_t>(walk) + static_cast<int64_t>(stage);
+}
+
+// Tasks are independent (Section 4.1), so a count splits over devices by
+// task.  Tasks sharing their edge block A_ij form one group, so that a
+// device reads each edge block it holds for all of its k; groups are dealt
+// by longest processing time on the estimated work of the graph's default
+// walk: heaviest first (ties: the group whose first task comes first), each
+// to the least loaded shard (ties: lowest index).  The paper's task weight
+// (edges of the block-list) balances edges, not work: on skewed graphs the
+// walk of a task grows with the mean row length of the walked block.
+std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards) {
+    const int32_t T = static_cast<int32_t>(g->tasks.size());
+    const size_t nb = g->blocks.size();
+    pgabb_tc_options dflt;
+    std::memset(&dflt, 0, sizeof dflt);
+    const int orient = orient_of_option(dflt, g);
+    std::vector<int64_t> gw(nb, 0);
+    std::vector<int32_t> first(nb, -1);
+    for (int32_t t = 0; t < T; ++t) {
+        const Task &k = g->tasks[t];
+        gw[k.bij] += task_work_estimate(g, k, orient);
+        if (first[k.bij] < 0) first[k.bij] = t;
+    }
+    std::vector<int32_t> groups;
+    for (size_t b = 0; b < nb; ++b)
+        if (first[b] >= 0) groups.push_back(static_cast<int32_t>(b));
+    std::sort(groups.begin(), groups.end(), [&](int32_t a, int32_t b) {
+        return gw[a] != gw[b] ? gw[a] > gw[b] : first[a] < first[b];
+    });
+    using Load = std::pair<int64_t, int32_t>;  // (weight so far, shard)
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int32_t s = 0; s < nshards; ++s) heap.push({0, s});
+    std::vector<int32_t> group_shard(nb, -1);
+    for (int32_t b : groups) {
+        Load l = heap.top();
+        heap.pop();
+        group_shard[b] = l.second;
+        l.first += gw[b];
+        heap.push(l);
+    }
+    std::vector<int32_t> of(T);
+    for (int32_t t = 0; t < T; ++t) of[t] = group_shard[g->tasks[t].bij];
+    return of;
+}
+
+uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards) {
+    if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    const std::vector<int32_t> of = task_shards(g, nshards);
+    const int orient = orient_of_option(opt, g);
+    std::vector<int32_t> idx;  // the shard's tasks, heaviest first as in the full list
+    int64_t items = 0, all_items = 0;
+    for (size_t t = 0; t < of.size(); ++t) {
+        const int64_t it = task_items(g, g->tasks[t], orient);
+        all_items += it;
+        if (of[t] == shard) {
+            idx.push_back(static_cast<int32_t>(t));
+            items += it;
+        }
+    }
+    std::vector<Task> all;
+    all.swap(g->tasks);
+    for (int32_t t : idx) g->tasks.push_back(all[t]);
+    g->task_share = all_items ? static_cast<double>(items) / static_cast<double>(all_items) : 1.0;
+    uint64_t total = 0;
+    std::vector<uint64_t> sub;
+    try {
+        total = count_graph(g, opt);
+        sub.swap(g->task_counts);
+    } catch (...) {
+        g->tasks.swap(all);
+        g->task_share = 1.0;
+        g->task_counts.assign(g->tasks.size(), 0);
+        throw;
+    }
+    g->tasks.swap(all);
+    g->task_share = 1.0;
+    g->task_counts.assign(g->tasks.size(), 0);
+    for (size_t q = 0; q < idx.size() && q < sub.size(); ++q) g->task_counts[idx[q]] = sub[q];
     return total;
 }
 

@@ -37,6 +37,8 @@ struct BlockInfo {
     int32_t nitems = 0;   // row work items
     int32_t ncitems = 0;  // column work items
     int32_t max_row = 0;  // longest row of the block
+    int32_t nrows = 0;    // non-empty rows
+    int32_t ncols = 0;    // non-empty columns
     int64_t nnz = 0;
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
@@ -95,6 +97,8 @@ struct pgabb_graph {
     uint64_t probe_work = 0;      // sum over oriented edges (x, y) of |N+(y)|
     uint64_t probe_work_col = 0;  // entries column walks read under the current cuts
     int64_t walked_columns = 0;   // the last count walked columns
+    double task_share = 1.0;      // work items of `tasks` over those of all
+                                  // tasks (below 1 while a shard is counted)
 
     pgabb::DArray<int64_t> row_off;  // n + 1
     pgabb::DArray<int32_t> col;      // m'
@@ -131,5 +135,9 @@ hipStream_t library_stream();
 void build_graph(pgabb_graph *g, const int32_t *src_dev, const int32_t *dst_dev, int64_t m);
 void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t *cuts_host);
 uint64_t count_graph(pgabb_graph *g, const pgabb_tc_options &opt);
+// Shard of each task when the tasks are split over nshards devices.
+std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards);
+// Count only the tasks task_shards deals to `shard`.
+uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards);
 
 }  // namespace pgabb

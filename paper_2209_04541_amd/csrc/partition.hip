@@ -281,28 +281,43 @@ __device__ __forceinline__ void for_long_rows(const int64_t *__restrict__ row_of
     }
 }
 
-// Per block (i, j): number of entries and number of work items (each row's
-// run split into pieces of at most kSplitV entries).  Each workgroup
-// accumulates in LDS and flushes its non-zero counters.
+// Index of the stripe pair {a, b} among the p (p + 1) / 2 unordered pairs.
+__device__ __forceinline__ int pair_index(int a, int b, int p) {
+    const int lo = min(a, b), hi = max(a, b);
+    return lo * (2 * p - lo + 1) / 2 + (hi - lo);
+}
+
+constexpr int kMaxPairs = kMaxP * (kMaxP + 1) / 2;
+
+// Per block (i, j): number of entries, of non-empty rows and of work items
+// (each row's run split into pieces of at most kSplitV entries).  A pass
+// sees blocks on one side of the diagonal only (upper: i <= j, the oriented
+// graph; else i >= j, its transpose), so each workgroup accumulates per
+// unordered stripe pair in LDS and flushes its non-zero counters to the
+// p x p arrays.
 template <bool LONG>
 __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ row_off,
                                                    const int32_t *__restrict__ col, int32_t n,
                                                    const CutTable *__restrict__ ctp, const int64_t *__restrict__ list,
-                                                   const unsigned int *__restrict__ count,
+                                                   const unsigned int *__restrict__ count, bool upper,
                                                    unsigned long long *__restrict__ nnz,
                                                    unsigned int *__restrict__ items,
+                                                   unsigned int *__restrict__ rows,
                                                    unsigned long long *__restrict__ walk,
                                                    unsigned int *__restrict__ maxrun) {
-    __shared__ unsigned int s_nnz[kMaxP * kMaxP];
-    __shared__ unsigned int s_items[kMaxP * kMaxP];
-    __shared__ unsigned int s_max[kMaxP * kMaxP];
+    __shared__ unsigned int s_nnz[kMaxPairs];
+    __shared__ unsigned int s_items[kMaxPairs];
+    __shared__ unsigned int s_rows[kMaxPairs];
+    __shared__ unsigned int s_max[kMaxPairs];
     __shared__ int32_t s_c[kMaxP + 1];
     __shared__ unsigned long long s_walk;
     const int p = ctp->p;
     const int pp = p * p;
-    for (int q = threadIdx.x; q < pp; q += B) {
+    const int npairs = p * (p + 1) / 2;
+    for (int q = threadIdx.x; q < npairs; q += B) {
         s_nnz[q] = 0;
         s_items[q] = 0;
+        s_rows[q] = 0;
         s_max[q] = 0;
     }
     for (int q = threadIdx.x; q <= p; q += B) s_c[q] = ctp->c[q];
@@ -316,9 +331,11 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
     auto add = [&](int32_t si, int32_t j, int64_t lo, int64_t hi) {
         const int64_t cnt = hi - lo;
         if (cnt > 0) {
-            atomicAdd(&s_nnz[si * p + j], static_cast<unsigned int>(cnt));
-            atomicAdd(&s_items[si * p + j], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
-            atomicMax(&s_max[si * p + j], static_cast<unsigned int>(cnt));
+            const int t = pair_index(si, j, p);
+            atomicAdd(&s_nnz[t], static_cast<unsigned int>(cnt));
+            atomicAdd(&s_items[t], static_cast<unsigned int>((cnt + kSplitV - 1) / kSplitV));
+            atomicAdd(&s_rows[t], 1u);
+            atomicMax(&s_max[t], static_cast<unsigned int>(cnt));
             my_walk += static_cast<unsigned long long>(cnt) * static_cast<unsigned long long>(row_end - lo);
         }
     };
@@ -341,10 +358,14 @@ __global__ __launch_bounds__(B) void k_block_sizes(const int64_t *__restrict__ r
     }
     __syncthreads();
     for (int q = threadIdx.x; q < pp; q += B) {
-        if (s_nnz[q]) {
-            atomicAdd(&nnz[q], static_cast<unsigned long long>(s_nnz[q]));
-            atomicAdd(&items[q], s_items[q]);
-            if (maxrun) atomicMax(&maxrun[q], s_max[q]);
+        const int a = q / p, b = q - a * p;
+        if (upper ? a > b : a < b) continue;
+        const int t = pair_index(a, b, p);
+        if (s_nnz[t]) {
+            atomicAdd(&nnz[q], static_cast<unsigned long long>(s_nnz[t]));
+            atomicAdd(&items[q], s_items[t]);
+            atomicAdd(&rows[q], s_rows[t]);
+            if (maxrun) atomicMax(&maxrun[q], s_max[t]);
         }
     }
     if (walk && threadIdx.x == 0 && s_walk) atomicAdd(walk, s_walk);
@@ -613,21 +634,24 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         // ---- block sizes, forward (entries, row items) and reversed (column items)
         // one buffer, one clear, one copy back: nnz[pp] nnz_r[pp] (u64) |
         // items[pp] items_r[pp] (u32) | walked entries of column walks (u64) |
-        // longest row run per block (u32)
-        const size_t nsz = 3 * pp + 1 + (pp + 1) / 2;
+        // longest row run per block, non-empty rows, non-empty rows of the
+        // transposes (u32 each)
+        const size_t nsz = 3 * pp + 1 + (3 * pp + 1) / 2;
         DArray<unsigned long long> dsz(nsz, s);
         PGABB_HIP(hipMemsetAsync(dsz.get(), 0, nsz * sizeof(unsigned long long), s));
         unsigned long long *dnnz = dsz.get(), *dnnz_r = dnnz + pp, *dwalk = dsz.get() + 3 * pp;
         unsigned int *ditems = reinterpret_cast<unsigned int *>(dnnz_r + pp), *ditems_r = ditems + pp;
         unsigned int *dmax = reinterpret_cast<unsigned int *>(dwalk + 1);
+        unsigned int *drows = dmax + pp, *drows_r = drows + pp;
         k_block_sizes<false><<<lgrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ctp, long_f.get(), nlong.get(),
-                                                  dnnz, ditems, dwalk, dmax);
+                                                  true, dnnz, ditems, drows, dwalk, dmax);
         k_block_sizes<true><<<kLongGrid, B, 0, s>>>(g->row_off.get(), g->col.get(), n, ctp, long_f.get(), nlong.get(),
-                                                     dnnz, ditems, dwalk, dmax);
+                                                     true, dnnz, ditems, drows, dwalk, dmax);
         k_block_sizes<false><<<lgrid, B, 0, s>>>(rev_off.get(), rev_col, n, ctp, long_r.get(), nlong.get() + 1,
-                                                  dnnz_r, ditems_r, nullptr, nullptr);
+                                                  false, dnnz_r, ditems_r, drows_r, nullptr, nullptr);
         k_block_sizes<true><<<kLongGrid, B, 0, s>>>(rev_off.get(), rev_col, n, ctp, long_r.get(),
-                                                     nlong.get() + 1, dnnz_r, ditems_r, nullptr, nullptr);
+                                                     nlong.get() + 1, false, dnnz_r, ditems_r, drows_r, nullptr,
+                                                     nullptr);
         PGABB_HIP(hipGetLastError());
         Staged<unsigned long long> hsz(nsz, s);
         PGABB_HIP(hipMemcpyAsync(hsz.get(), dsz.get(), hsz.bytes(), hipMemcpyDeviceToHost, s));
@@ -639,6 +663,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         const unsigned int *hitems = reinterpret_cast<const unsigned int *>(hsz.get() + 2 * pp);
         const unsigned int *hitems_r = hitems + pp;
         const unsigned int *hmax = reinterpret_cast<const unsigned int *>(hsz.get() + 3 * pp + 1);
+        const unsigned int *hrows = hmax + pp, *hrows_r = hrows + pp;
         g->probe_work_col = hsz[3 * pp];
 
         // ---- block table (row-major block order) and chunk layout
@@ -656,6 +681,8 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 bi.ncitems = static_cast<int32_t>(hitems_r[static_cast<size_t>(j) * p + i]);
                 bi.nnz = static_cast<int64_t>(hnnz[q]);
                 bi.max_row = static_cast<int32_t>(hmax[q]);
+                bi.nrows = static_cast<int32_t>(hrows[q]);
+                bi.ncols = static_cast<int32_t>(hrows_r[static_cast<size_t>(j) * p + i]);
                 bi.chunk_off = g->arena_words;
                 bi.chunk_len = bi.end() - bi.chunk_off;
                 g->arena_words += bi.chunk_len;

@@ -164,8 +164,15 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     const int32_t T = static_cast<int32_t>(g->tasks.size());
     const int32_t nblk = static_cast<int32_t>(g->blocks.size());
 
+    // bytes of the blocks these tasks read (all of them for a whole count;
+    // fewer for one shard's tasks)
     uint64_t total_bytes = 0;
-    for (const BlockInfo &b : g->blocks) total_bytes += chunk_bytes(b);
+    {
+        std::vector<char> used(nblk, 0);
+        for (const Task &t : g->tasks) used[t.bij] = used[t.bik] = used[t.bjk] = 1;
+        for (int32_t b = 0; b < nblk; ++b)
+            if (used[b]) total_bytes += chunk_bytes(g->blocks[b]);
+    }
     uint64_t cap = opt.device_cap_bytes ? opt.device_cap_bytes : total_bytes;
     cap = std::min(cap, total_bytes);
     cap = cap / kAlign * kAlign;

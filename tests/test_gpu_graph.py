@@ -74,7 +74,7 @@ def test_csr_bit_identical_to_oracle(order_by_id):
     assert info["probe_work"] == oracle.probe_work(n, row_off, col)
 
 
-@pytest.mark.parametrize("p", [2, 3, 5, 8, 13])
+@pytest.mark.parametrize("p", [2, 3, 5, 8, 13, 33, 64])
 def test_task_counts_equal_oracle_blocks(p):
     n, s, d = gen.rmat(12, 12, gen.seed(95, p))
     _, _, rk, row_off, col = oracle.oriented_csr(n, s, d)
