@@ -8,8 +8,9 @@ this package imports nothing from it: the two share no code.
 computes the triangle count of an undirected graph by its plain definition in
 the oriented form the paper uses (PGAbB Section 3.6 for the problem and the
 per-edge common-neighbour count over a block-list, Section 5.1 for cleaning,
-Section 5.4 for degree ordering and the oriented half of the edges).  This
-module is a thin ctypes wrapper around it.
+Section 5.4 for degree ordering and the oriented half of the edges), and the
+triangles containing each edge (edge support).  This module is a thin ctypes
+wrapper around it.
 """
 from __future__ import annotations
 
@@ -61,6 +62,8 @@ def _load():
         L.oracle_probe_work.argtypes = [ctypes.c_int32, vp, vp]
         L.oracle_probe_work_col.restype = ctypes.c_uint64
         L.oracle_probe_work_col.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
+        L.oracle_edge_support.restype = None
+        L.oracle_edge_support.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -129,6 +132,17 @@ def count_csr(n: int, row_off: np.ndarray, col: np.ndarray) -> int:
     if len(col) == 0:
         col = np.zeros(1, dtype=np.int32)
     return int(_load().oracle_count(n, _p(row_off), _p(col)))
+
+
+def edge_support(n: int, row_off: np.ndarray, col: np.ndarray) -> np.ndarray:
+    """uint32 triangles containing each oriented edge, in CSR order."""
+    row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    m = int(row_off[n]) if n > 0 else 0
+    out = np.zeros(max(m, 1), dtype=np.uint32)
+    if m:
+        _load().oracle_edge_support(n, _p(row_off), _p(col), _p(out))
+    return out[:m]
 
 
 def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:

@@ -162,6 +162,41 @@ uint64_t oracle_count(int32_t n, const int64_t *row_off, const int32_t *col)
     return total;
 }
 
+/* Per-edge triangle counts (edge support; the per-edge quantity behind the
+ * clustering coefficients of Section 1 and the peeling of k-truss named in
+ * Section 3.2).  For the oriented edge at CSR position e, support[e] is the
+ * number of triangles containing that edge.  Evaluated from the triangles
+ * themselves: every triangle r(a) < r(b) < r(c) is found once, at edge (a, b)
+ * with common out-neighbour c (the merge of step 5), and adds one to each of
+ * its three edges (a, b), (a, c) and (b, c), located by their positions in
+ * the merged lists.  Sequential, so the increments need no atomics. */
+void oracle_edge_support(int32_t n, const int64_t *row_off, const int32_t *col, uint32_t *support)
+{
+    memset(support, 0, sizeof(uint32_t) * (size_t)row_off[n]);
+    for (int32_t a = 0; a < n; ++a) {
+        const int64_t a0 = row_off[a], da = row_off[a + 1] - a0;
+        for (int64_t t = 0; t < da; ++t) {
+            const int32_t b = col[a0 + t];
+            const int64_t b0 = row_off[b], db = row_off[b + 1] - b0;
+            int64_t i = 0, j = 0;
+            while (i < da && j < db) {
+                const int32_t x = col[a0 + i], y = col[b0 + j];
+                if (x < y) {
+                    ++i;
+                } else if (y < x) {
+                    ++j;
+                } else {           /* c = x: triangle (a, b, c) */
+                    ++support[a0 + t];  /* (a, b) */
+                    ++support[a0 + i];  /* (a, c) */
+                    ++support[b0 + j];  /* (b, c) */
+                    ++i;
+                    ++j;
+                }
+            }
+        }
+    }
+}
+
 /* Number of oracle threads an OpenMP build uses (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -159,3 +159,30 @@ def brute_force(n, src, dst):
         if A[a, b] and A[b, c] and A[a, c]:
             t += 1
     return t
+
+
+def support_by_pairs(n, src, dst, rank, row_off, col):
+    """Oracle-independent per-edge expectations are compared by vertex pair:
+    map each oriented CSR edge (ranks x, y) to its input-id pair (a, b) with
+    a < b."""
+    inv = np.empty(n, np.int64)
+    inv[np.asarray(rank, np.int64)] = np.arange(n)
+    rows = np.repeat(np.arange(n), np.diff(row_off))
+    a, b = inv[rows], inv[np.asarray(col, np.int64)]
+    return np.minimum(a, b), np.maximum(a, b)
+
+
+def support_brute_force(n, src, dst):
+    """{(a, b): triangles containing edge {a, b}} by enumerating every vertex
+    triple against an adjacency matrix (n <= ~80)."""
+    A = np.zeros((n, n), dtype=bool)
+    for a, b in zip(src, dst):
+        if a != b:
+            A[a, b] = A[b, a] = True
+    sup = {(a, b): 0 for a, b in zip(*np.nonzero(np.triu(A)))}
+    for a, b, c in itertools.combinations(range(n), 3):
+        if A[a, b] and A[b, c] and A[a, c]:
+            sup[(a, b)] += 1
+            sup[(a, c)] += 1
+            sup[(b, c)] += 1
+    return sup

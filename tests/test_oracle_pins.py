@@ -273,3 +273,53 @@ def test_block_workload_sparse_identity():
     assert t == gold["triangles"]
     assert len(k) == gold["m"]
     assert int((deg == 0).sum()) == gold["isolated"]
+
+
+# ---------------------------------------------------------------- edge support
+
+def _support(n, s, d):
+    _, _, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    sup = oracle.edge_support(n, row_off, col)
+    a, b = graphs.support_by_pairs(n, s, d, rk, row_off, col)
+    return {(int(x), int(y)): int(v) for x, y, v in zip(a, b, sup)}, row_off, col
+
+
+@pytest.mark.parametrize("n,density,seed", [(9, 0.5, 1), (23, 0.3, 2), (40, 0.2, 3), (60, 0.5, 4), (1, 0, 5)])
+def test_edge_support_brute_force(n, density, seed):
+    rng = np.random.default_rng(seed)
+    pairs = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < density]
+    n_, s, d = graphs.messy(*graphs._edges(pairs, n), seed=seed)
+    got, _, _ = _support(n_, s, d)
+    assert got == graphs.support_brute_force(n_, s, d)
+
+
+def test_edge_support_dense_identity():
+    """support({a, b}) = (A A)[a, b] for every edge: the common neighbours."""
+    for n, s, d in (gen.er(300, 2500, gen.seed(41, 0)), gen.rmat(9, 16, gen.seed(41, 1)),
+                    gen.rgg(400, 9.0, gen.seed(41, 2))):
+        A = np.zeros((n, n), np.int64)
+        m = s != d
+        A[s[m], d[m]] = 1
+        A[d[m], s[m]] = 1
+        A2 = A @ A
+        got, row_off, col = _support(n, s, d)
+        assert len(got) == int(A.sum()) // 2
+        assert all(A2[a, b] == v for (a, b), v in got.items())
+        assert sum(got.values()) == 3 * oracle.count_csr(n, row_off, col)
+
+
+def test_edge_support_closed_forms():
+    (n, s, d), _ = graphs.complete(12)
+    assert set(_support(n, s, d)[0].values()) == {10}
+    (n, s, d), _ = graphs.complete_bipartite(4, 5)
+    assert set(_support(n, s, d)[0].values()) == {0}
+    (n, s, d), _ = graphs.wheel(9)  # spokes lie in 2 triangles, rim edges in 1
+    assert all(v == (2 if a == 0 else 1) for (a, b), v in _support(n, s, d)[0].items())
+    (n, s, d), _ = graphs.friendship(7)
+    assert set(_support(n, s, d)[0].values()) == {1}
+    (n, s, d), k = graphs.book(6)
+    assert all(v == (k if (a, b) == (0, 1) else 1) for (a, b), v in _support(n, s, d)[0].items())
+    (n, s, d), _ = graphs.complete_tripartite(2, 3, 4)  # an edge between two parts: size of the third
+    part = lambda x: 0 if x < 2 else (1 if x < 5 else 2)
+    size = [2, 3, 4]
+    assert all(v == size[3 - part(a) - part(b)] for (a, b), v in _support(n, s, d)[0].items())
