@@ -6,7 +6,7 @@ R-MAT scale-20 edge list (16.8 M int32 pairs already resident in HBM):
 clean + degree-rank + orient (CSR build), symmetric 8 x 8 partition into
 blocks and block-list tasks, and the triangle count returned to the host as a
 uint64.  `value` is m' (the graph's distinct undirected edges) divided by the
-step time.  Other workloads (--workload plain|ooc|batch|served) print their
+step time.  Other workloads (--workload plain|ooc|batch|served|support) print their
 own line; they are not the default.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on
@@ -31,23 +31,27 @@ KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_a
                   "paper_2209_04541_amd/csrc/wave.hpp", "paper_2209_04541_amd/csrc/count.hpp"]
 
 
-def kernel_digest():
+# device code of the edge-support kernel
+SUPPORT_SOURCES = ["paper_2209_04541_amd/csrc/support.hip", "paper_2209_04541_amd/csrc/wave.hpp"]
+
+
+def kernel_digest(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of the counting kernel from the committed
-    rocprofv3 counter summary, or None when the kernel changed since."""
+def measured_traffic(name, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None when the kernel changed since."""
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
     except OSError:
         return None
-    if t.get("kernel_digest") != kernel_digest():
+    if t.get("kernel_digest") != kernel_digest(sources):
         return None
     return t.get("bytes_per_launch")
 
@@ -257,6 +261,96 @@ def bench_block(args):
                      "%dx%d blocks" % (args.scale, args.p or 8, args.p or 8),
                      "traffic_tc_block_rmat20_p8.json",
                      cpu_sample=oracle_full_pass(n, s, d, m_est, "the whole R-MAT scale-%d graph" % args.scale))
+
+
+def bench_support(args):
+    """Triangles of every edge on R-MAT scale 20: per step, build the
+    oriented graph from device-resident edges and write each edge's count
+    into a device array."""
+    import numpy as np
+    import torch
+
+    import paper_2209_04541_amd as P
+    from paper_2209_04541_amd import gen
+
+    n, s, d = gen.block_graph()
+    ds = torch.from_numpy(s).cuda()
+    dd = torch.from_numpy(d).cuda()
+    torch.cuda.synchronize()
+
+    def step(keep=False):
+        g = P.Graph(n, ds, dd)
+        out = torch.empty(g.info()["m"], dtype=torch.int32, device="cuda")
+        _, tri = g.edge_support(out)
+        info = g.info()
+        if keep:
+            return g, out, tri, info
+        g.close()
+        return None, None, tri, info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos, tris, step_ms = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        _, _, tri, info = step()
+        step_ms.append((time.perf_counter() - a) * 1e3)
+        tris.append(tri)
+        infos.append(info)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+
+    g, out, tri, info = step(keep=True)
+    row_off, col, _ = g.export_csr()
+    sup = out.cpu().numpy().view(np.uint32)
+    g.close()
+    m = info["m"]
+    T = tri
+    # walked entries: for every edge (a, b), the entries of N+(a) after b
+    deg = np.diff(row_off).astype(np.int64)
+    walked = int((deg * (deg - 1) // 2).sum())
+    kernel_ms = float(np.mean([i["t_kernel_ms"] for i in infos]))
+    # algorithmic bytes: walked entries (4 B each); per edge, as an in-edge
+    # its CSR position, row and row end (16 B) and as a staged entry its
+    # value (4 B), and the read and write of its two counter flushes (16 B);
+    # per triangle one atomic on the walked edge (8 B: read and write)
+    alg = 4 * walked + 36 * m + 8 * T
+    achieved = alg / (kernel_ms / 1e3) / 1e9
+    gold = golden("block")
+    out_line = base_line(args, m / (ms / 1e3), "edges/s", ms, {
+        "workload": "edge support (triangles per edge), R-MAT scale 20, edge factor 16, "
+                    "(a,b,c,d)=(.57,.19,.19,.05), seed (2,0)", "n": n, "m_input": len(s), "m": m})
+    out_line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": measured_traffic("traffic_edge_support_rmat20.json", SUPPORT_SOURCES)}
+    out_line.update({
+        "triangles": T,
+        "parity": all(t == gold["triangles"] for t in tris) and int(sup.sum(dtype=np.uint64)) == 3 * T,
+        "step_ms_p50": pct(step_ms, 50), "step_ms_p99": pct(step_ms, 99),
+        "t_build_ms": float(np.mean([i["t_build_ms"] for i in infos])),
+        "t_support_ms": float(np.mean([i["t_count_ms"] for i in infos])),
+        "t_kernel_ms": kernel_ms,
+        "kernel_edges_per_s": m / (kernel_ms / 1e3),
+        "walked_entries": walked,
+        "algorithmic_bytes_per_launch": alg,
+        "max_support": int(sup.max()) if m else 0,
+    })
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        _, _, _, ro, cl = oracle.oriented_csr(n, s, d)
+        t_build = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        want = oracle.edge_support(n, ro, cl)
+        dt = time.perf_counter() - t1
+        out_line["cpu_baseline"] = {
+            "value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "the oracle's per-edge counts over the whole graph, sequential (%.1f s; its build "
+                      "took %.1f s on %d threads)" % (dt, t_build, oracle.threads())}
+        out_line["parity"] = out_line["parity"] and bool(np.array_equal(want, sup))
+    return out_line
 
 
 def bench_plain(args):
@@ -516,7 +610,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="block", choices=["block", "plain", "ooc", "batch", "served", "copy"])
+    ap.add_argument("--workload", default="block",
+                    choices=["block", "plain", "ooc", "batch", "served", "support", "copy"])
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0)
@@ -543,7 +638,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     fn = {"block": bench_block, "plain": bench_plain, "ooc": bench_ooc, "batch": bench_batch,
-          "served": bench_served, "copy": bench_copy}[args.workload]
+          "served": bench_served, "support": bench_support, "copy": bench_copy}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

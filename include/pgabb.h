@@ -261,6 +261,28 @@ pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, i
 pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_options *opts, int32_t shard,
                                   int32_t num_shards, uint64_t *count);
 
+/*
+ * Triangles containing each edge (edge support; the per-edge counts behind
+ * clustering coefficients, PGAbB Section 1, and k-truss peeling, Section
+ * 3.2), from the intersections of Section 3.6 over the whole oriented graph
+ * as one block (independent of pgabb_partition).
+ *   support   : m' uint32 entries; support[e] for the oriented edge at
+ *               position e of the CSR that pgabb_graph_export_csr returns
+ *               (row x = rank, col[e] = the higher-ranked endpoint).  Host
+ *               memory, or device memory with PGABB_SUPPORT_ON_DEVICE (the
+ *               call runs on the graph's stream: finish other streams'
+ *               work on it first); complete when the call returns.  May be
+ *               NULL only when m' = 0.
+ *   flags     : 0 or PGABB_SUPPORT_ON_DEVICE
+ *   triangles : optional; the triangle count (the sum of support over
+ *               three)
+ * pgabb_graph_info_get then reports the call's time (t_count_ms), kernel
+ * time and launches.  Errors: EINVAL (NULL graph or support, unknown
+ * flags), ENOMEM, EDEVICE.
+ */
+#define PGABB_SUPPORT_ON_DEVICE 0x1u
+pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t flags, uint64_t *triangles);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 

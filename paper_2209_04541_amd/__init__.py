@@ -28,6 +28,7 @@ CUT_NNZ, CUT_UNIFORM = 0, 1
 KERNEL_AUTO, KERNEL_HASH, KERNEL_BITMAP, KERNEL_SEARCH = 0, 1, 2, 3
 OPT_STREAM = 0x1
 OPT_ROWS = 0x8
+SUPPORT_ON_DEVICE = 0x1
 OPT_COLS = 0x10
 
 
@@ -95,6 +96,7 @@ def lib():
             "pgabb_graph_cuts": (st, [vp, vp]),
             "pgabb_graph_task_counts": (st, [vp, vp, vp]),
             "pgabb_graph_task_shards": (st, [vp, i32, vp]),
+            "pgabb_tc_edge_support": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
@@ -241,6 +243,29 @@ class Graph:
         _check(lib().pgabb_tc_count_shard(self._h, ctypes.byref(opts) if opts is not None else None,
                                           int(shard), int(num_shards), ctypes.byref(c)))
         return int(c.value)
+
+    def edge_support(self, out=None):
+        """Triangles containing each oriented edge (CSR order of export_csr)
+        and the triangle count.  out: None (a new numpy uint32 array), a
+        numpy uint32 array or a CUDA torch int32/uint32 tensor of m'
+        entries (complete when the call returns)."""
+        m = self.info()["m"]
+        tri = ctypes.c_uint64()
+        if out is None:
+            out = np.empty(m, np.uint32)
+        if isinstance(out, np.ndarray):
+            if out.dtype != np.uint32 or out.size != m or not out.flags.c_contiguous:
+                raise ValueError("out must be a contiguous uint32 array of m' entries")
+            _check(lib().pgabb_tc_edge_support(self._h, ctypes.c_void_p(out.ctypes.data) if m else None, 0,
+                                               ctypes.byref(tri)))
+        else:
+            if out.numel() != m or out.element_size() != 4 or not out.is_contiguous() or not out.is_cuda:
+                raise ValueError("out must be a contiguous 4-byte CUDA tensor of m' entries")
+            import torch
+            torch.cuda.current_stream().synchronize()  # torch's pending writes to out come first
+            _check(lib().pgabb_tc_edge_support(self._h, ctypes.c_void_p(out.data_ptr()) if m else None,
+                                               SUPPORT_ON_DEVICE, ctypes.byref(tri)))
+        return out, int(tri.value)
 
     def task_shards(self, num_shards):
         """Shard of each task (order of task_counts) for num_shards devices."""

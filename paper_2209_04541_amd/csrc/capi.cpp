@@ -222,6 +222,18 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t flags,
+                                             uint64_t *triangles) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!support && g->m > 0) return set_err(PGABB_EINVAL, "support is NULL");
+    if (flags & ~PGABB_SUPPORT_ON_DEVICE) return set_err(PGABB_EINVAL, "unknown flag bits");
+    PGABB_TRY
+    const uint64_t t = edge_support(g, support, (flags & PGABB_SUPPORT_ON_DEVICE) != 0);
+    if (triangles) *triangles = t;
+    return set_ok();
+    PGABB_CATCH
+}
+
 static constexpr int32_t kMaxShards = 4096;
 
 PGABB_API pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of) {
