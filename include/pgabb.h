@@ -278,7 +278,8 @@ pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_options *opts, 
  *               three)
  * pgabb_graph_info_get then reports the call's time (t_count_ms), kernel
  * time and launches.  Errors: EINVAL (NULL graph or support, unknown
- * flags), ENOMEM, EDEVICE.
+ * flags, m' >= 2^32: in-edges are indexed by 32-bit CSR positions),
+ * ENOMEM, EDEVICE.
  */
 #define PGABB_SUPPORT_ON_DEVICE 0x1u
 pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t flags, uint64_t *triangles);

@@ -9,8 +9,8 @@ computes the triangle count of an undirected graph by its plain definition in
 the oriented form the paper uses (PGAbB Section 3.6 for the problem and the
 per-edge common-neighbour count over a block-list, Section 5.1 for cleaning,
 Section 5.4 for degree ordering and the oriented half of the edges), and the
-triangles containing each edge (edge support).  This module is a thin ctypes
-wrapper around it.
+triangles containing each edge (edge support) and each vertex.  This module is
+a thin ctypes wrapper around it.
 """
 from __future__ import annotations
 
@@ -64,6 +64,8 @@ def _load():
         L.oracle_probe_work_col.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
         L.oracle_edge_support.restype = None
         L.oracle_edge_support.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.oracle_vertex_counts.restype = None
+        L.oracle_vertex_counts.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -143,6 +145,16 @@ def edge_support(n: int, row_off: np.ndarray, col: np.ndarray) -> np.ndarray:
     if m:
         _load().oracle_edge_support(n, _p(row_off), _p(col), _p(out))
     return out[:m]
+
+
+def vertex_counts(n: int, src, dst, mode: int = 0) -> np.ndarray:
+    """uint64 triangles at each vertex, indexed by input id."""
+    _, _, rnk, row_off, col = oriented_csr(n, src, dst, mode)
+    t = np.zeros(max(n, 1), dtype=np.uint64)
+    if n > 0:
+        c = col if len(col) else np.zeros(1, dtype=np.int32)
+        _load().oracle_vertex_counts(n, _p(row_off), _p(np.ascontiguousarray(c, dtype=np.int32)), _p(t))
+    return t[:n][rnk] if n > 0 else t[:0]
 
 
 def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:

@@ -197,6 +197,38 @@ void oracle_edge_support(int32_t n, const int64_t *row_off, const int32_t *col, 
     }
 }
 
+/* Per-vertex triangle counts (the numerator of the local clustering
+ * coefficient, Section 1): t[x] for rank x is the number of triangles with x
+ * as a vertex.  Every triangle r(a) < r(b) < r(c), found once as in step 5,
+ * adds one to each of a, b and c.  Sequential. */
+void oracle_vertex_counts(int32_t n, const int64_t *row_off, const int32_t *col, uint64_t *t)
+{
+    memset(t, 0, sizeof(uint64_t) * (size_t)n);
+    for (int32_t a = 0; a < n; ++a) {
+        const int32_t *na = col + row_off[a];
+        const int64_t da = row_off[a + 1] - row_off[a];
+        for (int64_t s = 0; s < da; ++s) {
+            const int32_t b = na[s];
+            const int32_t *nb = col + row_off[b];
+            const int64_t db = row_off[b + 1] - row_off[b];
+            int64_t i = 0, j = 0;
+            while (i < da && j < db) {
+                if (na[i] < nb[j]) {
+                    ++i;
+                } else if (nb[j] < na[i]) {
+                    ++j;
+                } else {  /* c = na[i] */
+                    ++t[a];
+                    ++t[b];
+                    ++t[na[i]];
+                    ++i;
+                    ++j;
+                }
+            }
+        }
+    }
+}
+
 /* Number of oracle threads an OpenMP build uses (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -323,3 +323,43 @@ def test_edge_support_closed_forms():
     part = lambda x: 0 if x < 2 else (1 if x < 5 else 2)
     size = [2, 3, 4]
     assert all(v == size[3 - part(a) - part(b)] for (a, b), v in _support(n, s, d)[0].items())
+
+
+# ---------------------------------------------------------------- vertex counts
+
+def test_vertex_counts_dense_identity_and_brute_force():
+    """t(v) = (A^3)[v, v] / 2 (closed walks of length 3 through v), and a
+    triple enumeration on small graphs; order by id gives the same counts."""
+    for n, s, d in (gen.er(250, 2000, gen.seed(42, 0)), gen.rmat(9, 16, gen.seed(42, 1)),
+                    gen.rgg(300, 10.0, gen.seed(42, 2))):
+        A = np.zeros((n, n), np.int64)
+        m = s != d
+        A[s[m], d[m]] = 1
+        A[d[m], s[m]] = 1
+        want = np.diag(A @ A @ A) // 2
+        got = oracle.vertex_counts(n, s, d)
+        assert np.array_equal(got.astype(np.int64), want)
+        assert np.array_equal(oracle.vertex_counts(n, s, d, mode=1), got)
+        assert int(got.sum()) == 3 * oracle.tc(n, s, d)
+    rng = np.random.default_rng(8)
+    for n in (1, 7, 30):
+        pairs = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < 0.4]
+        n_, s, d = graphs.messy(*graphs._edges(pairs, n), seed=n)
+        t = np.zeros(n_, np.int64)
+        for (a, b), v in graphs.support_brute_force(n_, s, d).items():
+            t[a] += v
+            t[b] += v
+        assert np.array_equal(oracle.vertex_counts(n_, s, d).astype(np.int64), t // 2)
+
+
+def test_vertex_counts_closed_forms():
+    (n, s, d), _ = graphs.complete(9)
+    assert set(oracle.vertex_counts(n, s, d).tolist()) == {math.comb(8, 2)}
+    (n, s, d), _ = graphs.complete_bipartite(3, 6)
+    assert set(oracle.vertex_counts(n, s, d).tolist()) == {0}
+    (n, s, d), _ = graphs.wheel(10)  # hub in every rim triangle, rim vertices in 2
+    assert oracle.vertex_counts(n, s, d).tolist() == [9] + [2] * 9
+    (n, s, d), k = graphs.friendship(5)
+    assert oracle.vertex_counts(n, s, d).tolist() == [k] + [1] * (2 * k)
+    (n, s, d), k = graphs.book(4)
+    assert oracle.vertex_counts(n, s, d).tolist() == [k, k] + [1] * k
