@@ -326,6 +326,11 @@ def bench_support(args):
     g, out, tri, info = step(keep=True)
     row_off, col, _ = g.export_csr()
     sup = out.cpu().numpy().view(np.uint32)
+    # per-vertex counts from the same graph (support pass + per-vertex sums)
+    tv = torch.empty(n, dtype=torch.int64, device="cuda")
+    _, tri_v = g.vertex_counts(tv)
+    t_vertex_ms = g.info()["t_count_ms"]
+    tv_sum = int(tv.sum().item())
     g.close()
     m = info["m"]
     T = tri
@@ -357,7 +362,9 @@ def bench_support(args):
         "walked_entries": walked,
         "algorithmic_bytes_per_launch": alg,
         "max_support": int(sup.max()) if m else 0,
+        "t_vertex_counts_ms": t_vertex_ms,
     })
+    out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T
     if not args.no_cpu_baseline:
         import oracle
         t1 = time.perf_counter()

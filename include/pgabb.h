@@ -284,6 +284,22 @@ pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_options *opts, 
 #define PGABB_SUPPORT_ON_DEVICE 0x1u
 pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t flags, uint64_t *triangles);
 
+/*
+ * Triangles at each vertex (the numerator of the local clustering
+ * coefficient 2 t(v) / (deg(v) (deg(v) - 1)), PGAbB Section 1), from the
+ * per-edge counts of pgabb_tc_edge_support: t(v) is half the sum of the
+ * counts of v's edges.
+ *   per_vertex : n uint64 entries, indexed by input id (isolated and
+ *                out-of-triangle vertices get 0).  Host memory, or device
+ *                memory with PGABB_SUPPORT_ON_DEVICE (finish other streams'
+ *                work on it first); complete when the call returns.  May be
+ *                NULL only when n = 0.
+ *   flags      : 0 or PGABB_SUPPORT_ON_DEVICE
+ *   triangles  : optional; the triangle count
+ * Errors: as pgabb_tc_edge_support.
+ */
+pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vertex, uint32_t flags, uint64_t *triangles);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 

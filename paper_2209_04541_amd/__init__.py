@@ -97,6 +97,7 @@ def lib():
             "pgabb_graph_task_counts": (st, [vp, vp, vp]),
             "pgabb_graph_task_shards": (st, [vp, i32, vp]),
             "pgabb_tc_edge_support": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
+            "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
@@ -265,6 +266,28 @@ class Graph:
             torch.cuda.current_stream().synchronize()  # torch's pending writes to out come first
             _check(lib().pgabb_tc_edge_support(self._h, ctypes.c_void_p(out.data_ptr()) if m else None,
                                                SUPPORT_ON_DEVICE, ctypes.byref(tri)))
+        return out, int(tri.value)
+
+    def vertex_counts(self, out=None):
+        """Triangles at each vertex by input id, and the triangle count.
+        out: None (a new numpy uint64 array), a numpy uint64 array or a CUDA
+        torch int64 tensor of n entries (complete when the call returns)."""
+        n = self.info()["n"]
+        tri = ctypes.c_uint64()
+        if out is None:
+            out = np.empty(n, np.uint64)
+        if isinstance(out, np.ndarray):
+            if out.dtype != np.uint64 or out.size != n or not out.flags.c_contiguous:
+                raise ValueError("out must be a contiguous uint64 array of n entries")
+            _check(lib().pgabb_tc_vertex_counts(self._h, ctypes.c_void_p(out.ctypes.data) if n else None, 0,
+                                                ctypes.byref(tri)))
+        else:
+            if out.numel() != n or out.element_size() != 8 or not out.is_contiguous() or not out.is_cuda:
+                raise ValueError("out must be a contiguous 8-byte CUDA tensor of n entries")
+            import torch
+            torch.cuda.current_stream().synchronize()  # torch's pending writes to out come first
+            _check(lib().pgabb_tc_vertex_counts(self._h, ctypes.c_void_p(out.data_ptr()) if n else None,
+                                                SUPPORT_ON_DEVICE, ctypes.byref(tri)))
         return out, int(tri.value)
 
     def task_shards(self, num_shards):

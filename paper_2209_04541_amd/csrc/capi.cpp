@@ -234,6 +234,18 @@ PGABB_API pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, 
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vertex, uint32_t flags,
+                                              uint64_t *triangles) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!per_vertex && g->n > 0) return set_err(PGABB_EINVAL, "per_vertex is NULL");
+    if (flags & ~PGABB_SUPPORT_ON_DEVICE) return set_err(PGABB_EINVAL, "unknown flag bits");
+    PGABB_TRY
+    const uint64_t t = vertex_counts(g, per_vertex, (flags & PGABB_SUPPORT_ON_DEVICE) != 0);
+    if (triangles) *triangles = t;
+    return set_ok();
+    PGABB_CATCH
+}
+
 static constexpr int32_t kMaxShards = 4096;
 
 PGABB_API pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of) {

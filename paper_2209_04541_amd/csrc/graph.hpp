@@ -140,6 +140,9 @@ std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards);
 // Triangles containing each oriented edge, into out[m'] (device or host
 // memory); returns the triangle count.
 uint64_t edge_support(pgabb_graph *g, uint32_t *out, bool out_on_device);
+// Triangles at each vertex, by input id, into out[n] (device or host
+// memory); returns the triangle count.
+uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);
 // Count only the tasks task_shards deals to `shard`.
 uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards);
 

@@ -1,6 +1,7 @@
-"""GPU parity of the per-edge triangle counts (edge support) against the
-CPU oracle, through the C ABI: exact equality of every edge's count, in the
-CSR order both sides build, and of the triangle count."""
+"""GPU parity of the per-edge triangle counts (edge support) and the
+per-vertex triangle counts against the CPU oracle, through the C ABI: exact
+equality of every edge's count (in the CSR order both sides build), of every
+vertex's count (by input id) and of the triangle count."""
 import json
 import os
 import sys
@@ -135,3 +136,58 @@ def test_block_workload_full_size():
         nx_ = A.indices[A.indptr[x]:A.indptr[x + 1]]
         ny_ = A.indices[A.indptr[y]:A.indptr[y + 1]]
         assert got[e] == len(np.intersect1d(nx_, ny_, assume_unique=True)), e
+
+
+# ---------------------------------------------------------------- vertex counts
+
+def check_vertices(n, s, d):
+    want = oracle.vertex_counts(n, s, d)
+    with P.Graph(n, s, d) as g:
+        got, tri = g.vertex_counts()
+    assert np.array_equal(got, want)
+    assert 3 * tri == int(want.sum())
+    return got, tri
+
+
+@pytest.mark.parametrize("name,g,expected", graphs.closed_forms(), ids=lambda x: x if isinstance(x, str) else "")
+def test_vertex_counts_closed_forms(name, g, expected):
+    n, s, d = g
+    _, tri = check_vertices(*graphs.messy(n, s, d, seed=4))
+    assert tri == expected
+
+
+@pytest.mark.parametrize("kind", ["random", "rmat", "rgg", "k1500"])
+def test_vertex_counts_graphs(kind):
+    if kind == "random":
+        rng = np.random.default_rng(77)
+        n = 70
+        s = rng.integers(0, n, 900).astype(np.int32)
+        d = rng.integers(0, n, 900).astype(np.int32)
+    elif kind == "rmat":
+        n, s, d = gen.rmat(15, 16, gen.seed(63, 0))
+    elif kind == "rgg":
+        n, s, d = gen.rgg(30000, 20.0, gen.seed(63, 1))
+    else:
+        n = 1500
+        s, d = np.triu_indices(n, 1)
+        s, d = s.astype(np.int32), d.astype(np.int32)
+    say("vertex counts", kind, n, len(s))
+    got, _ = check_vertices(n, s, d)
+    if kind == "k1500":
+        assert set(got.tolist()) == {1499 * 1498 // 2}
+
+
+def test_vertex_counts_device_output_and_edge_cases():
+    import torch
+    n, s, d = gen.rmat(12, 16, gen.seed(64, 0))
+    want = oracle.vertex_counts(n, s, d)
+    with P.Graph(n, s, d) as g:
+        out = torch.full((n,), 5, dtype=torch.int64, device="cuda")
+        _, tri = g.vertex_counts(out)
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), want)
+        with pytest.raises(ValueError):
+            g.vertex_counts(np.empty(n + 1, np.uint64))
+    for n in (0, 6):
+        with P.Graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32)) as g:
+            got, tri = g.vertex_counts()
+            assert got.size == n and tri == 0 and not got.any()
