@@ -66,6 +66,8 @@ def _load():
         L.oracle_edge_support.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.oracle_vertex_counts.restype = None
         L.oracle_vertex_counts.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.oracle_ktruss.restype = ctypes.c_int64
+        L.oracle_ktruss.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -155,6 +157,18 @@ def vertex_counts(n: int, src, dst, mode: int = 0) -> np.ndarray:
         c = col if len(col) else np.zeros(1, dtype=np.int32)
         _load().oracle_vertex_counts(n, _p(row_off), _p(np.ascontiguousarray(c, dtype=np.int32)), _p(t))
     return t[:n][rnk] if n > 0 else t[:0]
+
+
+def ktruss(n: int, row_off: np.ndarray, col: np.ndarray, k: int) -> np.ndarray:
+    """uint8 mask over the oriented CSR positions: 1 for the edges of the
+    k-truss."""
+    row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    m = int(row_off[n]) if n > 0 else 0
+    keep = np.zeros(max(m, 1), dtype=np.uint8)
+    if m:
+        _load().oracle_ktruss(n, _p(row_off), _p(col), int(k), _p(keep))
+    return keep[:m]
 
 
 def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:

@@ -229,6 +229,83 @@ void oracle_vertex_counts(int32_t n, const int64_t *row_off, const int32_t *col,
     }
 }
 
+/* k-truss (the peeling algorithm named in Section 3.2): the largest
+ * subgraph in which every edge lies in at least k - 2 triangles of the
+ * subgraph; it is unique.  Classic peeling, one edge at a time: start from
+ * every edge's support; while some remaining edge has support below k - 2,
+ * delete it, and for every vertex w still joined to both of its ends take one
+ * from the supports of the edges to w (queueing those that fall below).
+ * keep[e] = 1 for the oriented CSR positions left; returns their number.
+ * Sequential. */
+int64_t oracle_ktruss(int32_t n, const int64_t *row_off, const int32_t *col, int32_t k, uint8_t *keep)
+{
+    const int64_t m = row_off[n];
+    if (m == 0) return 0;
+    uint32_t *sup = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)m);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    uint8_t *queued = (uint8_t *)calloc((size_t)m, 1);
+    /* undirected adjacency with edge positions: adj_off over vertices */
+    int64_t *adj_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m));
+    int64_t *adj_e = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * m));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int32_t x = 0; x < n; ++x)
+        for (int64_t e = row_off[x]; e < row_off[x + 1]; ++e) {
+            adj_off[x + 1]++;
+            adj_off[col[e] + 1]++;
+        }
+    for (int32_t x = 0; x < n; ++x) adj_off[x + 1] += adj_off[x];
+    for (int32_t x = 0; x < n; ++x) fill[x] = adj_off[x];
+    /* rows in increasing x: each list receives its lower neighbours in
+     * increasing order first, then its higher ones in increasing order */
+    for (int32_t x = 0; x < n; ++x)
+        for (int64_t e = row_off[x]; e < row_off[x + 1]; ++e) {
+            const int32_t y = col[e];
+            adj[fill[y]] = x; adj_e[fill[y]++] = e;
+        }
+    for (int32_t x = 0; x < n; ++x)
+        for (int64_t e = row_off[x]; e < row_off[x + 1]; ++e) {
+            adj[fill[x]] = col[e]; adj_e[fill[x]++] = e;
+        }
+    oracle_edge_support(n, row_off, col, sup);
+    for (int64_t e = 0; e < m; ++e) keep[e] = 1;
+    const uint32_t need = k > 2 ? (uint32_t)(k - 2) : 0u;
+    int64_t head = 0, tail = 0;
+    for (int64_t e = 0; e < m; ++e)
+        if (sup[e] < need) { queue[tail++] = e; queued[e] = 1; }
+    while (head < tail) {
+        const int64_t e = queue[head++];
+        keep[e] = 0;
+        /* ends of e: its row (binary search over row_off) and column */
+        int32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) / 2;
+            if (row_off[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int32_t a = lo, b = col[e];
+        int64_t i = adj_off[a], j = adj_off[b];
+        while (i < adj_off[a + 1] && j < adj_off[b + 1]) {
+            if (adj[i] < adj[j]) { ++i; continue; }
+            if (adj[j] < adj[i]) { ++j; continue; }
+            const int64_t ea = adj_e[i], eb = adj_e[j];
+            if (keep[ea] && keep[eb]) {  /* the triangle (a, b, w) was intact */
+                const int64_t two[2] = {ea, eb};
+                for (int q = 0; q < 2; ++q) {
+                    const int64_t f = two[q];
+                    if (!queued[f]) {
+                        if (--sup[f] < need) { queue[tail++] = f; queued[f] = 1; }
+                    }
+                }
+            }
+            ++i; ++j;
+        }
+    }
+    int64_t left = 0;
+    for (int64_t e = 0; e < m; ++e) left += keep[e];
+    free(sup); free(queue); free(queued); free(adj_off); free(adj); free(adj_e); free(fill);
+    return left;
+}
+
 /* Number of oracle threads an OpenMP build uses (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -186,3 +186,20 @@ def support_brute_force(n, src, dst):
             sup[(a, c)] += 1
             sup[(b, c)] += 1
     return sup
+
+
+def ktruss_by_rounds(n, src, dst, k):
+    """{(a, b)} of the k-truss by whole rounds: drop every edge whose support
+    within the remaining edges, (A A)[a, b] on the dense adjacency matrix, is
+    below k - 2, until a round drops none."""
+    A = np.zeros((n, n), np.int64)
+    for a, b in zip(src, dst):
+        if a != b:
+            A[a, b] = A[b, a] = 1
+    while True:
+        S = (A @ A) * A
+        drop = (A == 1) & (S < k - 2)
+        if not drop.any():
+            break
+        A[drop] = 0
+    return {(int(a), int(b)) for a, b in zip(*np.nonzero(np.triu(A)))}

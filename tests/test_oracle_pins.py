@@ -363,3 +363,42 @@ def test_vertex_counts_closed_forms():
     assert oracle.vertex_counts(n, s, d).tolist() == [k] + [1] * (2 * k)
     (n, s, d), k = graphs.book(4)
     assert oracle.vertex_counts(n, s, d).tolist() == [k, k] + [1] * k
+
+
+# ---------------------------------------------------------------- k-truss
+
+def _truss(n, s, d, k):
+    _, _, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    keep = oracle.ktruss(n, row_off, col, k)
+    a, b = graphs.support_by_pairs(n, s, d, rk, row_off, col)
+    return {(int(x), int(y)) for x, y, f in zip(a, b, keep) if f}, len(col)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ktruss_against_whole_rounds(seed):
+    """One edge at a time (the oracle) and whole rounds over the dense
+    support matrix reach the same unique k-truss."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(10, 70))
+    dens = float(rng.uniform(0.1, 0.6))
+    pairs = [(x, y) for x, y in itertools.combinations(range(n), 2) if rng.random() < dens]
+    n_, s, d = graphs.messy(*graphs._edges(pairs, n), seed=seed)
+    for k in (2, 3, 4, 5, 7):
+        got, _ = _truss(n_, s, d, k)
+        assert got == graphs.ktruss_by_rounds(n_, s, d, k), k
+
+
+def test_ktruss_closed_forms():
+    (n, s, d), _ = graphs.complete(8)
+    assert len(_truss(n, s, d, 8)[0]) == 28 and len(_truss(n, s, d, 9)[0]) == 0
+    (n, s, d), _ = graphs.wheel(9)
+    assert len(_truss(n, s, d, 3)[0]) == 16 and len(_truss(n, s, d, 4)[0]) == 0
+    (n, s, d), _ = graphs.book(5)
+    assert len(_truss(n, s, d, 3)[0]) == 11 and len(_truss(n, s, d, 4)[0]) == 0
+    (n, s, d), _ = graphs.cocktail_party(3)  # octahedron: every edge in 2 triangles
+    assert len(_truss(n, s, d, 4)[0]) == 12 and len(_truss(n, s, d, 5)[0]) == 0
+    (n, s, d), _ = graphs.disjoint_union(graphs.complete(5), graphs.complete(4))
+    got, _ = _truss(n, s, d, 5)
+    assert got == {(a, b) for a, b in itertools.combinations(range(5), 2)}
+    (n, s, d), _ = graphs.complete_bipartite(4, 4)
+    assert len(_truss(n, s, d, 3)[0]) == 0 and len(_truss(n, s, d, 2)[0]) == 16
