@@ -331,6 +331,13 @@ def bench_support(args):
     _, tri_v = g.vertex_counts(tv)
     t_vertex_ms = g.info()["t_count_ms"]
     tv_sum = int(tv.sum().item())
+    # k-truss by rounds of the support pass, for a few k
+    truss = {}
+    for k in (4, 8, 16, 32):
+        _, left, rounds = g.ktruss(k)
+        inf = g.info()
+        truss[str(k)] = {"edges": left, "rounds": rounds, "t_ms": inf["t_count_ms"],
+                         "t_support_kernels_ms": inf["t_kernel_ms"]}
     g.close()
     m = info["m"]
     T = tri
@@ -363,6 +370,7 @@ def bench_support(args):
         "algorithmic_bytes_per_launch": alg,
         "max_support": int(sup.max()) if m else 0,
         "t_vertex_counts_ms": t_vertex_ms,
+        "ktruss": truss,
     })
     out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T
     if not args.no_cpu_baseline:

@@ -300,6 +300,28 @@ pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t f
  */
 pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vertex, uint32_t flags, uint64_t *triangles);
 
+/*
+ * The k-truss (the peeling algorithm named in PGAbB Section 3.2): the
+ * largest subgraph in which every edge lies in at least k - 2 triangles of
+ * the subgraph (unique; k <= 2 keeps every edge).  Computed by rounds: each
+ * round counts the triangles of every remaining edge (the pass of
+ * pgabb_tc_edge_support on the graph of the remaining edges) and keeps the
+ * edges with at least k - 2; the rounds end when one keeps every edge.
+ *   k         : k >= 0
+ *   keep      : optional; m' bytes, keep[e] = 1 for the oriented edge at CSR
+ *               position e (pgabb_graph_export_csr) if it is in the k-truss,
+ *               else 0.  Host memory, or device memory with
+ *               PGABB_SUPPORT_ON_DEVICE; complete when the call returns.
+ *   num_edges : optional; edges of the k-truss
+ *   rounds    : optional; support passes run
+ * pgabb_graph_info_get then reports the call's time (t_count_ms), the
+ * support kernels' time and the rounds as launches.
+ * Errors: EINVAL (NULL graph, k < 0, unknown flags, m' >= 2^32), ENOMEM,
+ * EDEVICE.
+ */
+pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t flags, int64_t *num_edges,
+                             int32_t *rounds);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 

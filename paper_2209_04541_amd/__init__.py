@@ -98,6 +98,7 @@ def lib():
             "pgabb_graph_task_shards": (st, [vp, i32, vp]),
             "pgabb_tc_edge_support": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
+            "pgabb_tc_ktruss": (st, [vp, i32, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
@@ -289,6 +290,16 @@ class Graph:
             _check(lib().pgabb_tc_vertex_counts(self._h, ctypes.c_void_p(out.data_ptr()) if n else None,
                                                 SUPPORT_ON_DEVICE, ctypes.byref(tri)))
         return out, int(tri.value)
+
+    def ktruss(self, k):
+        """(keep, edges, rounds): keep is a numpy uint8 mask over the oriented
+        CSR positions (export_csr order), 1 for the edges of the k-truss."""
+        m = self.info()["m"]
+        keep = np.empty(max(m, 1), np.uint8)
+        left, rounds = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().pgabb_tc_ktruss(self._h, int(k), ctypes.c_void_p(keep.ctypes.data), 0, ctypes.byref(left),
+                                     ctypes.byref(rounds)))
+        return keep[:m], int(left.value), int(rounds.value)
 
     def task_shards(self, num_shards):
         """Shard of each task (order of task_counts) for num_shards devices."""

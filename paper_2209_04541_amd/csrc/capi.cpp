@@ -246,6 +246,18 @@ PGABB_API pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vert
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t flags,
+                                       int64_t *num_edges, int32_t *rounds) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (k < 0) return set_err(PGABB_EINVAL, "k < 0");
+    if (flags & ~PGABB_SUPPORT_ON_DEVICE) return set_err(PGABB_EINVAL, "unknown flag bits");
+    PGABB_TRY
+    const int64_t left = ktruss(g, k, keep, (flags & PGABB_SUPPORT_ON_DEVICE) != 0, rounds);
+    if (num_edges) *num_edges = left;
+    return set_ok();
+    PGABB_CATCH
+}
+
 static constexpr int32_t kMaxShards = 4096;
 
 PGABB_API pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of) {

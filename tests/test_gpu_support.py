@@ -191,3 +191,56 @@ def test_vertex_counts_device_output_and_edge_cases():
         with P.Graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32)) as g:
             got, tri = g.vertex_counts()
             assert got.size == n and tri == 0 and not got.any()
+
+
+# ---------------------------------------------------------------- k-truss
+
+def check_truss(n, s, d, k):
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    want = oracle.ktruss(n, row_off, col, k)
+    with P.Graph(n, s, d) as g:
+        keep, left, rounds = g.ktruss(k)
+        info = g.info()
+    assert np.array_equal(keep, want), k
+    assert left == int(want.sum())
+    assert info["kernel_launches"] == rounds
+    return left, rounds
+
+
+@pytest.mark.parametrize("name,g,expected", graphs.closed_forms(), ids=lambda x: x if isinstance(x, str) else "")
+def test_ktruss_closed_forms(name, g, expected):
+    n, s, d = graphs.messy(*g, seed=6)
+    for k in (0, 2, 3, 4, 5):
+        check_truss(n, s, d, k)
+
+
+@pytest.mark.parametrize("kind", ["random", "rmat", "rgg"])
+def test_ktruss_graphs(kind):
+    if kind == "random":
+        rng = np.random.default_rng(91)
+        n = 80
+        s = rng.integers(0, n, 1500).astype(np.int32)
+        d = rng.integers(0, n, 1500).astype(np.int32)
+    elif kind == "rmat":
+        n, s, d = gen.rmat(14, 16, gen.seed(65, 0))
+    else:
+        n, s, d = gen.rgg(20000, 20.0, gen.seed(65, 1))
+    for k in (3, 4, 6, 9, 14, 25):
+        left, rounds = check_truss(n, s, d, k)
+        say("k-truss", kind, k, left, rounds)
+
+
+def test_ktruss_cliques():
+    """K_300 plus a pendant K_12: the 300-truss is the large clique, the
+    301-truss is empty, the 12-truss holds both cliques."""
+    a, b = np.triu_indices(300, 1)
+    c, e = np.triu_indices(12, 1)
+    s = np.concatenate([a, c + 300, [0]]).astype(np.int32)
+    d = np.concatenate([b, e + 300, [300]]).astype(np.int32)
+    n = 312
+    assert check_truss(n, s, d, 300)[0] == 300 * 299 // 2
+    assert check_truss(n, s, d, 301)[0] == 0
+    assert check_truss(n, s, d, 12)[0] == 300 * 299 // 2 + 66
+    with P.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32)) as g:
+        keep, left, rounds = g.ktruss(3)
+        assert keep.size == 0 and left == 0 and rounds == 0
