@@ -68,6 +68,8 @@ def _load():
         L.oracle_vertex_counts.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.oracle_ktruss.restype = ctypes.c_int64
         L.oracle_ktruss.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
+        L.oracle_four_cliques.restype = ctypes.c_uint64
+        L.oracle_four_cliques.argtypes = [ctypes.c_int32, vp, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -169,6 +171,14 @@ def ktruss(n: int, row_off: np.ndarray, col: np.ndarray, k: int) -> np.ndarray:
     if m:
         _load().oracle_ktruss(n, _p(row_off), _p(col), int(k), _p(keep))
     return keep[:m]
+
+
+def four_cliques(n: int, src, dst, mode: int = 0) -> int:
+    """Sets of four pairwise adjacent vertices."""
+    _, _, _, row_off, col = oriented_csr(n, src, dst, mode)
+    if n == 0 or len(col) == 0:
+        return 0
+    return int(_load().oracle_four_cliques(n, _p(row_off), _p(np.ascontiguousarray(col, dtype=np.int32))))
 
 
 def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:

@@ -306,6 +306,52 @@ int64_t oracle_ktruss(int32_t n, const int64_t *row_off, const int32_t *col, int
     return left;
 }
 
+/* 4-cliques (the multi-block pattern family of Section 3.2, one level past
+ * triangles): sets of four pairwise adjacent vertices.  Each 4-clique with
+ * ranks a < b < c < d is counted once, at the oriented edge (a, b): its
+ * other two vertices c < d are both common out-neighbours of a and b, and
+ * d is an out-neighbour of c.  So: for every edge (a, b), list
+ * C = N+(a) & N+(b) (by merge), and count the pairs c < d of C with d in
+ * N+(c) (by binary search in N+(c)).  Sequential; uint64 count. */
+static int has_out(const int64_t *row_off, const int32_t *col, int32_t c, int32_t d)
+{
+    int64_t lo = row_off[c], hi = row_off[c + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (col[mid] < d) lo = mid + 1; else hi = mid;
+    }
+    return lo < row_off[c + 1] && col[lo] == d;
+}
+
+uint64_t oracle_four_cliques(int32_t n, const int64_t *row_off, const int32_t *col)
+{
+    int32_t maxd = 0;
+    for (int32_t x = 0; x < n; ++x)
+        if (row_off[x + 1] - row_off[x] > maxd) maxd = (int32_t)(row_off[x + 1] - row_off[x]);
+    int32_t *common = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    uint64_t total = 0;
+    for (int32_t a = 0; a < n; ++a) {
+        const int32_t *na = col + row_off[a];
+        const int64_t da = row_off[a + 1] - row_off[a];
+        for (int64_t t = 0; t < da; ++t) {
+            const int32_t b = na[t];
+            const int32_t *nb = col + row_off[b];
+            const int64_t db = row_off[b + 1] - row_off[b];
+            int64_t i = 0, j = 0, nc = 0;
+            while (i < da && j < db) {
+                if (na[i] < nb[j]) ++i;
+                else if (nb[j] < na[i]) ++j;
+                else { common[nc++] = na[i]; ++i; ++j; }
+            }
+            for (int64_t x = 0; x < nc; ++x)
+                for (int64_t y = x + 1; y < nc; ++y)
+                    total += (uint64_t)has_out(row_off, col, common[x], common[y]);
+        }
+    }
+    free(common);
+    return total;
+}
+
 /* Number of oracle threads an OpenMP build uses (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

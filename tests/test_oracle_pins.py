@@ -402,3 +402,43 @@ def test_ktruss_closed_forms():
     assert got == {(a, b) for a, b in itertools.combinations(range(5), 2)}
     (n, s, d), _ = graphs.complete_bipartite(4, 4)
     assert len(_truss(n, s, d, 3)[0]) == 0 and len(_truss(n, s, d, 2)[0]) == 16
+
+
+# ---------------------------------------------------------------- 4-cliques
+
+def test_four_cliques_brute_force_and_networkx():
+    rng = np.random.default_rng(12)
+    for n, dens in ((8, 0.7), (20, 0.5), (35, 0.35), (45, 0.3)):
+        pairs = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < dens]
+        n_, s, d = graphs.messy(*graphs._edges(pairs, n), seed=n)
+        A = np.zeros((n_, n_), bool)
+        A[s, d] = A[d, s] = True
+        np.fill_diagonal(A, False)
+        want = sum(1 for q in itertools.combinations(range(n_), 4)
+                   if all(A[x, y] for x, y in itertools.combinations(q, 2)))
+        assert oracle.four_cliques(n_, s, d) == want
+        assert oracle.four_cliques(n_, s, d, mode=1) == want
+    n, s, d = gen.rmat(10, 16, gen.seed(43, 0))
+    G = nx.Graph()
+    G.add_edges_from((int(a), int(b)) for a, b in zip(s, d) if a != b)
+    want = 0
+    for c in nx.enumerate_all_cliques(G):  # by increasing size
+        if len(c) > 4:
+            break
+        want += len(c) == 4
+    assert oracle.four_cliques(n, s, d) == want
+
+
+def test_four_cliques_closed_forms():
+    (n, s, d), _ = graphs.complete(11)
+    assert oracle.four_cliques(n, s, d) == math.comb(11, 4)
+    (n, s, d), _ = graphs.cocktail_party(5)  # one vertex from each of 4 of the 5 pairs
+    assert oracle.four_cliques(n, s, d) == 16 * math.comb(5, 4)
+    (n, s, d), _ = graphs.complete_tripartite(3, 4, 5)
+    assert oracle.four_cliques(n, s, d) == 0
+    (n, s, d), _ = graphs.wheel(8)
+    assert oracle.four_cliques(n, s, d) == 0
+    (n, s, d), _ = graphs.complete(4)
+    assert oracle.four_cliques(n, s, d) == 1
+    (n, s, d), _ = graphs.disjoint_union(graphs.complete(6), graphs.complete(5))
+    assert oracle.four_cliques(n, s, d) == math.comb(6, 4) + math.comb(5, 4)
