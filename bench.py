@@ -338,6 +338,9 @@ def bench_support(args):
         inf = g.info()
         truss[str(k)] = {"edges": left, "rounds": rounds, "t_ms": inf["t_count_ms"],
                          "t_support_kernels_ms": inf["t_kernel_ms"]}
+    c4 = g.four_cliques()
+    inf = g.info()
+    cliques = {"four_cliques": c4, "t_ms": inf["t_count_ms"], "t_kernel_ms": inf["t_kernel_ms"]}
     g.close()
     m = info["m"]
     T = tri
@@ -371,6 +374,7 @@ def bench_support(args):
         "max_support": int(sup.max()) if m else 0,
         "t_vertex_counts_ms": t_vertex_ms,
         "ktruss": truss,
+        "cliques": cliques,
     })
     out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T
     if not args.no_cpu_baseline:

@@ -322,6 +322,16 @@ pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vertex, uint32
 pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t flags, int64_t *num_edges,
                              int32_t *rounds);
 
+/*
+ * Number of 4-cliques (sets of four pairwise adjacent vertices; the
+ * multi-block pattern family of PGAbB Section 3.2, one intersection level
+ * past triangles), over the whole oriented graph as one block.  Each
+ * 4-clique a < b < c < d (ranks) is counted once, at its edge (a, b).
+ * pgabb_graph_info_get then reports the call's time and kernel time.
+ * Errors: EINVAL (NULL argument), ENOMEM, EDEVICE.
+ */
+pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 

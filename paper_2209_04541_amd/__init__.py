@@ -99,6 +99,7 @@ def lib():
             "pgabb_tc_edge_support": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_ktruss": (st, [vp, i32, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+            "pgabb_count_4cliques": (st, [vp, ctypes.POINTER(u64)]),
             "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
@@ -300,6 +301,12 @@ class Graph:
         _check(lib().pgabb_tc_ktruss(self._h, int(k), ctypes.c_void_p(keep.ctypes.data), 0, ctypes.byref(left),
                                      ctypes.byref(rounds)))
         return keep[:m], int(left.value), int(rounds.value)
+
+    def four_cliques(self):
+        """Sets of four pairwise adjacent vertices."""
+        c = ctypes.c_uint64()
+        _check(lib().pgabb_count_4cliques(self._h, ctypes.byref(c)))
+        return int(c.value)
 
     def task_shards(self, num_shards):
         """Shard of each task (order of task_counts) for num_shards devices."""

@@ -258,6 +258,14 @@ PGABB_API pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep,
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count) {
+    if (!g || !count) return set_err(PGABB_EINVAL, "NULL argument");
+    PGABB_TRY
+    *count = four_cliques(g);
+    return set_ok();
+    PGABB_CATCH
+}
+
 static constexpr int32_t kMaxShards = 4096;
 
 PGABB_API pgabb_status pgabb_graph_task_shards(const pgabb_graph *g, int32_t num_shards, int32_t *shard_of) {

@@ -146,6 +146,8 @@ uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);
 // Edges of the k-truss: keep[e] = 1 for the oriented CSR positions left
 // (keep may be null); returns their number.
 int64_t ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, bool on_device, int32_t *rounds);
+// Sets of four pairwise adjacent vertices.
+uint64_t four_cliques(pgabb_graph *g);
 // Count only the tasks task_shards deals to `shard`.
 uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards);
 

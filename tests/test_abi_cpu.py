@@ -55,6 +55,7 @@ def test_argument_errors_before_device_work():
     assert L.pgabb_tc_edge_support(None, None, 0, None) == P.EINVAL
     assert L.pgabb_tc_vertex_counts(None, None, 0, None) == P.EINVAL
     assert L.pgabb_tc_ktruss(None, 3, None, 0, None, None) == P.EINVAL
+    assert L.pgabb_count_4cliques(None, ctypes.byref(c)) == P.EINVAL
     counts = (ctypes.c_uint64 * 2)(7, 7)
     assert L.pgabb_tc_count_batch(None, -1, None, counts) == P.EINVAL
     assert L.pgabb_tc_count_batch(None, 2, None, counts) == P.EINVAL
