@@ -66,6 +66,18 @@ def test_generated(kind):
     assert info["kernel_launches"] == 1
 
 
+def test_rows_longer_than_the_lds_region():
+    """K_1100 plus a pendant K_30: rows above 1024 entries take the
+    thread-per-edge path, shorter rows the staged one."""
+    a, b = np.triu_indices(1100, 1)
+    c, e = np.triu_indices(30, 1)
+    s = np.concatenate([a, c + 1100, [0, 7]]).astype(np.int32)
+    d = np.concatenate([b, e + 1100, [1100, 1101]]).astype(np.int32)
+    got, info = gpu_four(1130, s, d)
+    assert got == math.comb(1100, 4) + math.comb(30, 4)
+    assert info["kernel_launches"] == 2
+
+
 def test_empty():
     for n in (0, 3):
         assert gpu_four(n, np.zeros(0, np.int32), np.zeros(0, np.int32))[0] == 0
