@@ -28,6 +28,17 @@ namespace {
 constexpr int kQB = 256;
 constexpr int kCliqueCap = 1024;  // longest row a wave stages
 constexpr int kCliqueWaves = 4;
+constexpr int kCliqueSpan = 8;  // b's of a row per work item
+
+// Work items per row: rows of 3 to kCliqueCap entries, kCliqueSpan b's each.
+__global__ __launch_bounds__(kQB) void k_clique_items(const int64_t *__restrict__ row_off, int32_t n,
+                                                       int64_t *__restrict__ items) {
+    for (int64_t a = blockIdx.x * static_cast<int64_t>(kQB) + threadIdx.x; a < n;
+         a += static_cast<int64_t>(gridDim.x) * kQB) {
+        const int64_t d = row_off[a + 1] - row_off[a];
+        items[a] = (d >= 3 && d <= kCliqueCap) ? (d - 2 + kCliqueSpan - 1) / kCliqueSpan : 0;
+    }
+}
 
 struct CliqueLds {
     int32_t row[kCliqueCap];          // N+(a)
@@ -51,6 +62,7 @@ __device__ __forceinline__ int32_t lds_lower_bound(const int32_t *row, int32_t l
 __global__ __launch_bounds__(kCliqueWaves *kWave) void k_four_cliques_rows(const int64_t *__restrict__ row_off,
                                                                             const int32_t *__restrict__ col,
                                                                             int32_t n,
+                                                                            const int64_t *__restrict__ item_pre,
                                                                             unsigned long long *__restrict__ next,
                                                                             unsigned long long *__restrict__ total) {
     __shared__ CliqueLds s_lds[kCliqueWaves];
@@ -59,21 +71,30 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_four_cliques_rows(const
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
     gptr<int64_t> ro = as_global(row_off);
     gptr<int32_t> cl = as_global(col);
+    gptr<int64_t> ip = as_global(item_pre);
+    const int64_t nitems = ip[n];
     unsigned long long cnt = 0;
     for (;;) {
         unsigned long long q0 = 0;
         if (lane == 0) q0 = atomicAdd(next, 1ull);
         q0 = shfl_t(q0, 0);
-        if (q0 >= static_cast<unsigned long long>(n)) break;
-        const int32_t a = static_cast<int32_t>(q0);
+        if (q0 >= static_cast<unsigned long long>(nitems)) break;
+        const int64_t q = static_cast<int64_t>(q0);
+        int32_t a = 0, ahi = n - 1;  // the row holding item q: the last with item_pre <= q
+        while (a < ahi) {
+            const int32_t mid = (a + ahi + 1) >> 1;
+            if (ip[mid] <= q) a = mid;
+            else ahi = mid - 1;
+        }
         const int64_t a0 = ro[a];
         const int32_t d = static_cast<int32_t>(ro[a + 1] - a0);
-        if (d < 3 || d > kCliqueCap) continue;
+        const int32_t i_lo = static_cast<int32_t>(q - ip[a]) * kCliqueSpan;
+        const int32_t i_hi = min(i_lo + kCliqueSpan, d - 2);
         for (int x = lane; x < d; x += kWave) L.row[x] = cl[a0 + x];
         wave_lds_sync();
         const int32_t top = L.row[d - 1];
         const int nwords = (d + 31) >> 5;
-        for (int32_t i = 0; i + 2 < d; ++i) {
+        for (int32_t i = i_lo; i < i_hi; ++i) {
             const int32_t b = L.row[i];
             const int64_t b0 = ro[b];
             const int64_t db = ro[b + 1] - b0;
@@ -194,15 +215,19 @@ uint64_t four_cliques(pgabb_graph *g) {
     g->t_kernel_ms = 0;
     g->kernel_launches = 0;
     if (m > 0) {
-        DArray<unsigned long long> tot(2, s);  // count, row counter
+        DArray<unsigned long long> tot(2, s);  // count, item counter
         PGABB_HIP(hipMemsetAsync(tot.get(), 0, 2 * sizeof(unsigned long long), s));
         const unsigned grid = std::min<unsigned>(grid_for(m, kQB), 256u * 16u);
-        const int64_t want = (static_cast<int64_t>(g->n) + kCliqueWaves - 1) / kCliqueWaves;
-        const int rgrid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, 256 * 4)));
+        // work items of the staged rows: kCliqueSpan b's of one row each
+        DArray<int64_t> item_pre(static_cast<size_t>(g->n) + 1, s);
+        k_clique_items<<<grid_for(g->n, kQB), kQB, 0, s>>>(g->row_off.get(), g->n, item_pre.get());
+        PGABB_HIP(hipGetLastError());
+        scan_exclusive_i64(item_pre.get(), item_pre.get(), g->n, item_pre.get() + g->n, s);
+        const int rgrid = 256 * 4;
         StreamTimer tm;
         tm.start(s);
         k_four_cliques_rows<<<rgrid, kCliqueWaves * kWave, 0, s>>>(g->row_off.get(), g->col.get(), g->n,
-                                                                    tot.get() + 1, tot.get());
+                                                                    item_pre.get(), tot.get() + 1, tot.get());
         if (g->max_out > kCliqueCap)
             k_four_cliques<<<grid, kQB, 0, s>>>(g->row_off.get(), g->col.get(), g->n, m, tot.get());
         PGABB_HIP(hipGetLastError());
