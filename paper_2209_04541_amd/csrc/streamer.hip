@@ -7,10 +7,15 @@
 // computation.  Instead of waiting for all tasks and clearing the device
 // when memory runs low, this keeps a block cache: a device pool of at most
 // `device_cap_bytes` managed first-fit, with least-recently-used eviction of
-// blocks that no in-flight task still reads.
+// blocks that no in-flight task still reads (every stream's last window that
+// read a block has finished before its range is reused).
 //
 // Tasks are taken in the heaviest-first order and grouped into windows of a
-// few tasks whose blocks are resident together.  For each window the missing
+// few tasks whose blocks are resident together.  In the hybrid mode host
+// threads run the host kernel on the lightest remaining tasks, read straight
+// from the host store, while the device takes windows from the heavy end
+// (Section 4.4: heavy tasks to the GPU, light ones to CPU threads, all
+// pulled from one task queue).  For each window the missing
 // blocks are copied on a copy stream; the window's counting launch runs on
 // one of several compute streams once its copies are done; windows on
 // different streams overlap, and the copies of later windows overlap earlier
@@ -18,7 +23,10 @@
 #include <algorithm>
 #include <list>
 #include <map>
+#include <mutex>
+#include <thread>
 
+#include "block_readers.hpp"
 #include "common.hpp"
 #include "count.hpp"
 #include "graph.hpp"
@@ -208,7 +216,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
 
     RangePool rp(cap);
     std::vector<uint64_t> where(nblk, UINT64_MAX);   // pool offset of resident blocks
-    std::vector<int32_t> last_window(nblk, -1);      // last window that reads the block
+    BlockReaders readers(nblk, nstreams);            // windows per stream that read each block
     std::list<int32_t> lru;                           // resident blocks, least recent first
     std::vector<std::list<int32_t>::iterator> lru_pos(nblk);
     std::vector<hipEvent_t> done;                     // per window
@@ -231,7 +239,11 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     // A window is cut when its blocks would exceed the cap or when it would
     // copy more than about an eighth of all block bytes: the first launch
     // starts after a short copy, and later copies overlap earlier launches.
-    const int window_tasks = T;
+    const bool hybrid = (opt.flags & PGABB_OPT_HYBRID) != 0;
+    // in the hybrid mode windows hold at most 1/32 of the tasks, so the
+    // device claims work in steps small enough for the two sides to meet
+    // near the balance point
+    const int window_tasks = hybrid ? std::max(1, T / 32) : T;
     const uint64_t window_new_bytes = std::max<uint64_t>(64ull << 20, std::min<uint64_t>(cap / 4, total_bytes / 8));
 
     std::vector<int64_t> chunk_dev(nblk, 0);  // in int32 words from pool start
@@ -242,9 +254,60 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     if (total_bytes > cap) order = locality_order(g, cap);
 
     uint64_t h2d = 0;
-    int32_t next_task = 0;  // position in `order`
+    int32_t next_task = 0;  // position in `order`: the device takes [0, next_task)
     int32_t win = 0;
     int64_t pre_at = 0;
+
+    // ---- hybrid: the host takes positions [back, T) of `order`, one task
+    // at a time from the end; with a fixed share it stops at host_stop (the
+    // device then stops there too), otherwise where the device has come to
+    std::mutex qmu;
+    int32_t back = T;
+    int32_t host_stop = T;
+    std::vector<uint64_t> host_cnt(T, 0);
+    std::vector<std::thread> host;
+    double host_work = 0, all_work = 0;
+    if (hybrid) {
+        std::vector<double> est(T);
+        for (int32_t q = 0; q < T; ++q) {
+            est[q] = static_cast<double>(task_work_estimate(g, g->tasks[order[q]], orient));
+            all_work += est[q];
+        }
+        if (opt.host_permille > 0) {
+            const double share = all_work * opt.host_permille / 1000.0;
+            double acc = 0;
+            host_stop = T;
+            while (host_stop > 0 && acc + est[host_stop - 1] <= share + 1e-9) acc += est[--host_stop];
+        } else {
+            host_stop = 0;
+        }
+        const int nth = opt.host_threads > 0
+                            ? opt.host_threads
+                            : static_cast<int>(std::max(1u, std::min(64u, std::thread::hardware_concurrency())));
+        const int32_t *harena = g->host_arena.get();
+        for (int h = 0; h < nth; ++h)
+            host.emplace_back([&, harena] {
+                for (;;) {
+                    int32_t pos;
+                    {
+                        std::lock_guard<std::mutex> lk(qmu);
+                        if (back <= std::max(next_task, host_stop)) return;
+                        pos = --back;
+                    }
+                    const int32_t t = order[pos];
+                    host_cnt[t] = host_count_task(g, harena, g->tasks[t]);
+                }
+            });
+        (void)est;
+    }
+    auto stop_host = [&]() {
+        {
+            std::lock_guard<std::mutex> lk(qmu);
+            host_stop = T;  // host threads end after their current task
+        }
+        for (auto &th : host)
+            if (th.joinable()) th.join();
+    };
 
     auto touch = [&](int32_t b) {
         lru.erase(lru_pos[b]);
@@ -253,13 +316,19 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     };
 
     try {
-        while (next_task < T) {
+        for (;;) {
+            // in the hybrid mode at most one window per stream is in flight,
+            // so the device claims tasks only as fast as it counts them
+            if (hybrid && win >= nstreams) PGABB_HIP(hipEventSynchronize(done[win - nstreams]));
+            std::unique_lock<std::mutex> qlk(qmu);
+            const int32_t limit = hybrid ? (opt.host_permille > 0 ? host_stop : back) : T;
+            if (next_task >= limit) break;
             // ---- form a window: tasks whose blocks fit together
             std::vector<int32_t> wtasks;  // task indices, in processing order
             const int32_t p0 = next_task;   // the window's first position in `order`
             std::vector<char> in_window(nblk, 0);
             uint64_t pinned_bytes = 0, new_bytes = 0;
-            while (next_task < T && static_cast<int>(wtasks.size()) < window_tasks) {
+            while (next_task < limit && static_cast<int>(wtasks.size()) < window_tasks) {
                 const Task &t = g->tasks[order[next_task]];
                 // bytes this task adds to the window (its block ids may repeat)
                 uint64_t add = 0, add_new = 0;
@@ -280,6 +349,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 new_bytes += add_new;
                 wtasks.push_back(order[next_task++]);
             }
+            qlk.unlock();
 
             // ---- make the window's blocks resident.  If first-fit cannot place
             // a block even with every block outside the window evicted (the pool
@@ -303,7 +373,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                             while (it != lru.end() && in_window[*it]) ++it;
                             if (it == lru.end()) break;
                             const int32_t v = *it;
-                            if (last_window[v] >= 0) PGABB_HIP(hipEventSynchronize(done[last_window[v]]));
+                            readers.release(v, [&](int32_t w) { PGABB_HIP(hipEventSynchronize(done[w])); });
                             rp.release(where[v], chunk_bytes(g->blocks[v]));
                             where[v] = UINT64_MAX;
                             lru.erase(it);
@@ -326,6 +396,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                     PGABB_HIP(hipStreamSynchronize(copy_s));
                     for (int32_t v : lru) where[v] = UINT64_MAX;
                     lru.clear();
+                    readers.clear();
                     rp = RangePool(cap);
                 }
             }
@@ -358,7 +429,8 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 items += task_items(g, g->tasks[ti], orient);
                 hpre[pre_at + q + 1] = items;
             }
-            hipStream_t st = cs[win % nstreams];
+            const int si = win % nstreams;
+            hipStream_t st = cs[si];
             PGABB_HIP(hipStreamWaitEvent(st, ce, 0));
             hipEvent_t k0 = nullptr, k1 = nullptr;
             PGABB_HIP(hipEventCreate(&k0));
@@ -386,10 +458,11 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             PGABB_HIP(hipEventRecord(k1, st));
             PGABB_HIP(hipEventRecord(de, st));
             for (int32_t ti : wtasks)
-                for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) last_window[b] = win;
+                for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) readers.read(b, si, win);
             pre_at += W + 1;
             ++win;
         }
+        for (auto &th : host) th.join();
         for (auto x : cs) PGABB_HIP(hipStreamSynchronize(x));
         PGABB_HIP(hipStreamSynchronize(copy_s));
         double kms = 0;
@@ -402,7 +475,16 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         g->task_counts.assign(T, 0);
         PGABB_HIP(hipMemcpyAsync(g->task_counts.data(), dcnt.get(), sizeof(uint64_t) * T, hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        // device tasks left their host slot at 0, host tasks their device slot
+        for (int32_t t = 0; t < T; ++t) g->task_counts[t] += host_cnt[t];
+        g->host_tasks = T - back;
+        if (hybrid && all_work > 0) {
+            for (int32_t q = back; q < T; ++q)
+                host_work += static_cast<double>(task_work_estimate(g, g->tasks[order[q]], orient));
+            g->host_work_share = host_work / all_work;
+        }
     } catch (...) {
+        stop_host();
         for (auto x : cs) (void)hipStreamSynchronize(x);
         (void)hipStreamSynchronize(copy_s);
         for (auto e : copied) (void)hipEventDestroy(e);

@@ -1,6 +1,9 @@
 """GPU parity of the batched form (one persistent, graph-captured launch over
 many graphs) and of the continuous-batching server, against the CPU oracle.
 """
+import json
+import math
+import os
 import sys
 import time
 
@@ -13,6 +16,8 @@ from paper_2209_04541_amd import gen
 from tests import graphs
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -70,12 +75,21 @@ def test_batch_workload_sample():
 
 
 def _rmat_requests(k, seed0=500):
+    """k R-MAT requests of scales 10 .. 18 (r * 5 mod 9 visits every
+    residue) and edge factors 8 .. 32, counted by the oracle in the test."""
     out = []
     for r in range(k):
-        sc = 8 + (r * 7) % 7
+        sc = 10 + (r * 5) % 9
         ef = 8 + (r * 5) % 25
         out.append(gen.rmat(sc, ef, gen.seed(seed0, r)))
     return out
+
+
+def _served_pool():
+    """Oracle counts of the served workload's request pool (written by
+    tests/golden/make_golden.py from the oracle)."""
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        return json.load(f)["served"]
 
 
 def _wait(srv, tickets, timeout=60):
@@ -120,7 +134,7 @@ def test_server_small_budget_and_rejection():
     with P.Server(budget) as srv:
         tickets = [srv.submit(*g) for g in reqs]
         assert _wait(srv, tickets) == want
-        n, s, d = gen.rmat(16, 32, gen.seed(601, 0))
+        n, s, d = gen.rmat(20, 16, gen.seed(601, 0))  # 16.8 M pairs: about 0.7 GB estimated
         with pytest.raises(P.PgabbError) as ei:
             srv.submit(n, s, d)
         assert ei.value.status == P.EBUDGET
@@ -143,3 +157,71 @@ def test_batch_rows_longer_than_a_wave():
         for kernel in (P.KERNEL_HASH, P.KERNEL_BITMAP):
             assert np.array_equal(b.count(kernel=kernel, waves_per_block=4, rows_per_grab=2), want)
         assert np.array_equal(b.count(), want)
+
+
+def test_server_scales_10_to_22_alone_equals_mix():
+    """The served recipe at its real sizes: one pool request per R-MAT scale
+    10 .. 22 (edge factors 8 .. 32, up to 134 M pairs) plus K_1100, whose
+    staged lists (up to 1099 entries) split the merged launch into two LDS
+    classes.  Each result equals the oracle's count when the request runs
+    alone and when all of them are submitted at once."""
+    pool = _served_pool()
+    by_scale = {}
+    for r in sorted(pool, key=int):
+        by_scale.setdefault(pool[r]["scale"], int(r))
+    assert sorted(by_scale) == list(range(10, 23))
+    reqs, want = [], []
+    for sc in range(10, 23):
+        r = by_scale[sc]
+        n, s, d = gen.served_graph(r)
+        assert len(s) == pool[str(r)]["m_input"]
+        reqs.append((n, s, d))
+        want.append(pool[str(r)]["triangles"])
+        say("pool request", r, "scale", sc, "pairs", len(s))
+    k_s, k_d = np.triu_indices(1100, 1)
+    reqs.append((1100, k_s.astype(np.int32), k_d.astype(np.int32)))
+    want.append(math.comb(1100, 3))
+    with P.Server(64 << 30) as srv:
+        alone = []
+        for q, g in enumerate(reqs):
+            say("alone", q)
+            alone += _wait(srv, [srv.submit(*g)], timeout=100)
+        say("mix of", len(reqs))
+        tickets = [srv.submit(*g) for g in reqs]
+        mix = _wait(srv, tickets, timeout=100)
+        srv.drain()
+    assert alone == want
+    assert mix == want
+
+
+def test_batch_all_10000_graphs():
+    """Every graph of the 10,000-graph batch workload (even g random
+    geometric, odd g Erdos-Renyi, n 64 .. 8192, degree 8 .. 64) against the
+    oracle's stored count, with the autotuned, graph-captured launch."""
+    want = np.array([int(x) for x in open(os.path.join(GOLDEN, "batch_counts.txt")) if not x.startswith("#")],
+                    np.uint64)
+    G = len(want)
+    assert G == 10000
+    nv = np.empty(G, np.int32)
+    eoff = np.zeros(G + 1, np.int64)
+    srcs, dsts = [], []
+    for g in range(G):
+        n, s, d = gen.batch_graph(g)
+        nv[g] = n
+        eoff[g + 1] = eoff[g] + len(s)
+        srcs.append(s)
+        dsts.append(d)
+        if g % 2000 == 0:
+            say("generated", g)
+    src = np.concatenate(srcs)
+    dst = np.concatenate(dsts)
+    del srcs, dsts
+    say("pairs", len(src))
+    with P.Batch((nv, eoff, src, dst)) as b:
+        say("built")
+        got = b.count()
+        say("counted")
+        bad = np.nonzero(got != want)[0]
+        assert len(bad) == 0, bad[:10]
+        got = b.count(kernel=P.KERNEL_HASH, waves_per_block=4, rows_per_grab=4)
+        assert np.array_equal(got, want)

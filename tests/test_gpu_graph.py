@@ -363,3 +363,61 @@ def test_streamed_under_small_caps(n, p):
             assert sorted(zip(map(tuple, ijk), cnt)) == sorted(zip(map(tuple, ijk0), cnt0))
             assert g.info()["h2d_bytes"] >= total
         assert ran >= 1
+
+
+@pytest.mark.parametrize("streams", [2, 3, 4])
+def test_streamed_eviction_with_windows_in_flight(streams):
+    """Caps that hold a small share of the blocks, with several compute
+    streams: windows on different streams read the same blocks, so a block
+    is evicted while an earlier window on another stream may still read it
+    unless every stream's last reader is awaited.  Per-task counts equal the
+    oracle's per-triple counts."""
+    n, s, d = gen.rmat(15, 16, gen.seed(95, 21))
+    with P.Graph(n, s, d) as g:
+        g.partition(12)
+        cuts = g.cuts()
+        row_off, col, _ = g.export_csr()
+        B = oracle.block_counts(n, row_off, col, cuts)
+        total = g.info()["block_bytes"]
+        ran = 0
+        for frac in (0.25, 0.4, 0.6):
+            try:
+                got = g.count(stream_blocks=True, device_cap_bytes=int(total * frac), num_streams=streams)
+            except P.PgabbError as e:
+                assert e.status == P.ENOMEM
+                continue
+            ran += 1
+            say("eviction", streams, frac, got, g.info()["h2d_bytes"])
+            assert got == int(B.sum())
+            ijk, cnt = g.task_counts()
+            for (i, j, k), c in zip(ijk, cnt):
+                assert c == B[i, j, k], (i, j, k)
+            assert g.info()["h2d_bytes"] > total  # blocks were evicted and copied again
+        assert ran >= 2
+
+
+def test_ooc_workload_full_size():
+    """R-MAT scale 24, edge factor 16 (268 M pairs), p = 32, blocks held in
+    pinned host memory and streamed under an 8 GB device cap, and again under
+    a 1 GiB cap that evicts blocks across four compute streams: the count
+    equals the oracle's stored count."""
+    with open(os.path.join(GOLDEN, "workload_counts.json")) as f:
+        gold = json.load(f)["ooc"]
+    import torch
+    n, s, d = gen.ooc_graph()
+    say("ooc generated", len(s))
+    ds = torch.from_numpy(s).cuda()
+    dd = torch.from_numpy(d).cuda()
+    del s, d
+    with P.Graph(n, ds, dd) as g:
+        del ds, dd
+        g.partition(32)
+        say("ooc partitioned")
+        got = g.count(stream_blocks=True, device_cap_bytes=8 * 10**9)
+        info = g.info()
+        say("ooc count", got, "h2d", info["h2d_bytes"], "ms", info["t_count_ms"])
+        assert got == gold["triangles"]
+        assert info["m"] == gold["m"] and info["probe_work"] == gold["probe_work"]
+        got = g.count(device_cap_bytes=1 << 30, num_streams=4)
+        say("ooc count at 1 GiB", got, "h2d", g.info()["h2d_bytes"])
+        assert got == gold["triangles"]

@@ -148,6 +148,51 @@ def test_orient_properties():
     assert np.diff(row_off).max() <= math.isqrt(2 * len(keys)) + 1
 
 
+def _W(n, s, d):
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    return oracle.probe_work(n, row_off, col)
+
+
+def test_probe_work_closed_forms():
+    """W = sum over oriented edges (x, y) of |N+(y)| counts the directed
+    two-step paths x -> y -> z of the oriented graph.
+    K_n: ranks follow ids, so every a < b < c is one such path: C(n, 3).
+    Star K_{1,k} (k >= 2): leaves rank below the hub, whose out-list is
+    empty: 0.  Wheel (hub + rim of r = n - 1 >= 4): the rim ranks by id below
+    the hub; rim vertex 1 has out-list {2, r, hub}, rim vertices 2 .. r - 1
+    {next, hub}, r {hub}; the rim edges (v, v + 1) land on out-lists of 2
+    (r - 2 times) and 1 (once), edge (1, r) on 1, the spokes on the empty
+    hub: 2 (r - 2) + 2 = 2 n - 4.  Disjoint unions add."""
+    for n in (1, 2, 3, 4, 7, 30):
+        (nn, s, d), _ = graphs.complete(n)
+        assert _W(nn, s, d) == math.comb(n, 3), n
+    for k in (2, 5, 40):
+        (nn, s, d), _ = graphs.star(k)
+        assert _W(nn, s, d) == 0, k
+    for n in (5, 6, 11, 50):
+        (nn, s, d), _ = graphs.wheel(n)
+        assert _W(nn, s, d) == 2 * n - 4, n
+    parts = [graphs.complete(9)[0], graphs.wheel(12)[0], graphs.star(6)[0]]
+    (nu, su, du), _ = graphs.disjoint_union(*[(g, 0) for g in parts])
+    assert _W(nu, su, du) == math.comb(9, 3) + (2 * 12 - 4) + 0
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 40), st.floats(0.0, 1.0), st.integers(0, 2**31 - 1))
+def test_probe_work_counts_two_paths(n, dens, sd):
+    """Against the dense count of two-step paths: sum of (A A) over the
+    oriented adjacency matrix A (built here from the oriented CSR rows)."""
+    rng = np.random.default_rng(sd)
+    m = int(dens * n * n)
+    s = rng.integers(0, n, m).astype(np.int32)
+    d = rng.integers(0, n, m).astype(np.int32)
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    A = np.zeros((n, n), np.int64)
+    for x in range(n):
+        A[x, col[row_off[x]:row_off[x + 1]]] = 1
+    assert oracle.probe_work(n, row_off, col) == int((A @ A).sum())
+
+
 def test_probe_work_against_numpy():
     n, s, d = gen.rmat(11, 8, gen.seed(91, 2))
     _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
