@@ -87,8 +87,25 @@ typedef enum pgabb_status {
                                     probe_work_col of pgabb_graph_info_t, columns
                                     on a tie) and the server walks columns;
                                     both flags are EINVAL */
+#define PGABB_OPT_HYBRID   0x20u /* hybrid host + device count (Section 4.4:
+                                    heavy block-lists on the device, light
+                                    ones on host threads; Section 3.6's host
+                                    kernel).  The blocks are counted from the
+                                    pinned host block store (moved there
+                                    first if they are on the device): the
+                                    device streams windows of the heaviest
+                                    remaining tasks while host threads take
+                                    the lightest remaining tasks one at a
+                                    time, until the two meet (host_permille
+                                    = 0), or the host takes a fixed share of
+                                    the estimated work (host_permille > 0) */
 
 typedef struct pgabb_tc_options {
+    int32_t p;                 /* grid size of the count (Section 4.3): 0 = keep
+                                  the graph's partition (p = 1 if it has none);
+                                  1 .. 64 = partition with p and cut_mode first
+                                  unless the graph already is */
+    int32_t cut_mode;          /* PGABB_CUT_*, used when p > 0 */
     int32_t kernel;            /* PGABB_KERNEL_* */
     int32_t num_streams;       /* compute streams of the streamer (0 = 4) */
     uint64_t device_cap_bytes; /* 0 = no cap; otherwise block cache bound */
@@ -102,7 +119,14 @@ typedef struct pgabb_tc_options {
     int32_t unroll;            /* 64-element chunks of walked lists per load
                                   batch (the next batch loads while one is
                                   probed): 1, 2, 4 or 8 (0 = 2) */
-    int32_t reserved;          /* must be 0 */
+    int32_t host_threads;      /* PGABB_OPT_HYBRID only: host threads that
+                                  count the light tasks (0 = one per core,
+                                  at most 64) */
+    int32_t host_permille;     /* PGABB_OPT_HYBRID only: share of the tasks'
+                                  estimated work, per mille, given to the
+                                  host threads, lightest tasks first
+                                  (0 = chosen from measured rates, see
+                                  pgabb_tc_count_ex; 1000 = every task) */
 } pgabb_tc_options;
 
 typedef struct pgabb_graph pgabb_graph;
@@ -131,6 +155,9 @@ typedef struct pgabb_graph_info_t {
                                 cuts: sum over oriented edges (u,v) of
                                 |{w in N+(u): stripe(w) >= stripe(v)}| */
     int64_t walked_columns;  /* 1 if the last count walked columns, 0 rows */
+    int64_t host_tasks;      /* tasks the host kernel counted in the last count
+                                (PGABB_OPT_HYBRID; 0 otherwise) */
+    double host_work_share;  /* their share of the tasks' estimated work */
 } pgabb_graph_info_t;
 
 /*
@@ -177,13 +204,25 @@ uint64_t pgabb_tc_count(pgabb_graph *g);
 pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
 
 /*
- * Count several graph objects (PGAbB Section 3.6's count, per graph):
+ * Count several graph objects (PGAbB Section 3.6's count, per graph; Section
+ * 4.4's task-parallel execution over the tasks of all of them):
  * counts[q] for gs[q], q < num_graphs (host array of num_graphs entries).
- * Each graph is counted as by pgabb_tc_count_ex with opts (NULL = defaults),
- * in order, on its own stream.  To count thousands of small graphs in one
- * launch, build a pgabb_batch from their edge lists instead.  EINVAL for a
- * NULL array or graph or num_graphs < 0; on any error the counts from the
- * failing graph on are PGABB_COUNT_ERROR.
+ * Each graph is partitioned as opts says (see pgabb_tc_options.p).  The
+ * tasks of every graph whose blocks are in device memory run in ONE
+ * persistent counting launch on the library's stream (after each graph's
+ * stream has reached the call); a graph whose blocks are in the host store,
+ * or that opts ask to stream or count hybrid, is counted on its own, as by
+ * pgabb_tc_count_ex.  opts == NULL selects the default options with an
+ * autotuned launch shape: waves per workgroup, items per grab and chunks per
+ * load batch are timed on the launch itself the first time a shape class is
+ * seen, and the winner is kept in a tuning cache (in memory and in the file
+ * named by PGABB_TUNE_CACHE, else $XDG_CACHE_HOME/pgabb/tune.txt or
+ * $HOME/.cache/pgabb/tune.txt).  Afterwards each graph's
+ * pgabb_graph_task_counts holds its own tasks' counts and
+ * pgabb_graph_info_get the shared launch's times.  Errors: EINVAL
+ * (num_graphs < 0, a NULL array or graph, a graph listed twice, bad
+ * options), ENOMEM, EDEVICE; on any error every count is PGABB_COUNT_ERROR.
+ * Many small graphs built together count faster as a pgabb_batch.
  */
 pgabb_status pgabb_tc_count_batch(pgabb_graph *const *gs, int64_t num_graphs, const pgabb_tc_options *opts,
                                   uint64_t *counts);
@@ -405,12 +444,19 @@ pgabb_status pgabb_server_submit(pgabb_server *s, int32_t n, int64_t m, const in
                                  const int32_t *dst, uint64_t *ticket);
 
 /*
- * *done = 1 and *count = triangles once the request finished, else *done = 0.
- * Timestamps (seconds on the server's monotonic clock) of submission and
- * completion are written when the pointers are not NULL.
+ * *done = 1 and *count = triangles once the request finished, else *done = 0
+ * (count may be NULL).  A finished request that failed returns its status
+ * (EINVAL for an id outside [0, n), ENOMEM, EDEVICE).  EINVAL for a NULL
+ * server or done, or an unknown ticket.
  */
-pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count,
-                               double *t_submit, double *t_done);
+pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count);
+
+/*
+ * Timestamps of a request, in seconds on the server's monotonic clock
+ * (pgabb_server_now): submission, and completion (0 while it runs).  Either
+ * pointer may be NULL.  EINVAL for a NULL server or an unknown ticket.
+ */
+pgabb_status pgabb_server_times(pgabb_server *s, uint64_t ticket, double *t_submit, double *t_done);
 
 /* Block until every submitted request has finished. */
 pgabb_status pgabb_server_drain(pgabb_server *s);

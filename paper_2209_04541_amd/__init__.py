@@ -30,6 +30,7 @@ OPT_STREAM = 0x1
 OPT_ROWS = 0x8
 SUPPORT_ON_DEVICE = 0x1
 OPT_COLS = 0x10
+OPT_HYBRID = 0x20
 
 
 class PgabbError(RuntimeError):
@@ -39,10 +40,12 @@ class PgabbError(RuntimeError):
 
 
 class TcOptions(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("num_streams", ctypes.c_int32),
+    _fields_ = [("p", ctypes.c_int32), ("cut_mode", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("num_streams", ctypes.c_int32),
                 ("device_cap_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32),
-                ("unroll", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("unroll", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+                ("host_permille", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -54,7 +57,8 @@ class GraphInfo(ctypes.Structure):
                 ("t_build_ms", ctypes.c_double), ("t_partition_ms", ctypes.c_double),
                 ("t_count_ms", ctypes.c_double), ("t_kernel_ms", ctypes.c_double),
                 ("kernel_launches", ctypes.c_int64), ("probe_work_col", ctypes.c_uint64),
-                ("walked_columns", ctypes.c_int64)]
+                ("walked_columns", ctypes.c_int64), ("host_tasks", ctypes.c_int64),
+                ("host_work_share", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,8 +114,8 @@ def lib():
             "pgabb_batch_destroy": (None, [vp]),
             "pgabb_server_create": (st, [u64, vp, ctypes.POINTER(vp)]),
             "pgabb_server_submit": (st, [vp, i32, i64, vp, vp, ctypes.POINTER(u64)]),
-            "pgabb_server_poll": (st, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(u64),
-                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+            "pgabb_server_poll": (st, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(u64)]),
+            "pgabb_server_times": (st, [vp, u64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "pgabb_server_drain": (st, [vp]),
             "pgabb_server_now": (ctypes.c_double, [vp]),
             "pgabb_server_stats": (st, [vp, ctypes.POINTER(u64)]),
@@ -173,14 +177,24 @@ def _edges(src, dst):
 
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
-            waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=None):
+            waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=None, p=0, cut_mode=CUT_NNZ,
+            hybrid=False, host_threads=0, host_permille=0):
     """by_rows: True walks edge blocks by rows, False by columns, None lets
-    the library take the walk that reads fewer entries."""
+    the library take the walk that reads fewer entries.  p > 0 partitions
+    the graph with p (and cut_mode) before the count unless it already is.
+    hybrid: light tasks on host threads (host_permille: fixed share of the
+    estimated work, 0 = both sides pull from one queue until they meet)."""
     o = TcOptions()
+    o.p = p
+    o.cut_mode = cut_mode
+    o.host_threads = host_threads
+    o.host_permille = host_permille
     o.kernel = kernel
     o.num_streams = num_streams
     o.device_cap_bytes = device_cap_bytes
     o.flags = OPT_STREAM if stream_blocks else 0
+    if hybrid:
+        o.flags |= OPT_HYBRID
     if by_rows is not None:
         o.flags |= OPT_ROWS if by_rows else OPT_COLS
     o.waves_per_block = waves_per_block
@@ -355,7 +369,8 @@ def graph_info(g):
 
 
 def tc_count_batch(graphs, opts=None, **kw):
-    """Counts of several Graph objects, one after another."""
+    """Counts of several Graph objects in one merged launch (no options:
+    autotuned launch shape)."""
     if opts is None and kw:
         opts = options(**kw)
     hs = (ctypes.c_void_p * max(len(graphs), 1))(*[g._h for g in graphs])
@@ -475,15 +490,21 @@ class Server:
         return t.value
 
     def poll(self, ticket):
+        """(done, count, t_submit, t_done) of a request."""
         done = ctypes.c_int32()
         cnt = ctypes.c_uint64()
-        ts, td = ctypes.c_double(), ctypes.c_double()
-        st = lib().pgabb_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(cnt),
-                                     ctypes.byref(ts), ctypes.byref(td))
+        st = lib().pgabb_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(cnt))
         if done.value and self.borrow:
             self._borrowed.pop(ticket, None)
         _check(st)
-        return bool(done.value), int(cnt.value), ts.value, td.value
+        ts, td = self.times(ticket) if done.value else (0.0, 0.0)
+        return bool(done.value), int(cnt.value), ts, td
+
+    def times(self, ticket):
+        """(t_submit, t_done) on the server clock; t_done is 0 while it runs."""
+        ts, td = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pgabb_server_times(self._h, ticket, ctypes.byref(ts), ctypes.byref(td)))
+        return ts.value, td.value
 
     def drain(self):
         _check(lib().pgabb_server_drain(self._h))

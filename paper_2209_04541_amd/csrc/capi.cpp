@@ -84,6 +84,10 @@ using namespace pgabb;
         return set_err(PGABB_EDEVICE, "unexpected internal error");      \
     }
 
+// Largest grid: the partition kernels give each stripe of a row one lane of
+// a 64-wide wavefront.
+static constexpr int32_t kMaxGrid = 64;
+
 PGABB_API pgabb_status pgabb_last_status(void) { return t_status; }
 PGABB_API const char *pgabb_last_error(void) { return t_message.c_str(); }
 PGABB_API const char *pgabb_version(void) { return "pgabb-mi355x 0.1 (gfx950)"; }
@@ -167,7 +171,7 @@ PGABB_API pgabb_status pgabb_graph_from_edges(int32_t n, int64_t m, const int32_
 
 PGABB_API pgabb_status pgabb_partition_ex(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t *cuts) {
     if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
-    if (p < 1 || p > 64) return set_err(PGABB_EINVAL, "p must lie in [1, 64]");
+    if (p < 1 || p > kMaxGrid) return set_err(PGABB_EINVAL, "p must lie in [1, 64]");
     if (cut_mode != PGABB_CUT_NNZ && cut_mode != PGABB_CUT_UNIFORM)
         return set_err(PGABB_EINVAL, "unknown cut mode");
     if (cuts) {
@@ -201,8 +205,12 @@ static pgabb_status check_options(const pgabb_tc_options &o) {
         return set_err(PGABB_EINVAL, "waves_per_block must be 2, 4 or 8");
     if (o.unroll && o.unroll != 1 && o.unroll != 2 && o.unroll != 4 && o.unroll != 8)
         return set_err(PGABB_EINVAL, "unroll must be 1, 2, 4 or 8");
-    if (o.reserved) return set_err(PGABB_EINVAL, "reserved option field must be 0");
-    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW | PGABB_OPT_ROWS | PGABB_OPT_COLS))
+    if (o.p < 0 || o.p > kMaxGrid) return set_err(PGABB_EINVAL, "p must lie in [0, 64]");
+    if (o.cut_mode != PGABB_CUT_NNZ && o.cut_mode != PGABB_CUT_UNIFORM) return set_err(PGABB_EINVAL, "unknown cut mode");
+    if (o.host_threads < 0 || o.host_threads > 64) return set_err(PGABB_EINVAL, "host_threads must lie in [0, 64]");
+    if (o.host_permille < 0 || o.host_permille > 1000) return set_err(PGABB_EINVAL, "host_permille must lie in [0, 1000]");
+    if (o.flags & ~(PGABB_OPT_STREAM | PGABB_OPT_PER_GRAPH | PGABB_SERVER_BORROW | PGABB_OPT_ROWS | PGABB_OPT_COLS |
+                    PGABB_OPT_HYBRID))
         return set_err(PGABB_EINVAL, "unknown option flag bits");
     if ((o.flags & PGABB_OPT_ROWS) && (o.flags & PGABB_OPT_COLS))
         return set_err(PGABB_EINVAL, "PGABB_OPT_ROWS and PGABB_OPT_COLS together");
@@ -298,16 +306,23 @@ PGABB_API pgabb_status pgabb_tc_count_shard(pgabb_graph *g, const pgabb_tc_optio
 PGABB_API pgabb_status pgabb_tc_count_batch(pgabb_graph *const *gs, int64_t num_graphs,
                                             const pgabb_tc_options *opts, uint64_t *counts) {
     if (num_graphs < 0) return set_err(PGABB_EINVAL, "num_graphs < 0");
-    if (num_graphs > 0 && (!gs || !counts)) return set_err(PGABB_EINVAL, "NULL argument");
+    if (num_graphs == 0) return set_ok();
+    if (!gs || !counts) return set_err(PGABB_EINVAL, "NULL argument");
+    for (int64_t q = 0; q < num_graphs; ++q) counts[q] = PGABB_COUNT_ERROR;
     for (int64_t q = 0; q < num_graphs; ++q) {
-        const pgabb_status st = gs[q] ? pgabb_tc_count_ex(gs[q], opts, &counts[q])
-                                      : set_err(PGABB_EINVAL, "graph is NULL");
-        if (st != PGABB_OK) {
-            for (int64_t r = q; r < num_graphs; ++r) counts[r] = PGABB_COUNT_ERROR;
-            return st;
-        }
+        if (!gs[q]) return set_err(PGABB_EINVAL, "graph is NULL");
+        for (int64_t r = 0; r < q; ++r)
+            if (gs[r] == gs[q]) return set_err(PGABB_EINVAL, "a graph is listed twice");
     }
+    const pgabb_tc_options o = opts ? *opts : default_options();
+    const pgabb_status st = check_options(o);
+    if (st != PGABB_OK) return st;
+    std::vector<uint64_t> out(static_cast<size_t>(num_graphs), PGABB_COUNT_ERROR);
+    PGABB_TRY
+    count_graphs(gs, num_graphs, o, opts == nullptr, out.data());
+    std::memcpy(counts, out.data(), sizeof(uint64_t) * out.size());
     return set_ok();
+    PGABB_CATCH
 }
 
 PGABB_API uint64_t pgabb_tc_count(pgabb_graph *g) {
@@ -344,6 +359,8 @@ PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_in
     info->kernel_launches = g->kernel_launches;
     info->probe_work_col = g->probe_work_col;
     info->walked_columns = g->walked_columns;
+    info->host_tasks = g->host_tasks;
+    info->host_work_share = g->host_work_share;
     return set_ok();
 }
 

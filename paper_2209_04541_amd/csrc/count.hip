@@ -130,6 +130,10 @@ void launch_one(const CountArgs &a, int mode, int lds_words, int waves, hipStrea
     }
 }
 
+__global__ void k_zero_queues(unsigned long long *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
 }  // namespace
 
 void launch_tc_tasks(const CountArgs &args, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
@@ -144,7 +148,11 @@ void launch_tc_tasks(const CountArgs &args, const LaunchKind &lk, int waves, hip
     // the parts of a split launch run at the default shape (waves and unroll
     // options apply to single launches)
     for (int q = 0; q < lk.nparts; ++q) {
-        if (q > 0) PGABB_HIP(hipMemsetAsync(a.next, 0, sizeof(unsigned long long) * kQueueWords, s));
+        if (q > 0) {
+            // a fill kernel, not a memset node: callers may capture the launch
+            k_zero_queues<<<1, 256, 0, s>>>(a.next, kQueueWords);
+            PGABB_HIP(hipGetLastError());
+        }
         a.stage_lo = q == 0 ? 0 : lk.hi[q - 1];
         a.stage_hi = lk.hi[q];
         launch_filtered(a, lk.pmode[q], lk.pwords[q], s, grid_override);
@@ -314,16 +322,28 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     return total;
 }
 
+// The partition a count with these options runs on: the graph's own (p = 1
+// if it has none), or opt.p with opt.cut_mode when they differ from it.
+void ensure_partition(pgabb_graph *g, const pgabb_tc_options &opt) {
+    if (opt.p > 0) {
+        if (g->p != opt.p || g->cut_mode != opt.cut_mode) partition_graph(g, opt.p, opt.cut_mode, nullptr);
+    } else if (g->p == 0) {
+        partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    }
+}
+
 uint64_t count_graph(pgabb_graph *g, const pgabb_tc_options &opt) {
-    if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    ensure_partition(g, opt);
     auto t0 = std::chrono::steady_clock::now();
     g->h2d_bytes = 0;
     g->t_kernel_ms = 0;
     g->kernel_launches = 0;
+    g->host_tasks = 0;
+    g->host_work_share = 0;
     uint64_t total = 0;
     if (!g->tasks.empty()) {
         const uint64_t block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
-        const bool stream = g->blocks_on_host || (opt.flags & PGABB_OPT_STREAM) ||
+        const bool stream = g->blocks_on_host || (opt.flags & (PGABB_OPT_STREAM | PGABB_OPT_HYBRID)) ||
                             (opt.device_cap_bytes && block_bytes > opt.device_cap_bytes);
         total = stream ? count_streamed(g, opt) : count_in_core(g, opt);
     } else {
@@ -391,7 +411,7 @@ std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards) {
 }
 
 uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards) {
-    if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    ensure_partition(g, opt);
     const std::vector<int32_t> of = task_shards(g, nshards);
     const int orient = orient_of_option(opt, g);
     std::vector<int32_t> idx;  // the shard's tasks, heaviest first as in the full list
@@ -424,6 +444,142 @@ uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard,
     g->task_counts.assign(g->tasks.size(), 0);
     for (size_t q = 0; q < idx.size() && q < sub.size(); ++q) g->task_counts[idx[q]] = sub[q];
     return total;
+}
+
+// Counts of several graph objects.  Every graph whose blocks are in device
+// memory joins one counting launch over all of their tasks (each task keeps
+// its own counter, so each graph's per-task counts come back too); a graph
+// whose blocks are streamed from the host store, or that opts ask to stream
+// or count hybrid, is counted on its own.  With tune, the launch shape
+// (waves per workgroup, items per grab, chunks per load batch) is the
+// fastest of a few candidates timed on this launch, remembered by shape
+// class (graph count, tasks, items, walked entries per item, longest staged
+// list) in the persisted tuning cache.
+void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt, bool tune, uint64_t *counts) {
+    std::vector<int64_t> merged;
+    for (int64_t q = 0; q < G; ++q) {
+        pgabb_graph *g = gs[q];
+        ensure_partition(g, opt);
+        const uint64_t block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
+        const bool alone = g->blocks_on_host || (opt.flags & (PGABB_OPT_STREAM | PGABB_OPT_HYBRID)) ||
+                           (opt.device_cap_bytes && block_bytes > opt.device_cap_bytes);
+        if (alone) counts[q] = count_graph(g, opt);
+        else merged.push_back(q);
+    }
+    if (merged.empty()) return;
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = library_stream();
+    const int orient = orient_of_option(opt, nullptr);
+    std::vector<TaskDesc> tdv;
+    std::vector<int64_t> prev(1, 0);
+    int32_t max_wk = 0, min_wk = INT32_MAX, max_st = 0;
+    uint64_t walked = 0;
+    for (int64_t q : merged) {
+        pgabb_graph *g = gs[q];
+        g->walked_columns = orient == kOrientCol;
+        g->h2d_bytes = 0;
+        g->host_tasks = 0;
+        g->host_work_share = 0;
+        walked += walked_entries(g, orient);
+        for (const Task &t : g->tasks) {
+            tdv.push_back(make_desc(g, g->arena.get(), t, static_cast<int32_t>(tdv.size()), nullptr));
+            prev.push_back(prev.back() + task_items(g, t, orient));
+            max_wk = std::max(max_wk, tdv.back().width_k);
+            min_wk = std::min(min_wk, tdv.back().width_k);
+            max_st = std::max(max_st, staged_max(g, t, orient));
+        }
+        // the launch runs on the library stream after the graph's own work
+        hipEvent_t ev = nullptr;
+        PGABB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        PGABB_HIP(hipEventRecord(ev, g->stream));
+        PGABB_HIP(hipStreamWaitEvent(s, ev, 0));
+        PGABB_HIP(hipEventDestroy(ev));
+    }
+    const int32_t T = static_cast<int32_t>(tdv.size());
+    std::vector<uint64_t> tc(T, 0);
+    double kernel_ms = 0;
+    int launches = 0;
+    if (T > 0) {
+        Staged<TaskDesc> td(T, s);
+        Staged<int64_t> pre(static_cast<size_t>(T) + 1, s);
+        std::copy(tdv.begin(), tdv.end(), td.get());
+        std::copy(prev.begin(), prev.end(), pre.get());
+        DArray<TaskDesc> dtd(T, s);
+        DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
+        DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kQueueWords, s);
+        PGABB_HIP(hipMemcpyAsync(dtd.get(), td.get(), td.bytes(), hipMemcpyHostToDevice, s));
+        PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.get(), pre.bytes(), hipMemcpyHostToDevice, s));
+        CountArgs a;
+        a.tasks = dtd.get();
+        a.item_pre = dpre.get();
+        a.ntasks = T;
+        a.total = prev.back();
+        a.counts = dcnt.get();
+        a.next = dcnt.get() + T;
+        a.orient = orient;
+        const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
+        const int g0 = default_grab(a.total, walked);
+        int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
+        int grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : g0;
+        int unroll = opt.unroll;
+        StreamTimer tm;
+        auto run = [&](int w, int gr, int un) {
+            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kQueueWords), s));
+            a.grab = gr;
+            tm.start(s);
+            launch_tc_tasks(a, lk, w, s, 0, un);
+            tm.stop(s);
+            return tm.ms();
+        };
+        if (tune && lk.nparts == 1 && a.total > 0) {
+            const uint64_t per_item = a.total ? walked / static_cast<uint64_t>(a.total) : 0;
+            char key[160];
+            snprintf(key, sizeof key, "tc_graphs/G%d/T%d/I%d/W%d/S%d/K%d/O%d", bit_width_u64(merged.size()),
+                     bit_width_u64(T), bit_width_u64(a.total), bit_width_u64(per_item), bit_width_u64(max_st),
+                     lk.mode, orient);
+            std::vector<int> v;
+            if (tune_lookup(key, v) && v.size() == 3) {
+                waves = v[0];
+                grab = v[1];
+                unroll = v[2];
+            } else {
+                double best = 1e30;
+                for (int w : {2, 4, 8})
+                    for (int gr : {std::max(1, g0 / 2), g0, std::min(64, 2 * g0)})
+                        for (int un : {2, 4}) {
+                            run(w, gr, un);  // warm
+                            const double ms = std::min(run(w, gr, un), run(w, gr, un));
+                            if (ms < best) {
+                                best = ms;
+                                waves = w;
+                                grab = gr;
+                                unroll = un;
+                            }
+                        }
+                tune_store(key, {waves, grab, unroll});
+            }
+        }
+        kernel_ms = run(waves, grab, unroll);
+        launches = lk.nparts;
+        Staged<unsigned long long> hcnt(T, s);
+        PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), hcnt.bytes(), hipMemcpyDeviceToHost, s));
+        PGABB_HIP(hipStreamSynchronize(s));
+        std::copy(hcnt.get(), hcnt.get() + T, tc.begin());
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    size_t at = 0;
+    for (int64_t q : merged) {
+        pgabb_graph *g = gs[q];
+        const size_t nt = g->tasks.size();
+        g->task_counts.assign(tc.begin() + at, tc.begin() + at + nt);
+        at += nt;
+        uint64_t total = 0;
+        for (uint64_t c : g->task_counts) total += c;
+        counts[q] = total;
+        g->t_count_ms = ms;
+        g->t_kernel_ms = kernel_ms;
+        g->kernel_launches = launches;
+    }
 }
 
 }  // namespace pgabb

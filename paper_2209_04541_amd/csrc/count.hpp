@@ -57,11 +57,17 @@ int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 // walks).
 int32_t staged_max(const pgabb_graph *g, const Task &t, int orient);
 // One launch per part (see LaunchKind); a.next is cleared again between
-// them, so a split launch must not be captured into a graph.
+// them by a fill kernel.
 void launch_tc_tasks(const CountArgs &a, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
                      int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,
                    const int64_t *chunk_dev_off);
 uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt);
+// Entries a task's walk reads plus those its items stage, estimated from
+// block sizes (each list length taken as its block's mean).
+int64_t task_work_estimate(const pgabb_graph *g, const Task &t, int orient);
+// Host kernel: triangles of task t from block chunks in host memory (the
+// host store `arena`, laid out as the device arena).
+uint64_t host_count_task(const pgabb_graph *g, const int32_t *arena, const Task &t);
 
 }  // namespace pgabb

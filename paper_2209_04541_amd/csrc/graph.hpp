@@ -108,6 +108,7 @@ struct pgabb_graph {
 
     // partition
     int32_t p = 0;
+    int32_t cut_mode = -1;      // PGABB_CUT_* of the partition, -1 for caller cuts
     std::vector<int32_t> cuts;  // p + 1
     std::vector<int32_t> base;  // p: first rank of the dense row range
     std::vector<pgabb::BlockInfo> blocks;
@@ -126,6 +127,8 @@ struct pgabb_graph {
     bool part_time_pending = false;
     int64_t kernel_launches = 0;
     uint64_t h2d_bytes = 0;
+    int64_t host_tasks = 0;        // tasks the host kernel counted in the last count
+    double host_work_share = 0;    // their share of the tasks' estimated work
 };
 
 namespace pgabb {
@@ -135,6 +138,8 @@ hipStream_t library_stream();
 void build_graph(pgabb_graph *g, const int32_t *src_dev, const int32_t *dst_dev, int64_t m);
 void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t *cuts_host);
 uint64_t count_graph(pgabb_graph *g, const pgabb_tc_options &opt);
+// Partition g as a count with opt requires (see pgabb_tc_options.p).
+void ensure_partition(pgabb_graph *g, const pgabb_tc_options &opt);
 // Shard of each task when the tasks are split over nshards devices.
 std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards);
 // Triangles containing each oriented edge, into out[m'] (device or host
@@ -148,6 +153,9 @@ uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);
 int64_t ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, bool on_device, int32_t *rounds);
 // Sets of four pairwise adjacent vertices.
 uint64_t four_cliques(pgabb_graph *g);
+// Counts of several graphs, in one launch where their blocks are in device
+// memory (tune: launch shape from the autotuner).
+void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt, bool tune, uint64_t *counts);
 // Count only the tasks task_shards deals to `shard`.
 uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards);
 

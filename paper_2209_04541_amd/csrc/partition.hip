@@ -590,6 +590,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
     g->task_counts.clear();
     g->block_of.assign(static_cast<size_t>(p) * p, -1);
     g->p = p;
+    g->cut_mode = cuts_host ? -1 : cut_mode;
     g->arena_words = 0;
     g->probe_work_col = 0;
 

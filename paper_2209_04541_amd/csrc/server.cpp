@@ -323,8 +323,7 @@ PGABB_API pgabb_status pgabb_server_submit(pgabb_server *s, int32_t n, int64_t m
     return capture_status(Error{PGABB_OK, ""});
 }
 
-PGABB_API pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count,
-                                         double *t_submit, double *t_done) {
+PGABB_API pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32_t *done, uint64_t *count) {
     if (!s || !done) return capture_status(Error{PGABB_EINVAL, "NULL argument"});
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->all.find(ticket);
@@ -332,10 +331,19 @@ PGABB_API pgabb_status pgabb_server_poll(pgabb_server *s, uint64_t ticket, int32
     Request *r = it->second.get();
     *done = r->done ? 1 : 0;
     if (count) *count = r->done ? r->count : PGABB_COUNT_ERROR;
-    if (t_submit) *t_submit = r->t_submit;
-    if (t_done) *t_done = r->t_done;
     if (r->done && r->status != PGABB_OK)
         return capture_status(Error{r->status, "request failed"});
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_server_times(pgabb_server *s, uint64_t ticket, double *t_submit, double *t_done) {
+    if (!s) return capture_status(Error{PGABB_EINVAL, "server is NULL"});
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return capture_status(Error{PGABB_EINVAL, "unknown ticket"});
+    Request *r = it->second.get();
+    if (t_submit) *t_submit = r->t_submit;
+    if (t_done) *t_done = r->done ? r->t_done : 0.0;
     return capture_status(Error{PGABB_OK, ""});
 }
 

@@ -63,7 +63,41 @@ def test_argument_errors_before_device_work():
     assert L.pgabb_tc_count_batch(gs, 2, None, counts) == P.EINVAL
     assert list(counts) == [P.COUNT_ERROR, P.COUNT_ERROR]
     assert L.pgabb_tc_count_batch(None, 0, None, None) == P.OK
+    # two distinct (never dereferenced) graph handles: the options are
+    # checked before any graph is touched
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    for field, value in (("p", 65), ("p", -1), ("cut_mode", 7), ("host_threads", 65),
+                         ("host_permille", 1001), ("kernel", 9), ("flags", 0x400)):
+        o = P.options()
+        setattr(o, field, value)
+        counts[0] = counts[1] = 7
+        assert L.pgabb_tc_count_batch(fake, 2, ctypes.byref(o), counts) == P.EINVAL, field
+        assert list(counts) == [P.COUNT_ERROR, P.COUNT_ERROR]
+    dup = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    assert L.pgabb_tc_count_batch(dup, 2, None, counts) == P.EINVAL
     L.pgabb_graph_destroy(None)  # NULL-safe
+
+
+def test_server_calls_reject_null():
+    """pgabb_server_poll(s, ticket, done, count) and pgabb_server_times."""
+    L = P.lib()
+    done, cnt = ctypes.c_int32(), ctypes.c_uint64()
+    ts, td = ctypes.c_double(), ctypes.c_double()
+    assert L.pgabb_server_poll(None, 1, ctypes.byref(done), ctypes.byref(cnt)) == P.EINVAL
+    assert L.pgabb_server_times(None, 1, ctypes.byref(ts), ctypes.byref(td)) == P.EINVAL
+    assert L.pgabb_server_create(0, None, None) == P.EINVAL
+    assert L.pgabb_server_submit(None, 1, 0, None, None, None) == P.EINVAL
+
+
+def test_options_struct_names_the_grid():
+    """pgabb_tc_options carries the grid p and the cut mode (the count can
+    partition on its own), and the hybrid fields."""
+    names = [f for f, _ in P.TcOptions._fields_]
+    assert names[:2] == ["p", "cut_mode"]
+    assert {"host_threads", "host_permille", "device_cap_bytes", "num_streams"} <= set(names)
+    o = P.options(p=8, cut_mode=P.CUT_UNIFORM, hybrid=True, host_permille=250)
+    assert (o.p, o.cut_mode, o.host_permille) == (8, P.CUT_UNIFORM, 250)
+    assert o.flags & P.OPT_HYBRID
 
 
 def test_allocator_hook_argument_check():
