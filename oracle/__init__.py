@@ -9,8 +9,11 @@ computes the triangle count of an undirected graph by its plain definition in
 the oriented form the paper uses (PGAbB Section 3.6 for the problem and the
 per-edge common-neighbour count over a block-list, Section 5.1 for cleaning,
 Section 5.4 for degree ordering and the oriented half of the edges), and the
-triangles containing each edge (edge support) and each vertex.  This module is
-a thin ctypes wrapper around it.
+triangles containing each edge (edge support) and each vertex.
+``bsp_oracle.c`` computes the two single-block bulk-synchronous examples
+(Section 3.2): connected components by their definition (Section 3.4) and
+PageRank by its iteration (Section 5.2).  This module is a thin ctypes wrapper
+around both.
 """
 from __future__ import annotations
 
@@ -22,17 +25,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tc_oracle.c")
+_SRC_BSP = os.path.join(_HERE, "bsp_oracle.c")
 LIB_PATH = os.path.join(_HERE, "liboracle_tc.so")
 
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile tc_oracle.c with gcc into liboracle_tc.so."""
+    """Compile tc_oracle.c and bsp_oracle.c with gcc into liboracle_tc.so."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu99",
-                               _SRC, "-o", tmp])
+                               "-ffp-contract=off", _SRC, _SRC_BSP, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -70,6 +74,11 @@ def _load():
         L.oracle_ktruss.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
         L.oracle_four_cliques.restype = ctypes.c_uint64
         L.oracle_four_cliques.argtypes = [ctypes.c_int32, vp, vp]
+        L.oracle_components.restype = ctypes.c_int64
+        L.oracle_components.argtypes = [ctypes.c_int32, vp, ctypes.c_int64, vp]
+        L.oracle_pagerank.restype = ctypes.c_int32
+        L.oracle_pagerank.argtypes = [ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int32, vp, vp]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -237,3 +246,28 @@ def tc(n: int, src, dst, mode: int = 0) -> int:
     if t == 2**64 - 1:
         raise ValueError("vertex id out of range")
     return int(t)
+
+
+def components(n: int, src, dst):
+    """(label, count): label[v] = smallest vertex id reachable from v."""
+    keys = clean(n, src, dst)
+    lab = np.empty(max(n, 1), dtype=np.int32)
+    k = np.ascontiguousarray(keys if len(keys) else np.zeros(1, np.uint64))
+    c = _load().oracle_components(n, _p(k), len(keys), _p(lab))
+    if c < 0:
+        raise MemoryError("oracle_components")
+    return lab[:n], int(c)
+
+
+def pagerank(n: int, src, dst, damping: float = 0.85, tol: float = 1e-4, max_iter: int = 20):
+    """(ranks float64[n], iterations, last error) of the PageRank iteration
+    on the undirected graph behind (src, dst)."""
+    keys = clean(n, src, dst)
+    r = np.empty(max(n, 1), dtype=np.float64)
+    k = np.ascontiguousarray(keys if len(keys) else np.zeros(1, np.uint64))
+    err = ctypes.c_double()
+    it = _load().oracle_pagerank(n, _p(k), len(keys), float(damping), float(tol), int(max_iter), _p(r),
+                                 ctypes.byref(err))
+    if it < 0:
+        raise MemoryError("oracle_pagerank")
+    return r[:n], int(it), float(err.value)
