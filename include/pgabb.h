@@ -127,6 +127,11 @@ typedef struct pgabb_tc_options {
                                   host threads, lightest tasks first
                                   (0 = chosen from measured rates, see
                                   pgabb_tc_count_ex; 1000 = every task) */
+    int32_t queue_run;         /* work units (grabs) per run dealt to one of
+                                  the counting launch's 8 work queues, one
+                                  queue per XCD (0 = 1: round-robin); values
+                                  of an eighth of the launch's units or more
+                                  give one contiguous range per queue */
 } pgabb_tc_options;
 
 typedef struct pgabb_graph pgabb_graph;
@@ -158,6 +163,9 @@ typedef struct pgabb_graph_info_t {
     int64_t host_tasks;      /* tasks the host kernel counted in the last count
                                 (PGABB_OPT_HYBRID; 0 otherwise) */
     double host_work_share;  /* their share of the tasks' estimated work */
+    int64_t row_items;       /* work items over all blocks' rows (runs of at
+                                most 32 entries of one row of one block) */
+    int64_t col_items;       /* the same over the blocks' columns */
 } pgabb_graph_info_t;
 
 /*
@@ -371,6 +379,54 @@ pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t 
  */
 pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count);
 
+/*
+ * Connected components (the Shiloach-Vishkin example of PGAbB Section 3.4,
+ * single-block bulk-synchronous mode of Section 3.2) over the graph's device
+ * blocks: even iterations hook, for every edge whose endpoints point to
+ * different roots, the larger root under the smaller; odd iterations link
+ * every vertex to its root by pointer jumping; the iterations end after a
+ * hooking pass that hooked nothing.  A graph that was never partitioned is
+ * partitioned with p = 1 first.
+ *   label          : n int32; label[v] = the smallest input id in v's
+ *                    component (isolated vertices label themselves).  Host
+ *                    memory, or device memory with PGABB_SUPPORT_ON_DEVICE;
+ *                    complete when the call returns.  NULL allowed if n = 0.
+ *   num_components : optional; components, isolated vertices included
+ *   iterations     : optional; hooking plus linking iterations run (even)
+ * pgabb_graph_info_get then reports the call's time (t_count_ms), its kernel
+ * time and the iterations as launches.
+ * Errors: EINVAL (NULL graph, NULL label with n > 0, unknown flags), ESTATE
+ * (blocks held in host memory by a streamed count), ENOMEM, EDEVICE.
+ */
+pgabb_status pgabb_components(pgabb_graph *g, int32_t *label, uint32_t flags, int64_t *num_components,
+                              int32_t *iterations);
+
+/*
+ * PageRank (PGAbB Section 5.2: SpMV-like iteration, as its evaluation runs
+ * it with damping 0.85, tolerance 1e-4 and at most 20 iterations), in double
+ * precision over the graph's device blocks, pulled through every block's
+ * rows and stored columns with atomic additions (single-block bulk-
+ * synchronous mode, Section 3.2).  With deg(x) the number of neighbours:
+ *     r_0(x) = 1 / n,
+ *     r_{t+1}(x) = (1 - damping) / n + damping * sum over neighbours y of
+ *                  r_t(y) / deg(y);
+ * isolated vertices pass nothing on.  Stops after the first iteration whose
+ * sum over x of |r_{t+1}(x) - r_t(x)| is below tol, or after max_iter.
+ * A graph that was never partitioned is partitioned with p = 1 first.
+ *   ranks      : n doubles by input id; host memory, or device memory with
+ *                PGABB_SUPPORT_ON_DEVICE; complete when the call returns.
+ *                NULL allowed if n = 0.
+ *   iterations : optional; iterations run
+ *   last_err   : optional; the last iteration's sum of absolute changes
+ * Sums run in a different order from a sequential loop (atomic additions),
+ * so results agree with one to rounding, not bit for bit.
+ * Errors: EINVAL (NULL graph, NULL ranks with n > 0, damping outside
+ * [0, 1], tol < 0 or NaN, max_iter < 0, unknown flags), ESTATE, ENOMEM,
+ * EDEVICE.
+ */
+pgabb_status pgabb_pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, double *ranks,
+                            uint32_t flags, int32_t *iterations, double *last_err);
+
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
 
@@ -410,6 +466,16 @@ pgabb_status pgabb_batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uin
 
 /* Milliseconds of the last batch count (one replay) and of the build. */
 pgabb_status pgabb_batch_times(const pgabb_batch *b, double *t_build_ms, double *t_count_ms);
+
+/*
+ * Sizes of the batch's union graph (any pointer may be NULL): oriented
+ * edges m' over all graphs; active rows (out-degree >= 2, the count's work
+ * items) and their edges; entries a count walks (for every active row u,
+ * the out-lists of u's out-neighbours: sum over its edges (u, v) of
+ * |N+(v)|).
+ */
+pgabb_status pgabb_batch_stats(const pgabb_batch *b, int64_t *edges, int64_t *active_rows, int64_t *active_edges,
+                               uint64_t *walked);
 
 void pgabb_batch_destroy(pgabb_batch *b);
 

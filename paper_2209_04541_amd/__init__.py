@@ -45,7 +45,7 @@ class TcOptions(ctypes.Structure):
                 ("device_cap_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32),
                 ("unroll", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-                ("host_permille", ctypes.c_int32)]
+                ("host_permille", ctypes.c_int32), ("queue_run", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -58,7 +58,8 @@ class GraphInfo(ctypes.Structure):
                 ("t_count_ms", ctypes.c_double), ("t_kernel_ms", ctypes.c_double),
                 ("kernel_launches", ctypes.c_int64), ("probe_work_col", ctypes.c_uint64),
                 ("walked_columns", ctypes.c_int64), ("host_tasks", ctypes.c_int64),
-                ("host_work_share", ctypes.c_double)]
+                ("host_work_share", ctypes.c_double), ("row_items", ctypes.c_int64),
+                ("col_items", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +105,9 @@ def lib():
             "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_ktruss": (st, [vp, i32, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_count_4cliques": (st, [vp, ctypes.POINTER(u64)]),
+            "pgabb_components": (st, [vp, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+            "pgabb_pagerank": (st, [vp, ctypes.c_double, ctypes.c_double, i32, vp, u32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double)]),
             "pgabb_tc_count_shard": (st, [vp, vp, i32, i32, ctypes.POINTER(u64)]),
             "pgabb_graph_destroy": (None, [vp]),
             "pgabb_last_status": (st, []),
@@ -112,6 +116,8 @@ def lib():
             "pgabb_batch_count": (st, [vp, vp, vp]),
             "pgabb_batch_times": (st, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "pgabb_batch_destroy": (None, [vp]),
+            "pgabb_batch_stats": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                       ctypes.POINTER(u64)]),
             "pgabb_server_create": (st, [u64, vp, ctypes.POINTER(vp)]),
             "pgabb_server_submit": (st, [vp, i32, i64, vp, vp, ctypes.POINTER(u64)]),
             "pgabb_server_poll": (st, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(u64)]),
@@ -178,7 +184,7 @@ def _edges(src, dst):
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
             waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=None, p=0, cut_mode=CUT_NNZ,
-            hybrid=False, host_threads=0, host_permille=0):
+            hybrid=False, host_threads=0, host_permille=0, queue_run=0):
     """by_rows: True walks edge blocks by rows, False by columns, None lets
     the library take the walk that reads fewer entries.  p > 0 partitions
     the graph with p (and cut_mode) before the count unless it already is.
@@ -189,6 +195,7 @@ def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks
     o.cut_mode = cut_mode
     o.host_threads = host_threads
     o.host_permille = host_permille
+    o.queue_run = queue_run
     o.kernel = kernel
     o.num_streams = num_streams
     o.device_cap_bytes = device_cap_bytes
@@ -315,6 +322,29 @@ class Graph:
         _check(lib().pgabb_tc_ktruss(self._h, int(k), ctypes.c_void_p(keep.ctypes.data), 0, ctypes.byref(left),
                                      ctypes.byref(rounds)))
         return keep[:m], int(left.value), int(rounds.value)
+
+    def components(self):
+        """Connected components (Shiloach-Vishkin over the blocks): a numpy
+        int32 array label[v] = smallest input id in v's component, the
+        number of components and the iterations run."""
+        n = self.info()["n"]
+        label = np.empty(n, np.int32)
+        nc, it = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().pgabb_components(self._h, ctypes.c_void_p(label.ctypes.data) if n else None, 0,
+                                      ctypes.byref(nc), ctypes.byref(it)))
+        return label, int(nc.value), int(it.value)
+
+    def pagerank(self, damping=0.85, tol=1e-4, max_iter=20):
+        """PageRank over the blocks in double precision: a numpy float64
+        array of ranks by input id, the iterations run and the last
+        iteration's sum of absolute changes."""
+        n = self.info()["n"]
+        r = np.empty(n, np.float64)
+        it, err = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().pgabb_pagerank(self._h, float(damping), float(tol), int(max_iter),
+                                    ctypes.c_void_p(r.ctypes.data) if n else None, 0, ctypes.byref(it),
+                                    ctypes.byref(err)))
+        return r, int(it.value), float(err.value)
 
     def four_cliques(self):
         """Sets of four pairwise adjacent vertices."""
@@ -446,6 +476,13 @@ class Batch:
         b, c = ctypes.c_double(), ctypes.c_double()
         _check(lib().pgabb_batch_times(self._h, ctypes.byref(b), ctypes.byref(c)))
         return b.value, c.value
+
+    def stats(self):
+        """Sizes of the union graph: oriented edges, active rows (the
+        count's work items), their edges and the entries a count walks."""
+        e, r, ae, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+        _check(lib().pgabb_batch_stats(self._h, ctypes.byref(e), ctypes.byref(r), ctypes.byref(ae), ctypes.byref(w)))
+        return {"edges": e.value, "active_rows": r.value, "active_edges": ae.value, "walked": w.value}
 
     def close(self):
         if getattr(self, "_h", None):

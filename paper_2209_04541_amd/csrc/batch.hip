@@ -37,6 +37,8 @@ struct pgabb_batch {
     int nb = 1, gbits = 1;
     int64_t total_n = 0, total_m = 0, mu = 0, nactive = 0;
     int32_t max_out = 0, max_n = 0;
+    uint64_t walked = 0;    // entries the count walks: sum over active rows u of sum of |N+(v)|, v in N+(u)
+    int64_t m_active = 0;   // oriented edges of the active rows
     std::vector<int64_t> vbase;  // host, G + 1
     pgabb::DArray<int64_t> dvbase;
     pgabb::DArray<int32_t> rptr;      // total_n + 1
@@ -199,6 +201,27 @@ __global__ __launch_bounds__(B) void k_active_rows_b(const uint32_t *__restrict_
             rows[pos[x]] = static_cast<int32_t>(x);
             row_gid[pos[x]] = static_cast<int32_t>(g);
         }
+}
+
+// Entries a count walks (for each active row u, the lists N+(v) of its
+// out-neighbours v) and the oriented edges of the active rows.
+__global__ void k_walked_b(const int32_t *__restrict__ rows, int64_t nactive, const int32_t *__restrict__ rptr,
+                           const int32_t *__restrict__ col, unsigned long long *__restrict__ out) {
+    unsigned long long w = 0, e = 0;
+    for (int64_t q = blockIdx.x * int64_t(B) + threadIdx.x; q < nactive; q += int64_t(gridDim.x) * B) {
+        const int32_t u = rows[q];
+        for (int32_t t = rptr[u]; t < rptr[u + 1]; ++t) {
+            const int32_t v = col[t];
+            w += static_cast<unsigned long long>(rptr[v + 1] - rptr[v]);
+        }
+        e += static_cast<unsigned long long>(rptr[u + 1] - rptr[u]);
+    }
+    w = wave_sum(w);
+    e = wave_sum(e);
+    if (lane_id() == 0) {
+        if (w) atomicAdd(&out[0], w);
+        if (e) atomicAdd(&out[1], e);
+    }
 }
 
 __global__ void k_graph_row_pre_b(const uint32_t *__restrict__ pos, const int64_t *__restrict__ vbase,
@@ -560,7 +583,15 @@ void batch_build(pgabb_batch *b, const int32_t *n, const int64_t *eoff, const in
         if (G)
             PGABB_HIP(hipMemcpyAsync(b->h_graph_row_pre.data(), b->graph_row_pre.get(), sizeof(int64_t) * (G + 1),
                                      hipMemcpyDeviceToHost, s));
+        DArray<unsigned long long> wk(2, s);
+        k_zero_u64<<<1, B, 0, s>>>(wk.get(), 2);
+        if (na) k_walked_b<<<cap_grid(na), B, 0, s>>>(b->rows.get(), na, b->rptr.get(), b->col.get(), wk.get());
+        PGABB_HIP(hipGetLastError());
+        unsigned long long hw[2] = {0, 0};
+        PGABB_HIP(hipMemcpyAsync(hw, wk.get(), sizeof hw, hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
+        b->walked = hw[0];
+        b->m_active = static_cast<int64_t>(hw[1]);
     }
 }
 
@@ -682,6 +713,16 @@ PGABB_API pgabb_status pgabb_batch_times(const pgabb_batch *b, double *t_build_m
     if (!b) return capture_status(Error{PGABB_EINVAL, "batch is NULL"});
     if (t_build_ms) *t_build_ms = b->t_build_ms;
     if (t_count_ms) *t_count_ms = b->t_count_ms;
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_batch_stats(const pgabb_batch *b, int64_t *edges, int64_t *active_rows,
+                                         int64_t *active_edges, uint64_t *walked) {
+    if (!b) return capture_status(Error{PGABB_EINVAL, "batch is NULL"});
+    if (edges) *edges = b->mu;
+    if (active_rows) *active_rows = b->nactive;
+    if (active_edges) *active_edges = b->m_active;
+    if (walked) *walked = b->walked;
     return capture_status(Error{PGABB_OK, ""});
 }
 

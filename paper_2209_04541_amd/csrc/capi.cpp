@@ -199,7 +199,7 @@ static pgabb_tc_options default_options() {
 static pgabb_status check_options(const pgabb_tc_options &o) {
     if (o.kernel < PGABB_KERNEL_AUTO || o.kernel > PGABB_KERNEL_SEARCH)
         return set_err(PGABB_EINVAL, "unknown kernel");
-    if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0)
+    if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0 || o.queue_run < 0)
         return set_err(PGABB_EINVAL, "negative option");
     if (o.waves_per_block && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
         return set_err(PGABB_EINVAL, "waves_per_block must be 2, 4 or 8");
@@ -262,6 +262,33 @@ PGABB_API pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep,
     PGABB_TRY
     const int64_t left = ktruss(g, k, keep, (flags & PGABB_SUPPORT_ON_DEVICE) != 0, rounds);
     if (num_edges) *num_edges = left;
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_components(pgabb_graph *g, int32_t *label, uint32_t flags, int64_t *num_components,
+                                        int32_t *iterations) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!label && g->n > 0) return set_err(PGABB_EINVAL, "label is NULL");
+    if (flags & ~PGABB_SUPPORT_ON_DEVICE) return set_err(PGABB_EINVAL, "unknown flag bits");
+    PGABB_TRY
+    const int64_t c = components(g, label, (flags & PGABB_SUPPORT_ON_DEVICE) != 0, iterations);
+    if (num_components) *num_components = c;
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, double *ranks,
+                                      uint32_t flags, int32_t *iterations, double *last_err) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!ranks && g->n > 0) return set_err(PGABB_EINVAL, "ranks is NULL");
+    if (!(damping >= 0.0 && damping <= 1.0)) return set_err(PGABB_EINVAL, "damping outside [0, 1]");
+    if (!(tol >= 0.0)) return set_err(PGABB_EINVAL, "tol < 0 or NaN");
+    if (max_iter < 0) return set_err(PGABB_EINVAL, "max_iter < 0");
+    if (flags & ~PGABB_SUPPORT_ON_DEVICE) return set_err(PGABB_EINVAL, "unknown flag bits");
+    PGABB_TRY
+    const int32_t it = pagerank(g, damping, tol, max_iter, ranks, (flags & PGABB_SUPPORT_ON_DEVICE) != 0, last_err);
+    if (iterations) *iterations = it;
     return set_ok();
     PGABB_CATCH
 }
@@ -361,6 +388,12 @@ PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_in
     info->walked_columns = g->walked_columns;
     info->host_tasks = g->host_tasks;
     info->host_work_share = g->host_work_share;
+    info->row_items = 0;
+    info->col_items = 0;
+    for (const pgabb::BlockInfo &b : g->blocks) {
+        info->row_items += b.nitems;
+        info->col_items += b.ncitems;
+    }
     return set_ok();
 }
 

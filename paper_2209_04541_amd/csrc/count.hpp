@@ -5,9 +5,10 @@
 
 namespace pgabb {
 
-// Work queues of a counting launch: grab units are dealt round-robin to
-// kQueues counters; a workgroup starts on queue blockIdx % kQueues (its XCD
-// under round-robin dispatch) and moves on to the others once it is empty.
+// Work queues of a counting launch: grab units are dealt to kQueues counters
+// in runs of CountArgs::qrun consecutive units, run r to queue r % kQueues; a
+// workgroup starts on queue blockIdx % kQueues (its XCD under round-robin
+// dispatch) and moves on to the others once it is empty.
 constexpr int kQueues = 8;
 // Counters sit 256 bytes apart so no two share a memory channel's line.
 constexpr int kQueueStride = 32;
@@ -22,10 +23,14 @@ struct CountArgs {
     unsigned long long *counts;  // device, indexed by TaskDesc::slot
     unsigned long long *next;    // device, kQueueWords (zero before launch); queue q at q * kQueueStride
     int32_t orient;              // kOrientRow or kOrientCol (which item lists)
+    int64_t qrun = 0;            // grab units per run dealt to one queue (0 = queue_run's choice)
     int32_t stage_lo = 0;        // items whose staged list has more than stage_lo
     int32_t stage_hi = INT32_MAX;  // and at most stage_hi entries
 };
 
+// Grab units per run dealt to one work queue: `requested` if positive, else
+// 1 (round-robin).
+int64_t queue_run(int64_t units, int64_t requested);
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 // Kernel template (staging kind) and LDS words per wave of a counting launch,
 // from the kernel option, the longest staged list and the widths of stripe k

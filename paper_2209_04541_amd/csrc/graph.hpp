@@ -153,6 +153,14 @@ uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);
 int64_t ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, bool on_device, int32_t *rounds);
 // Sets of four pairwise adjacent vertices.
 uint64_t four_cliques(pgabb_graph *g);
+// Connected components by Shiloach-Vishkin over the device blocks:
+// label[v] = smallest input id of v's component; returns the number of
+// components.
+int64_t components(pgabb_graph *g, int32_t *label, bool on_device, int32_t *iterations);
+// PageRank over the device blocks (ranks by input id); returns the
+// iterations run.
+int32_t pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, double *ranks, bool on_device,
+                 double *last_err);
 // Counts of several graphs, in one launch where their blocks are in device
 // memory (tune: launch shape from the autotuner).
 void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt, bool tune, uint64_t *counts);

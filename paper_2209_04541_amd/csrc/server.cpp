@@ -230,6 +230,7 @@ static void counter_loop(pgabb_server *s) {
                 a.ntasks = T;
                 a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back(), walked);
                 a.orient = orient_of_option(s->opt, nullptr);
+                a.qrun = s->opt.queue_run;
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;

@@ -450,6 +450,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             // a grab sized from the mean would be too coarse for them
             a.grab = grab_opt > 0 ? grab_opt : default_grab(items, 0);
             a.orient = orient;
+            a.qrun = opt.queue_run;
             a.total = items;
             a.counts = dcnt.get();
             a.next = dcnt.get() + T + static_cast<size_t>(win) * kQueueWords;
