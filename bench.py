@@ -56,6 +56,24 @@ def measured_traffic(name, sources=KERNEL_SOURCES):
     return t.get("bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name and the cores this process may use."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": name, "cores_usable": usable}
+
+
 def golden(name):
     with open(os.path.join(ROOT, "tests", "golden", "workload_counts.json")) as f:
         return json.load(f).get(name)
@@ -152,6 +170,9 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
         "block_bytes": infos[0]["block_bytes"],
     })
     out["compulsory_bytes"] = 4 * m + 8 * n  # every oriented edge and row offset read once
+    if not args.no_hybrid:
+        out["hybrid"] = hybrid_leg(args, n, ds, dd, p, opts, counts[0])
+        out["parity"] = out["parity"] and out["hybrid"]["exact"]
     out["copy_probe_gbs"] = copy_probe_gbs()
     out["frac_of_copy_probe"] = roof["achieved"] / out["copy_probe_gbs"]
     if args.shards:
@@ -162,6 +183,65 @@ def run_graph(args, n, s, d, p, gold_name, workload, traffic_file, opts=None, cp
         out["cpu_baseline"] = cb
         if tri is not None:
             out["parity"] = out["parity"] and tri == counts[0]
+    return out
+
+
+def hybrid_leg(args, n, ds, dd, p, opts, triangles, reps=5):
+    """Device-only against hybrid host + device counts (the lightest
+    block-lists counted by host threads from the pinned host block store
+    while the device streams the heaviest ones) on one partitioned graph.
+    Each figure is the median of `reps` counts, transfers included.  An
+    in-core graph's blocks are moved to the host store before its first
+    hybrid count; that one-time move is reported apart."""
+    import ctypes
+    import numpy as np
+
+    import paper_2209_04541_amd as P
+
+    threads = cpu_model()["cores_usable"] or 1
+    g = P.Graph(n, ds, dd)
+    g.partition(p)
+    exact = True
+
+    def med(o):
+        nonlocal exact
+        ts, info = [], None
+        for _ in range(reps):
+            c = g.count(o)
+            info = g.info()
+            ts.append(info["t_count_ms"])
+            exact = exact and c == triangles
+        return float(np.median(ts)), info
+
+    def variant(flags=0, permille=0):
+        o = P.TcOptions.from_buffer_copy(opts)
+        o.flags |= flags
+        o.host_permille = permille
+        o.host_threads = min(64, threads)
+        return o
+
+    out = {"host_threads": min(64, threads), "reps": reps}
+    in_core = not (opts.flags & P.OPT_STREAM) and not opts.device_cap_bytes
+    if in_core:
+        out["device_in_core_ms"], _ = med(opts)
+        t0 = time.perf_counter()
+        g.count(variant(P.OPT_HYBRID, 0))  # moves the blocks to the host store
+        out["move_to_host_store_ms"] = (time.perf_counter() - t0) * 1e3
+    out["device_streamed_ms"], _ = med(variant(P.OPT_STREAM))
+    ms, info = med(variant(P.OPT_HYBRID, 0))
+    out["hybrid_meet"] = {"t_count_ms": ms, "host_tasks": info["host_tasks"],
+                          "host_work_share": info["host_work_share"], "tasks": info["num_tasks"]}
+    fixed = {}
+    for pm in (10, 50, 200):
+        ms, info = med(variant(P.OPT_HYBRID, pm))
+        fixed[str(pm)] = {"t_count_ms": ms, "host_tasks": info["host_tasks"],
+                          "host_work_share": info["host_work_share"]}
+    out["hybrid_fixed_permille"] = fixed
+    best_h = min([out["hybrid_meet"]["t_count_ms"]] + [v["t_count_ms"] for v in fixed.values()])
+    best_d = min(out.get("device_in_core_ms", 1e30), out["device_streamed_ms"])
+    out["best_hybrid_over_best_device"] = best_h / best_d
+    out["exact"] = exact
+    g.close()
     return out
 
 
@@ -485,23 +565,41 @@ def bench_batch(args):
         rep_ms.append(b.times()[1])
         assert np.array_equal(c2, counts)
     per_ms = []
-    for _ in range(max(1, args.steps // 5)):
+    for _ in range(0 if args.no_per_graph else max(1, args.steps // 5)):
         c3 = b.count(per_graph=True)
         per_ms.append(b.times()[1])
         assert np.array_equal(c3, counts)
     ms = float(np.median(rep_ms))
-    pg = float(np.median(per_ms))
+    pg = float(np.median(per_ms)) if per_ms else float("nan")
     mtot = int(eoff[-1])
     out = base_line(args, G / (ms / 1e3), "graphs/s", ms, {
         "workload": "%d graphs, seed (4,g): even g random geometric, odd g Erdos-Renyi, n ~ U{64..8192}, "
                     "average degree ~ U{8..64}; one persistent HIP-graph launch, autotuned" % G,
         "graphs": G, "pairs": mtot, "vertices": int(nv.sum())})
     out.update({
-        "per_graph_launches_ms": pg, "per_graph_launches_graphs_per_s": G / (pg / 1e3),
-        "speedup_vs_per_graph": pg / ms, "batched_build_ms": t_build,
+        "per_graph_launches_ms": pg if per_ms else None,
+        "per_graph_launches_graphs_per_s": G / (pg / 1e3) if per_ms else None,
+        "speedup_vs_per_graph": pg / ms if per_ms else None, "batched_build_ms": t_build,
         "end_to_end_graphs_per_s": G / ((t_build + ms) / 1e3), "autotune_s": t_tune,
         "generation_s": t_gen, "triangles_total": int(counts.sum()),
     })
+    # roofline of the counting launch: every walked entry (4 B), per edge of
+    # an active row its staged value, its id and the walked row's two
+    # offsets (16 B), per active row its id, graph id and two offsets (16 B);
+    # time = one replay of the captured launch (zeroing and the 8 B-per-graph
+    # copy of the counts included)
+    st = b.stats()
+    alg = 4 * st["walked"] + 16 * st["active_edges"] + 16 * st["active_rows"]
+    achieved = alg / (ms / 1e3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    out.update({"algorithmic_bytes_per_launch": alg, "walked_entries": st["walked"],
+                "edges": st["edges"], "active_rows": st["active_rows"]})
+    # parity: every graph's count against the oracle's stored count
+    gold = [int(x) for x in open(os.path.join(ROOT, "tests", "golden", "batch_counts.txt"))
+            if not x.startswith("#")]
+    out["parity"] = G <= len(gold) and [int(c) for c in counts] == gold[:G]
+    out["parity_checked_graphs"] = G if G <= len(gold) else 0
     if not args.no_cpu_baseline:
         import oracle
         sample = list(range(0, G, max(1, G // 200)))
@@ -514,7 +612,7 @@ def bench_batch(args):
         out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "graphs/s", "cores": oracle.threads(),
                                "kind": "oracle", "sample": "%d of the %d graphs (every %d-th), %.1f s"
                                % (len(sample), G, max(1, G // 200), dt)}
-        out["parity"] = ok
+        out["parity"] = out["parity"] and ok
     b.close()
     return out
 
@@ -522,8 +620,15 @@ def bench_batch(args):
 # ---------------------------------------------------------------- served
 
 def bench_served(args):
-    """Poisson request stream against the continuous-batching server, and the
-    same trace served one request at a time (plain sequential launches)."""
+    """A Poisson request trace against the continuous-batching server and
+    against plain sequential launches (one request at a time, build then
+    count), on the same trace.  Requests arrive for `duration` seconds; an
+    arrival that finds `max_outstanding` requests already waiting or running
+    is shed (counted, not served), so an overloaded run measures capacity
+    instead of an ever-growing queue.  Two traces: the configured rate, and
+    `sustain_rate` (a load the sequential loop also keeps up with; 0 skips
+    it).  Every served count is checked against the oracle's stored count of
+    its pool graph."""
     import numpy as np
     import torch
 
@@ -540,73 +645,97 @@ def bench_served(args):
         ps = torch.from_numpy(s).pin_memory().numpy()
         pd = torch.from_numpy(d).pin_memory().numpy()
         pool.append((n, ps, pd, sc, ef))
-    rate = args.rate
-    arrivals = gen.poisson_arrivals(rate, args.duration, gen.seed(5, 0))
-    reqs = [pool[i % pool_size] for i in range(len(arrivals))]
+    gold = golden("served") or {}
+    K = args.max_outstanding
 
-    def drive(submit_fn):
-        """Submit requests at their arrival times; returns per-request
-        (arrival, done) times."""
-        t_start = time.perf_counter()
-        for i, a in enumerate(arrivals):
-            now = time.perf_counter() - t_start
-            if a > now:
-                time.sleep(a - now)
-            submit_fn(i, t_start)
-        return t_start
+    def served_run(rate, duration):
+        arrivals = gen.poisson_arrivals(rate, duration, gen.seed(5, 0))
+        reqs = [i % pool_size for i in range(len(arrivals))]
+        with P.Server(args.budget_gb << 30, borrow=True, num_streams=args.builders) as srv:
+            clock0 = srv.now()
+            t0 = time.perf_counter()
+            outstanding = []  # (request index, ticket)
+            tickets = {}
+            shed = 0
+            for i, a in enumerate(arrivals):
+                now = time.perf_counter() - t0
+                if a > now:
+                    time.sleep(a - now)
+                if len(outstanding) >= K:
+                    outstanding = [(j, t) for j, t in outstanding if not srv.poll(t)[0]]
+                if len(outstanding) >= K:
+                    shed += 1
+                    continue
+                n, s, d, _, _ = pool[reqs[i]]
+                t = srv.submit(n, s, d)
+                tickets[i] = t
+                outstanding.append((i, t))
+            srv.drain()
+            lat, ok, t_end = [], True, clock0
+            for i, t in tickets.items():
+                done, cnt, ts, td = srv.poll(t)
+                lat.append((td - (clock0 + arrivals[i])) * 1e3)
+                g = gold.get(str(reqs[i]))
+                ok = ok and done and g is not None and cnt == g["triangles"]
+                t_end = max(t_end, td)
+            span = t_end - clock0
+            launches = srv.launches()
+        pairs = sum(len(pool[reqs[i]][1]) for i in tickets)
+        return {"offered": len(arrivals), "served": len(tickets), "shed": shed, "span_s": span,
+                "requests_per_s": len(tickets) / span, "input_pairs_per_s": pairs / span,
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": launches, "exact": ok}
 
-    # continuous batching
-    with P.Server(args.budget_gb << 30, borrow=True, num_streams=args.builders) as srv:
-        tickets = [None] * len(arrivals)
-        sub_t = [0.0] * len(arrivals)
-        clock0 = srv.now()
+    def sequential_run(rate, duration):
+        arrivals = gen.poisson_arrivals(rate, duration, gen.seed(5, 0))
+        reqs = [i % pool_size for i in range(len(arrivals))]
+        t0 = time.perf_counter()
+        queue, lat, served, shed, ok, nxt, pairs = [], [], 0, 0, True, 0, 0
+        while nxt < len(arrivals) or queue:
+            now = time.perf_counter() - t0
+            # arrivals up to now join the queue unless it is full; nothing
+            # left the queue since the last request started, so its length
+            # at each arrival is the length now
+            while nxt < len(arrivals) and arrivals[nxt] <= now:
+                if len(queue) >= K:
+                    shed += 1
+                else:
+                    queue.append(nxt)
+                nxt += 1
+            if not queue:
+                time.sleep(max(0.0, arrivals[nxt] - now))
+                continue
+            i = queue.pop(0)
+            n, s, d, _, _ = pool[reqs[i]]
+            with P.Graph(n, s, d) as g:
+                g.partition(1)
+                c = g.count()
+            lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+            gg = gold.get(str(reqs[i]))
+            ok = ok and gg is not None and c == gg["triangles"]
+            served += 1
+            pairs += len(s)
+        span = time.perf_counter() - t0
+        return {"offered": len(arrivals), "served": served, "shed": shed, "span_s": span,
+                "requests_per_s": served / span, "input_pairs_per_s": pairs / span,
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "exact": ok}
 
-        def sub(i, t_start):
-            n, s, d, _, _ = reqs[i]
-            sub_t[i] = srv.now()
-            tickets[i] = srv.submit(n, s, d)
-
-        t_start = drive(sub)
-        srv.drain()
-        lat, res = [], []
-        for i, t in enumerate(tickets):
-            done, cnt, ts, td = srv.poll(t)
-            lat.append((td - (clock0 + arrivals[i])) * 1e3)
-            res.append(cnt)
-        t_end = max(srv.poll(t)[3] for t in tickets)
-        span = t_end - clock0
-        launches = srv.launches()
-
-    # sequential FIFO: one request at a time, build then count
-    seq_lat, seq_res = [], []
-    t0 = time.perf_counter()
-    free_at = 0.0
-    for i, a in enumerate(arrivals):
-        now = time.perf_counter() - t0
-        if a > now:
-            time.sleep(a - now)
-        n, s, d, _, _ = reqs[i]
-        with P.Graph(n, s, d) as g:
-            g.partition(1)
-            c = g.count()
-        done = time.perf_counter() - t0
-        seq_lat.append((done - a) * 1e3)
-        seq_res.append(c)
-    seq_span = time.perf_counter() - t0
-
-    edges = sum(len(reqs[i][1]) for i in range(len(arrivals)))
-    out = base_line(args, len(arrivals) / span, "requests/s", span * 1e3 / max(1, len(arrivals)), {
+    main = served_run(args.rate, args.duration)
+    seq = sequential_run(args.rate, args.duration)
+    out = base_line(args, main["requests_per_s"], "requests/s", main["span_s"] * 1e3 / max(1, main["served"]), {
         "workload": "Poisson arrivals at %.0f req/s for %.1f s; request r: R-MAT scale ~ U{10..22}, "
-                    "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget, %d builders"
-                    % (rate, args.duration, pool_size, args.budget_gb, args.builders),
-        "requests": len(arrivals), "pool": pool_size})
-    out.update({
-        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "input_pairs_per_s": edges / span,
-        "launches": launches,
-        "sequential": {"p50_ms": pct(seq_lat, 50), "p99_ms": pct(seq_lat, 99),
-                       "requests_per_s": len(arrivals) / seq_span},
-        "alone_equals_mix": res == seq_res,
-    })
+                    "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget, %d builders; arrivals "
+                    "finding %d requests outstanding are shed" % (args.rate, args.duration, pool_size,
+                                                                 args.budget_gb, args.builders, K),
+        "rate": args.rate, "duration_s": args.duration, "pool": pool_size, "max_outstanding": K})
+    out.update({"p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "server": main, "sequential": seq,
+                "speedup_vs_sequential": main["requests_per_s"] / seq["requests_per_s"]})
+    parity = main["exact"] and seq["exact"]
+    if args.sustain_rate > 0:
+        out["sustained"] = {"rate": args.sustain_rate, "duration_s": args.duration,
+                            "server": served_run(args.sustain_rate, args.duration),
+                            "sequential": sequential_run(args.sustain_rate, args.duration)}
+        parity = parity and out["sustained"]["server"]["exact"] and out["sustained"]["sequential"]["exact"]
+    out["parity"] = parity
     if not args.no_cpu_baseline:
         import oracle
         small = [i for i in range(pool_size) if pool[i][3] <= 16][:8]
@@ -614,13 +743,101 @@ def bench_served(args):
         ok = True
         for i in small:
             n, s, d, _, _ = pool[i]
-            ok = ok and oracle.tc(n, s, d) == res[i] if i < len(res) else ok
+            ok = ok and oracle.tc(n, s, d) == gold[str(i)]["triangles"]
         dt = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": len(small) / dt if dt > 0 else None, "unit": "requests/s",
                                "cores": oracle.threads(), "kind": "oracle",
-                               "sample": "%d pool requests of scale <= 16 counted by the oracle, %.1f s"
-                               % (len(small), dt)}
-        out["parity"] = ok and res == seq_res
+                               "sample": "%d pool requests of scale <= 16 counted by the oracle, %.1f s "
+                                         "(larger requests take the oracle minutes each)" % (len(small), dt)}
+        out["parity"] = out["parity"] and ok
+    return out
+
+
+def bench_bsp(args):
+    """The single-block bulk-synchronous computations on the block
+    workload's graph (R-MAT scale 20, edge factor 16, 8 x 8 blocks): one step
+    is connected components (Shiloach-Vishkin) plus PageRank (damping 0.85,
+    tolerance 1e-4, at most 20 iterations) over the partitioned graph, whose
+    build and partition come before the timed region.  `value` is PageRank
+    edge visits per second (m' edges per iteration over the iterations'
+    time), the paper's per-iteration figure for bulk computations."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2209_04541_amd as P
+    from paper_2209_04541_amd import gen
+
+    p = args.p or 8
+    n, s, d = gen.block_graph()
+    ds = torch.from_numpy(s).cuda()
+    dd = torch.from_numpy(d).cuda()
+    torch.cuda.synchronize()
+    g = P.Graph(n, ds, dd)
+    g.partition(p)
+    info0 = g.info()
+    m = info0["m"]
+
+    def step():
+        lab, nc, cit = g.components()
+        ci = g.info()
+        r, pit, err = g.pagerank()
+        pi = g.info()
+        return lab, nc, cit, ci, r, pit, err, pi
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    res, step_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        res.append(step())
+        step_ms.append((time.perf_counter() - a) * 1e3)
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    lab, nc, cit, ci, r, pit, err, pi = res[-1]
+    pr_ms = float(np.median([x[7]["t_count_ms"] for x in res]))
+    pr_kernel_ms = float(np.median([x[7]["t_kernel_ms"] for x in res]))
+    cc_ms = float(np.median([x[3]["t_count_ms"] for x in res]))
+    cc_kernel_ms = float(np.median([x[3]["t_kernel_ms"] for x in res]))
+    # algorithmic bytes of one PageRank iteration: each stored entry of every
+    # block's rows and columns (2 m') reads its id (4 B) and its neighbour's
+    # share (8 B); each item reads its record (12 B) and adds to one sum
+    # (8 B read + 8 B write); each vertex reads its rank and two degrees and
+    # writes its share and zeroed sum (32 B), then reads the sum and rank and
+    # writes the new rank (24 B)
+    items = info0["row_items"] + info0["col_items"]
+    alg = 2 * m * 12 + items * 28 + n * 56
+    per_iter_ms = pr_kernel_ms / max(1, pit)
+    achieved = alg / (per_iter_ms / 1e3) / 1e9
+    out = base_line(args, m * pit / (pr_ms / 1e3), "edges/s", ms, {
+        "workload": "connected components + PageRank (d 0.85, tol 1e-4, <= 20 iterations) over R-MAT scale 20, "
+                    "edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed (2,0), %dx%d blocks" % (p, p),
+        "n": n, "m": m, "p": p}, dtype="int32+f64")
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    want_lab, want_nc = oracle.components(n, s, d)
+    want_r, want_it, _ = oracle.pagerank(n, s, d)
+    pr_ok = pit == want_it and bool(np.allclose(r, want_r, rtol=1e-10, atol=1e-15))
+    cc_ok = nc == want_nc and bool(np.array_equal(lab, want_lab))
+    out.update({
+        "parity": pr_ok and cc_ok and all(x[1] == nc and x[5] == pit for x in res),
+        "components": nc, "cc_iterations": cit, "cc_ms": cc_ms, "cc_kernel_ms": cc_kernel_ms,
+        "cc_edges_per_s": m / (cc_ms / 1e3),
+        "pagerank_iterations": pit, "pagerank_ms": pr_ms, "pagerank_kernel_ms": pr_kernel_ms,
+        "pagerank_ms_per_iteration": pr_ms / max(1, pit), "pagerank_last_err": err,
+        "pagerank_max_rel_diff_vs_oracle": float(np.max(np.abs(r - want_r) / np.maximum(want_r, 1e-300))),
+        "algorithmic_bytes_per_pagerank_iteration": alg, "items": items,
+        "step_ms_p50": pct(step_ms, 50), "step_ms_p99": pct(step_ms, 99),
+    })
+    if not args.no_cpu_baseline:
+        t1 = time.perf_counter()
+        _, it_cpu, _ = oracle.pagerank(n, s, d)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": m * it_cpu / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "sample": "the oracle's PageRank over the whole graph, sequential, %d iterations "
+                                         "including its adjacency build (%.1f s)" % (it_cpu, dt)}
+    g.close()
     return out
 
 
@@ -656,7 +873,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="block",
-                    choices=["block", "plain", "ooc", "batch", "served", "support", "copy"])
+                    choices=["block", "plain", "ooc", "batch", "served", "support", "copy", "bsp"])
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0)
@@ -666,12 +883,19 @@ def main():
                     help="hand the edge list over in pinned host memory (its copy is then in the step)")
     ap.add_argument("--graphs", type=int, default=10000)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--duration", type=float, default=0.25)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--sustain-rate", type=float, default=40.0,
+                    help="served: also run the trace at this rate (0 = skip)")
+    ap.add_argument("--max-outstanding", type=int, default=64,
+                    help="served: arrivals finding this many requests outstanding are shed")
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gb", type=int, default=64)
     ap.add_argument("--builders", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid host + device comparison")
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="batch: skip the per-graph launches baseline (10,000 launches; for profiler runs)")
     ap.add_argument("--shards", type=int, default=0,
                     help="block and ooc workloads: also count each of this many task shards "
                          "(one device's share of a count split over that many devices)")
@@ -683,8 +907,11 @@ def main():
     import torch
     torch.cuda.set_device(0)
     fn = {"block": bench_block, "plain": bench_plain, "ooc": bench_ooc, "batch": bench_batch,
-          "served": bench_served, "support": bench_support, "copy": bench_copy}[args.workload]
-    print(json.dumps(fn(args)), flush=True)
+          "served": bench_served, "support": bench_support, "copy": bench_copy, "bsp": bench_bsp}[args.workload]
+    out = fn(args)
+    if "cpu_baseline" in out:
+        out["cpu_baseline"].update(cpu_model())
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -41,9 +41,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
             unsigned long long c = 0;
             if (lane == 0) c = atomicAdd(&a.next[q * kQueueStride], 1ull);
             c = shfl_t(c, 0);
-            // runs of a.qrun consecutive units are dealt to the queues in
-            // turn, so the waves of one XCD walk neighbouring items (the same
-            // task's blocks) and share its L2
+            // round-robin over the queues, or runs of a.qrun consecutive
+            // units per queue when asked (queue_run)
             int64_t unit = static_cast<int64_t>(c) * kQueues + q;
             if (a.qrun > 1) {
                 const int64_t run = static_cast<int64_t>(c) / a.qrun;
