@@ -212,6 +212,33 @@ uint64_t pgabb_tc_count(pgabb_graph *g);
 pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
 
 /*
+ * For callers that cannot allocate memory during the call (code under
+ * stream capture, tight serving loops, hosts that forbid allocation after
+ * start-up): the in-core count of pgabb_tc_count_ex, with its scratch (task
+ * descriptors, work-item prefix, per-task and work-queue counters) in a
+ * fixed device array of pgabb_tc_count_noalloc_scratch_bytes() bytes (8 MiB)
+ * that each GPU the library runs on holds until the process ends.  No device
+ * or pinned host memory is allocated and no HIP allocation routine is
+ * called; host-side descriptors go through thread-local vectors that grow
+ * to the largest graph seen on the calling thread.
+ *   g     : partitioned graph whose blocks are in device memory
+ *   opts  : as pgabb_tc_count_ex (NULL = defaults); p must be 0 or the
+ *           graph's own, streamed and hybrid counts are refused
+ *   count : receives the count (PGABB_COUNT_ERROR on failure)
+ * Every call on one GPU shares that GPU's array; the counters are cleared at
+ * the start of each call, the rest keeps the last call's contents, and calls
+ * that overlap on one GPU (from several threads) race.  Per-task counts
+ * (pgabb_graph_task_counts) are updated as by pgabb_tc_count_ex.
+ * Errors: EINVAL (NULL pointer, bad options, more tasks than the array
+ * holds: about 43,000 at 8 MiB), ESTATE (graph not partitioned, blocks in
+ * host memory, options asking for another partition), EDEVICE.
+ */
+pgabb_status pgabb_tc_count_noalloc(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
+
+/* Bytes of the per-GPU scratch array of pgabb_tc_count_noalloc. */
+size_t pgabb_tc_count_noalloc_scratch_bytes(void);
+
+/*
  * Count several graph objects (PGAbB Section 3.6's count, per graph; Section
  * 4.4's task-parallel execution over the tasks of all of them):
  * counts[q] for gs[q], q < num_graphs (host array of num_graphs entries).

@@ -93,6 +93,8 @@ def lib():
             "pgabb_partition_ex": (st, [vp, i32, i32, vp]),
             "pgabb_tc_count": (u64, [vp]),
             "pgabb_tc_count_ex": (st, [vp, vp, ctypes.POINTER(u64)]),
+            "pgabb_tc_count_noalloc": (st, [vp, vp, ctypes.POINTER(u64)]),
+            "pgabb_tc_count_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "pgabb_graph_info_get": (st, [vp, ctypes.POINTER(GraphInfo)]),
             "pgabb_graph_info": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                       ctypes.POINTER(i64)]),
@@ -257,6 +259,17 @@ class Graph:
         c = ctypes.c_uint64()
         _check(lib().pgabb_tc_count_ex(self._h, ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(c)))
+        return int(c.value)
+
+    def count_noalloc(self, opts=None, **kw):
+        """The in-core count with its scratch in the library's fixed
+        per-GPU array (pgabb_tc_count_noalloc): the graph must be
+        partitioned and its blocks in device memory."""
+        if opts is None and kw:
+            opts = options(**kw)
+        c = ctypes.c_uint64()
+        _check(lib().pgabb_tc_count_noalloc(self._h, ctypes.byref(opts) if opts is not None else None,
+                                            ctypes.byref(c)))
         return int(c.value)
 
     def count_shard(self, shard, num_shards, opts=None, **kw):

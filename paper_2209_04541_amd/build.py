@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpgabb.so")
 
-SOURCES = ["prims.hip", "build.hip", "partition.hip", "count.hip", "streamer.hip", "support.hip", "vertex.hip", "ktruss.hip", "kclique.hip", "bsp.hip", "host_count.cpp", "tune_cache.cpp",
+SOURCES = ["prims.hip", "build.hip", "partition.hip", "count.hip", "streamer.hip", "support.hip", "vertex.hip", "ktruss.hip", "kclique.hip", "bsp.hip", "host_count.cpp", "noalloc.cpp", "tune_cache.cpp",
            "batch.hip", "server.cpp", "memory.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

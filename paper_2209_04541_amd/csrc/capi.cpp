@@ -230,6 +230,21 @@ PGABB_API pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options 
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tc_count_noalloc(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    if (!count) return set_err(PGABB_EINVAL, "count is NULL");
+    *count = PGABB_COUNT_ERROR;
+    const pgabb_tc_options o = opts ? *opts : default_options();
+    const pgabb_status st = check_options(o);
+    if (st != PGABB_OK) return st;
+    PGABB_TRY
+    *count = count_noalloc(g, o);
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API size_t pgabb_tc_count_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
+
 PGABB_API pgabb_status pgabb_tc_edge_support(pgabb_graph *g, uint32_t *support, uint32_t flags,
                                              uint64_t *triangles) {
     if (!g) return set_err(PGABB_EINVAL, "graph is NULL");

@@ -164,6 +164,9 @@ int32_t pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, d
 // Counts of several graphs, in one launch where their blocks are in device
 // memory (tune: launch shape from the autotuner).
 void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt, bool tune, uint64_t *counts);
+// The in-core count with its scratch in a fixed device array (noalloc.cpp).
+uint64_t count_noalloc(pgabb_graph *g, const pgabb_tc_options &opt);
+size_t noalloc_scratch_bytes();
 // Count only the tasks task_shards deals to `shard`.
 uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard, int32_t nshards);
 
