@@ -60,6 +60,8 @@ def _load():
         L.oracle_count.argtypes = [ctypes.c_int32, vp, vp]
         L.oracle_block_counts.restype = ctypes.c_int
         L.oracle_block_counts.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp]
+        L.oracle_four_clique_blocks.restype = ctypes.c_int
+        L.oracle_four_clique_blocks.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp]
         L.oracle_tc.restype = ctypes.c_uint64
         L.oracle_tc.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
         L.oracle_probe_work.restype = ctypes.c_uint64
@@ -188,6 +190,22 @@ def four_cliques(n: int, src, dst, mode: int = 0) -> int:
     if n == 0 or len(col) == 0:
         return 0
     return int(_load().oracle_four_cliques(n, _p(row_off), _p(np.ascontiguousarray(col, dtype=np.int32))))
+
+
+def four_clique_blocks(n: int, row_off: np.ndarray, col: np.ndarray, cuts) -> np.ndarray:
+    """Q[i, j, k, l] = 4-cliques whose ranked vertices lie in stripes
+    i <= j <= k <= l."""
+    cuts = np.ascontiguousarray(cuts, dtype=np.int32)
+    p = len(cuts) - 1
+    row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    if len(col) == 0:
+        col = np.zeros(1, dtype=np.int32)
+    out = np.zeros(p ** 4, dtype=np.uint64)
+    rc = _load().oracle_four_clique_blocks(n, _p(row_off), _p(col), p, _p(cuts), _p(out))
+    if rc != 0:
+        raise ValueError("bad cut vector")
+    return out.reshape(p, p, p, p)
 
 
 def probe_work(n: int, row_off: np.ndarray, col: np.ndarray) -> int:

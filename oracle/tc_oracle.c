@@ -408,6 +408,51 @@ int oracle_block_counts(int32_t n, const int64_t *row_off, const int32_t *col,
     return 0;
 }
 
+/* 4-cliques by block 4-list (PGAbB Section 3.2, the multi-block pattern
+ * mode one level past triangles): out[((i * p + j) * p + k) * p + l] = the
+ * 4-cliques a < b < c < d (ranks) whose vertices lie in stripes i, j, k and
+ * l (so i <= j <= k <= l; zero elsewhere).  Each is found once, at its edge
+ * (a, b), as in oracle_four_cliques.  cuts as in oracle_block_counts;
+ * returns -1 on a bad cut vector or allocation failure. */
+int oracle_four_clique_blocks(int32_t n, const int64_t *row_off, const int32_t *col,
+                              int32_t p, const int32_t *cuts, uint64_t *out)
+{
+    if (p < 1 || cuts[0] != 0 || cuts[p] != n) return -1;
+    for (int32_t s = 0; s < p; ++s)
+        if (cuts[s] > cuts[s + 1]) return -1;
+    memset(out, 0, sizeof(uint64_t) * (size_t)p * p * p * p);
+    int32_t maxd = 0;
+    for (int32_t x = 0; x < n; ++x)
+        if (row_off[x + 1] - row_off[x] > maxd) maxd = (int32_t)(row_off[x + 1] - row_off[x]);
+    int32_t *common = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    if (!common) return -1;
+    for (int32_t a = 0; a < n; ++a) {
+        const int32_t *na = col + row_off[a];
+        const int64_t da = row_off[a + 1] - row_off[a];
+        const int32_t si = stripe_of(a, p, cuts);
+        for (int64_t t = 0; t < da; ++t) {
+            const int32_t b = na[t];
+            const int32_t sj = stripe_of(b, p, cuts);
+            const int32_t *nb = col + row_off[b];
+            const int64_t db = row_off[b + 1] - row_off[b];
+            int64_t i = 0, j = 0, nc = 0;
+            while (i < da && j < db) {
+                if (na[i] < nb[j]) ++i;
+                else if (nb[j] < na[i]) ++j;
+                else { common[nc++] = na[i]; ++i; ++j; }
+            }
+            for (int64_t x = 0; x < nc; ++x)
+                for (int64_t y = x + 1; y < nc; ++y)
+                    if (has_out(row_off, col, common[x], common[y])) {
+                        const int32_t sk = stripe_of(common[x], p, cuts), sl = stripe_of(common[y], p, cuts);
+                        out[(((size_t)si * p + sj) * p + sk) * p + sl]++;
+                    }
+        }
+    }
+    free(common);
+    return 0;
+}
+
 /* Whole pipeline: clean, degree, rank (mode), orient, count.  Returns
  * UINT64_MAX on an out-of-range id or allocation failure.  If mu_out is not
  * NULL it receives m'. */

@@ -487,3 +487,44 @@ def test_four_cliques_closed_forms():
     assert oracle.four_cliques(n, s, d) == 1
     (n, s, d), _ = graphs.disjoint_union(graphs.complete(6), graphs.complete(5))
     assert oracle.four_cliques(n, s, d) == math.comb(6, 4) + math.comb(5, 4)
+
+
+def test_four_clique_blocks_pins():
+    """Per-4-list counts: networkx's 4-cliques binned by the stripes of their
+    ranked vertices, the total, the ordered support i <= j <= k <= l, and
+    K_n, where the count of a stripe pattern is a product of binomials."""
+    rng = np.random.default_rng(21)
+    n, s, d = gen.rmat(9, 12, gen.seed(44, 0))
+    _, _, rk, row_off, col = oracle.oriented_csr(n, s, d)
+    G = nx.Graph()
+    G.add_edges_from((int(a), int(b)) for a, b in zip(s, d) if a != b)
+    cliques = [c for c in nx.enumerate_all_cliques(G) if len(c) == 4]
+    total = oracle.four_cliques(n, s, d)
+    assert len(cliques) == total > 0
+    for p in (1, 2, 3, 5, 8):
+        cuts = np.concatenate([[0], np.sort(rng.integers(0, n + 1, p - 1)), [n]]).astype(np.int32)
+        Q = oracle.four_clique_blocks(n, row_off, col, cuts)
+        want = np.zeros((p, p, p, p), np.uint64)
+        for c in cliques:
+            st = sorted(int(np.searchsorted(cuts, rk[v], side="right") - 1) for v in c)
+            st = [min(x, p - 1) for x in st]
+            want[tuple(st)] += 1
+        assert np.array_equal(Q, want), p
+        assert int(Q.sum()) == total
+        idx = np.argwhere(Q > 0)
+        assert all(i <= j <= k <= l for i, j, k, l in idx)
+    # K_n under uniform cuts: a stripe pattern with multiplicities m_s counts
+    # the product over stripes of C(size_s, m_s)
+    (n, s, d), _ = graphs.complete(13)
+    _, _, _, row_off, col = oracle.oriented_csr(n, s, d)
+    p = 3
+    cuts = np.array([0, 4, 9, 13], np.int32)
+    size = np.diff(cuts)
+    Q = oracle.four_clique_blocks(n, row_off, col, cuts)
+    for q in itertools.combinations_with_replacement(range(p), 4):
+        mult = np.bincount(q, minlength=p)
+        want = 1
+        for st in range(p):
+            want *= math.comb(int(size[st]), int(mult[st]))
+        assert int(Q[q]) == want, q
+    assert int(Q.sum()) == math.comb(13, 4)
