@@ -44,8 +44,11 @@ def kernel_digest(sources=KERNEL_SOURCES):
 
 
 def measured_traffic(name, sources=KERNEL_SOURCES):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary, or None when the kernel changed since."""
+    """L2-to-fabric bytes of a step's counting launches (one launch, or all
+    of a streamed step's) from the committed rocprofv3 counter summary, or
+    None when the kernel changed since.  The bytes are request counts by
+    size (32, 64, 128 B) times their size; they include what Infinity Cache
+    answers, so they bound HBM traffic from above."""
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
@@ -53,7 +56,7 @@ def measured_traffic(name, sources=KERNEL_SOURCES):
         return None
     if t.get("kernel_digest") != kernel_digest(sources):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_step") or t.get("bytes_per_launch")
 
 
 def cpu_model():
@@ -638,6 +641,7 @@ def bench_served(args):
     torch.cuda.init()
     pool_size = args.pool
     pool = []
+    print("served: generating the pool of %d graphs" % pool_size, file=sys.stderr, flush=True)
     for r in range(pool_size):
         sc, ef = gen.served_params(r)
         n, s, d = gen.served_graph(r)
@@ -645,6 +649,8 @@ def bench_served(args):
         ps = torch.from_numpy(s).pin_memory().numpy()
         pd = torch.from_numpy(d).pin_memory().numpy()
         pool.append((n, ps, pd, sc, ef))
+        if r % 16 == 15:
+            print("served: %d pool graphs ready" % (r + 1), file=sys.stderr, flush=True)
     gold = golden("served") or {}
     K = args.max_outstanding
 
@@ -657,8 +663,13 @@ def bench_served(args):
             outstanding = []  # (request index, ticket)
             tickets = {}
             shed = 0
+            next_report = 5.0
             for i, a in enumerate(arrivals):
                 now = time.perf_counter() - t0
+                if now >= next_report:  # progress on stderr, a line every 5 s
+                    print("served %.0f req/s: t=%.0f s, %d submitted, %d shed" % (rate, now, len(tickets), shed),
+                          file=sys.stderr, flush=True)
+                    next_report += 5.0
                 if a > now:
                     time.sleep(a - now)
                 if len(outstanding) >= K:
@@ -671,6 +682,7 @@ def bench_served(args):
                 tickets[i] = t
                 outstanding.append((i, t))
             srv.drain()
+            kms, walked, edges = srv.kernel_stats()
             lat, ok, t_end = [], True, clock0
             for i, t in tickets.items():
                 done, cnt, ts, td = srv.poll(t)
@@ -683,15 +695,21 @@ def bench_served(args):
         pairs = sum(len(pool[reqs[i]][1]) for i in tickets)
         return {"offered": len(arrivals), "served": len(tickets), "shed": shed, "span_s": span,
                 "requests_per_s": len(tickets) / span, "input_pairs_per_s": pairs / span,
-                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": launches, "exact": ok}
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": launches, "exact": ok,
+                "kernel_ms": kms, "walked_entries": walked, "edges_counted": edges}
 
     def sequential_run(rate, duration):
         arrivals = gen.poisson_arrivals(rate, duration, gen.seed(5, 0))
         reqs = [i % pool_size for i in range(len(arrivals))]
         t0 = time.perf_counter()
         queue, lat, served, shed, ok, nxt, pairs = [], [], 0, 0, True, 0, 0
+        next_report = 5.0
         while nxt < len(arrivals) or queue:
             now = time.perf_counter() - t0
+            if now >= next_report:
+                print("sequential %.0f req/s: t=%.0f s, %d served, %d shed" % (rate, now, served, shed),
+                      file=sys.stderr, flush=True)
+                next_report += 5.0
             # arrivals up to now join the queue unless it is full; nothing
             # left the queue since the last request started, so its length
             # at each arrival is the length now
@@ -727,6 +745,14 @@ def bench_served(args):
                     "finding %d requests outstanding are shed" % (args.rate, args.duration, pool_size,
                                                                  args.budget_gb, args.builders, K),
         "rate": args.rate, "duration_s": args.duration, "pool": pool_size, "max_outstanding": K})
+    # roofline of the server's counting launches over the run: algorithmic
+    # bytes (4 per walked entry, 16 per edge, as for one count) over their
+    # summed device time
+    if main["kernel_ms"] > 0:
+        alg = 4 * main["walked_entries"] + 16 * main["edges_counted"]
+        ach = alg / (main["kernel_ms"] / 1e3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None}
     out.update({"p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "server": main, "sequential": seq,
                 "speedup_vs_sequential": main["requests_per_s"] / seq["requests_per_s"]})
     parity = main["exact"] and seq["exact"]

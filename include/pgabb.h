@@ -127,11 +127,6 @@ typedef struct pgabb_tc_options {
                                   host threads, lightest tasks first
                                   (0 = chosen from measured rates, see
                                   pgabb_tc_count_ex; 1000 = every task) */
-    int32_t queue_run;         /* work units (grabs) per run dealt to one of
-                                  the counting launch's 8 work queues, one
-                                  queue per XCD (0 = 1: round-robin); values
-                                  of an eighth of the launch's units or more
-                                  give one contiguous range per queue */
 } pgabb_tc_options;
 
 typedef struct pgabb_graph pgabb_graph;
@@ -166,6 +161,14 @@ typedef struct pgabb_graph_info_t {
     int64_t row_items;       /* work items over all blocks' rows (runs of at
                                 most 32 entries of one row of one block) */
     int64_t col_items;       /* the same over the blocks' columns */
+    double t_tune_ms;        /* tuning time (grid and launch shape searches or
+                                cache look-ups) of the last autotuned
+                                pgabb_tc_count_batch that counted this graph */
+    uint64_t walk_bytes_rows; /* bytes of the blocks' parts a row walk reads
+                                 (row items, row offsets, column ids): what
+                                 a streamed count walking rows copies once */
+    uint64_t walk_bytes_cols; /* the same for column walks (row offsets,
+                                 column ids, column items, row ids) */
 } pgabb_graph_info_t;
 
 /*
@@ -189,8 +192,14 @@ pgabb_status pgabb_graph_from_edges(int32_t n, int64_t m, const int32_t *src,
 /*
  * Cut the oriented graph into a p x p grid with nnz-balanced cuts (stripe s
  * starts at the first row whose CSR offset reaches s * m' / p), then build
- * the blocks and the task list.  1 <= p <= 64.  Replaces an earlier
- * partition.  Errors: EINVAL (NULL, p out of range), ENOMEM, EDEVICE.
+ * the blocks and the task list (PGAbB Section 4.3: symmetric rectilinear
+ * partition, one cut vector for rows and columns, blocks stored as CSR with
+ * local ids; Section 3.6: the block-lists (A_ij, A_ik, A_jk), i <= j <= k,
+ * with three non-empty blocks; Section 4.1: tasks weighted by their edges
+ * and ordered heaviest first).  1 <= p <= 64 (a narrower range than the
+ * paper's, which leaves p open: a long row is split over the stripes by one
+ * wave lane per stripe).  Replaces an earlier partition.
+ * Errors: EINVAL (NULL, p out of range), ENOMEM, EDEVICE.
  */
 pgabb_status pgabb_partition(pgabb_graph *g, int32_t p);
 
@@ -203,8 +212,12 @@ pgabb_status pgabb_partition_ex(pgabb_graph *g, int32_t p, int32_t cut_mode,
                                 const int32_t *cuts);
 
 /*
- * Triangle count with default options.  Partitions with p = 1 first if the
- * graph was not partitioned.  Returns PGABB_COUNT_ERROR on failure.
+ * Triangle count with default options: the number of sets of three mutually
+ * adjacent vertices (PGAbB Section 3.6), as the sum over every task
+ * (A_ij, A_ik, A_jk) and every edge (u, v) of A_ij of the common entries of
+ * row u of A_ik and row v of A_jk.  Partitions with p = 1 first if the
+ * graph was not partitioned.  Returns PGABB_COUNT_ERROR on failure (the
+ * reason is in pgabb_last_error()).
  */
 uint64_t pgabb_tc_count(pgabb_graph *g);
 
@@ -216,7 +229,7 @@ pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uin
  * stream capture, tight serving loops, hosts that forbid allocation after
  * start-up): the in-core count of pgabb_tc_count_ex, with its scratch (task
  * descriptors, work-item prefix, per-task and work-queue counters) in a
- * fixed device array of pgabb_tc_count_noalloc_scratch_bytes() bytes (8 MiB)
+ * fixed device array of pgabb_tc_count_noalloc_scratch_bytes() bytes (4 MiB)
  * that each GPU the library runs on holds until the process ends.  No device
  * or pinned host memory is allocated and no HIP allocation routine is
  * called; host-side descriptors go through thread-local vectors that grow
@@ -230,7 +243,7 @@ pgabb_status pgabb_tc_count_ex(pgabb_graph *g, const pgabb_tc_options *opts, uin
  * that overlap on one GPU (from several threads) race.  Per-task counts
  * (pgabb_graph_task_counts) are updated as by pgabb_tc_count_ex.
  * Errors: EINVAL (NULL pointer, bad options, more tasks than the array
- * holds: about 43,000 at 8 MiB), ESTATE (graph not partitioned, blocks in
+ * holds: about 24,900 at 4 MiB, so every grid up to p = 52), ESTATE (graph not partitioned, blocks in
  * host memory, options asking for another partition), EDEVICE.
  */
 pgabb_status pgabb_tc_count_noalloc(pgabb_graph *g, const pgabb_tc_options *opts, uint64_t *count);
@@ -247,14 +260,19 @@ size_t pgabb_tc_count_noalloc_scratch_bytes(void);
  * persistent counting launch on the library's stream (after each graph's
  * stream has reached the call); a graph whose blocks are in the host store,
  * or that opts ask to stream or count hybrid, is counted on its own, as by
- * pgabb_tc_count_ex.  opts == NULL selects the default options with an
- * autotuned launch shape: waves per workgroup, items per grab and chunks per
- * load batch are timed on the launch itself the first time a shape class is
- * seen, and the winner is kept in a tuning cache (in memory and in the file
- * named by PGABB_TUNE_CACHE, else $XDG_CACHE_HOME/pgabb/tune.txt or
+ * pgabb_tc_count_ex.  opts == NULL selects the default options and tunes
+ * (Section 6 names automatic parameter tuning as future work): first the
+ * grid of each shape class of graphs (bit widths of m' and of the longest
+ * oriented row) -- p of 1, 2, 4, 8 or 16 with nnz-balanced cuts, or 8 with
+ * uniform cuts, each timed as one launch over the class's graphs, which
+ * are then partitioned with the winner -- then the launch shape of the
+ * merged launch (waves per workgroup, items per grab, chunks per load
+ * batch), timed on the launch itself.  Both are searched the first time a
+ * class is seen and kept in a tuning cache (in memory and in the file named
+ * by PGABB_TUNE_CACHE, else $XDG_CACHE_HOME/pgabb/tune.txt or
  * $HOME/.cache/pgabb/tune.txt).  Afterwards each graph's
  * pgabb_graph_task_counts holds its own tasks' counts and
- * pgabb_graph_info_get the shared launch's times.  Errors: EINVAL
+ * pgabb_graph_info_get the shared launch's times and the tuning time.  Errors: EINVAL
  * (num_graphs < 0, a NULL array or graph, a graph listed twice, bad
  * options), ENOMEM, EDEVICE; on any error every count is PGABB_COUNT_ERROR.
  * Many small graphs built together count faster as a pgabb_batch.
@@ -399,12 +417,26 @@ pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t 
 /*
  * Number of 4-cliques (sets of four pairwise adjacent vertices; the
  * multi-block pattern family of PGAbB Section 3.2, one intersection level
- * past triangles), over the whole oriented graph as one block.  Each
- * 4-clique a < b < c < d (ranks) is counted once, at its edge (a, b).
- * pgabb_graph_info_get then reports the call's time and kernel time.
- * Errors: EINVAL (NULL argument), ENOMEM, EDEVICE.
+ * past triangles), over the graph's partition (p = 1 first if it has
+ * none): every block 4-list (A_ij, A_ik, A_il, A_jk, A_jl, A_kl),
+ * i <= j <= k <= l, with six non-empty blocks is a task, heaviest first.
+ * Each 4-clique a < b < c < d (ranks) is counted once, in the 4-list of its
+ * stripes, at its edge (a, b) of A_ij: the pairs c in A_ik[a] & A_jk[b],
+ * d in A_il[a] & A_jl[b] with (c, d) in A_kl.  pgabb_graph_info_get then
+ * reports the call's time, kernel time and launches; pgabb_graph_4list_counts
+ * the 4-lists and their counts.
+ * Errors: EINVAL (NULL argument), ESTATE (blocks held in host memory by a
+ * streamed count), ENOMEM, EDEVICE.
  */
 pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count);
+
+/*
+ * The block 4-lists of the last pgabb_count_4cliques on g, in processing
+ * order: *num_lists (optional), ijkl[4 q .. 4 q + 3] = (i, j, k, l) and
+ * counts[q] = its 4-cliques (either array may be NULL; host arrays of
+ * *num_lists entries, queried first with both NULL).
+ */
+pgabb_status pgabb_graph_4list_counts(const pgabb_graph *g, int64_t *num_lists, int32_t *ijkl, uint64_t *counts);
 
 /*
  * Connected components (the Shiloach-Vishkin example of PGAbB Section 3.4,
@@ -453,6 +485,13 @@ pgabb_status pgabb_components(pgabb_graph *g, int32_t *label, uint32_t flags, in
  */
 pgabb_status pgabb_pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, double *ranks,
                             uint32_t flags, int32_t *iterations, double *last_err);
+
+/*
+ * Forget the tuning choices held in memory; the tuning cache file is read
+ * again when the next tuned call needs it (for a cache file edited or copied
+ * in while the process runs).
+ */
+pgabb_status pgabb_tune_cache_reload(void);
 
 /* Release a graph and its device and host memory.  NULL is ignored. */
 void pgabb_graph_destroy(pgabb_graph *g);
@@ -503,6 +542,18 @@ pgabb_status pgabb_batch_times(const pgabb_batch *b, double *t_build_ms, double 
  */
 pgabb_status pgabb_batch_stats(const pgabb_batch *b, int64_t *edges, int64_t *active_rows, int64_t *active_edges,
                                uint64_t *walked);
+
+/*
+ * The launch shape of the last graph-captured count (any pointer may be
+ * NULL): staging kernel (PGABB_KERNEL_BITMAP or PGABB_KERNEL_HASH; -1 before
+ * the first such count), waves per workgroup, rows per grab, and the
+ * milliseconds the last autotuned count spent choosing it (searching, or
+ * reading the tuning cache).  The autotuner's choice is kept per shape class
+ * (bit widths of graph count, largest n, m' and longest row) in the tuning
+ * cache of pgabb_tc_count_batch.
+ */
+pgabb_status pgabb_batch_launch_shape(const pgabb_batch *b, int32_t *kernel, int32_t *waves_per_block,
+                                      int32_t *rows_per_grab, double *t_tune_ms);
 
 void pgabb_batch_destroy(pgabb_batch *b);
 
@@ -559,6 +610,14 @@ double pgabb_server_now(const pgabb_server *s);
 
 /* Counting launches issued so far. */
 pgabb_status pgabb_server_stats(const pgabb_server *s, uint64_t *launches);
+
+/*
+ * Totals over the server's counting launches so far (any pointer may be
+ * NULL): their device milliseconds, the entries their walks read and the
+ * oriented edges m' of the requests they counted (4 bytes per walked entry
+ * plus 16 per edge are the launches' algorithmic bytes, as for a count).
+ */
+pgabb_status pgabb_server_kernel_stats(pgabb_server *s, double *kernel_ms, uint64_t *walked, uint64_t *edges);
 
 void pgabb_server_destroy(pgabb_server *s);
 

@@ -45,7 +45,7 @@ class TcOptions(ctypes.Structure):
                 ("device_cap_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("waves_per_block", ctypes.c_int32), ("rows_per_grab", ctypes.c_int32),
                 ("unroll", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-                ("host_permille", ctypes.c_int32), ("queue_run", ctypes.c_int32)]
+                ("host_permille", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -59,7 +59,8 @@ class GraphInfo(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int64), ("probe_work_col", ctypes.c_uint64),
                 ("walked_columns", ctypes.c_int64), ("host_tasks", ctypes.c_int64),
                 ("host_work_share", ctypes.c_double), ("row_items", ctypes.c_int64),
-                ("col_items", ctypes.c_int64)]
+                ("col_items", ctypes.c_int64), ("t_tune_ms", ctypes.c_double),
+                ("walk_bytes_rows", ctypes.c_uint64), ("walk_bytes_cols", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +100,7 @@ def lib():
             "pgabb_graph_info": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                       ctypes.POINTER(i64)]),
             "pgabb_tc_count_batch": (st, [vp, i64, vp, vp]),
+            "pgabb_tune_cache_reload": (st, []),
             "pgabb_graph_export_csr": (st, [vp, vp, vp, vp]),
             "pgabb_graph_cuts": (st, [vp, vp]),
             "pgabb_graph_task_counts": (st, [vp, vp, vp]),
@@ -107,6 +109,7 @@ def lib():
             "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_ktruss": (st, [vp, i32, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_count_4cliques": (st, [vp, ctypes.POINTER(u64)]),
+            "pgabb_graph_4list_counts": (st, [vp, ctypes.POINTER(i64), vp, vp]),
             "pgabb_components": (st, [vp, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_pagerank": (st, [vp, ctypes.c_double, ctypes.c_double, i32, vp, u32, ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_double)]),
@@ -118,6 +121,8 @@ def lib():
             "pgabb_batch_count": (st, [vp, vp, vp]),
             "pgabb_batch_times": (st, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "pgabb_batch_destroy": (None, [vp]),
+            "pgabb_batch_launch_shape": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                              ctypes.POINTER(ctypes.c_double)]),
             "pgabb_batch_stats": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                        ctypes.POINTER(u64)]),
             "pgabb_server_create": (st, [u64, vp, ctypes.POINTER(vp)]),
@@ -127,6 +132,8 @@ def lib():
             "pgabb_server_drain": (st, [vp]),
             "pgabb_server_now": (ctypes.c_double, [vp]),
             "pgabb_server_stats": (st, [vp, ctypes.POINTER(u64)]),
+            "pgabb_server_kernel_stats": (st, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                               ctypes.POINTER(u64)]),
             "pgabb_server_destroy": (None, [vp]),
             "pgabb_set_allocator": (st, [vp, vp, vp]),
             "pgabb_release_cached_memory": (st, []),
@@ -186,7 +193,7 @@ def _edges(src, dst):
 
 def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks=False,
             waves_per_block=0, rows_per_grab=0, unroll=0, by_rows=None, p=0, cut_mode=CUT_NNZ,
-            hybrid=False, host_threads=0, host_permille=0, queue_run=0):
+            hybrid=False, host_threads=0, host_permille=0):
     """by_rows: True walks edge blocks by rows, False by columns, None lets
     the library take the walk that reads fewer entries.  p > 0 partitions
     the graph with p (and cut_mode) before the count unless it already is.
@@ -197,7 +204,6 @@ def options(kernel=KERNEL_AUTO, num_streams=0, device_cap_bytes=0, stream_blocks
     o.cut_mode = cut_mode
     o.host_threads = host_threads
     o.host_permille = host_permille
-    o.queue_run = queue_run
     o.kernel = kernel
     o.num_streams = num_streams
     o.device_cap_bytes = device_cap_bytes
@@ -359,6 +365,17 @@ class Graph:
                                     ctypes.byref(err)))
         return r, int(it.value), float(err.value)
 
+    def four_clique_lists(self):
+        """(ijkl int32[L, 4], counts uint64[L]) of the last 4-clique count."""
+        nl = ctypes.c_int64()
+        _check(lib().pgabb_graph_4list_counts(self._h, ctypes.byref(nl), None, None))
+        L = nl.value
+        ijkl = np.empty((max(L, 1), 4), np.int32)
+        cnt = np.empty(max(L, 1), np.uint64)
+        _check(lib().pgabb_graph_4list_counts(self._h, None, ctypes.c_void_p(ijkl.ctypes.data),
+                                              ctypes.c_void_p(cnt.ctypes.data)))
+        return ijkl[:L], cnt[:L]
+
     def four_cliques(self):
         """Sets of four pairwise adjacent vertices."""
         c = ctypes.c_uint64()
@@ -490,6 +507,14 @@ class Batch:
         _check(lib().pgabb_batch_times(self._h, ctypes.byref(b), ctypes.byref(c)))
         return b.value, c.value
 
+    def launch_shape(self):
+        """Kernel, waves per workgroup and rows per grab of the last
+        captured count, and the time its autotuning took (ms)."""
+        k, w, r, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().pgabb_batch_launch_shape(self._h, ctypes.byref(k), ctypes.byref(w), ctypes.byref(r),
+                                              ctypes.byref(t)))
+        return {"kernel": k.value, "waves_per_block": w.value, "rows_per_grab": r.value, "t_tune_ms": t.value}
+
     def stats(self):
         """Sizes of the union graph: oriented edges, active rows (the
         count's work items), their edges and the entries a count walks."""
@@ -566,6 +591,13 @@ class Server:
         v = ctypes.c_uint64()
         _check(lib().pgabb_server_stats(self._h, ctypes.byref(v)))
         return v.value
+
+    def kernel_stats(self):
+        """(kernel ms, walked entries, edges) summed over the counting
+        launches so far."""
+        k, w, e = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pgabb_server_kernel_stats(self._h, ctypes.byref(k), ctypes.byref(w), ctypes.byref(e)))
+        return k.value, w.value, e.value
 
     def close(self):
         if getattr(self, "_h", None):

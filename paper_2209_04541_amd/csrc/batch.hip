@@ -47,13 +47,13 @@ struct pgabb_batch {
     pgabb::DArray<int32_t> row_gid;   // graph of each active row
     pgabb::DArray<int64_t> graph_row_pre;  // G + 1: active rows per graph prefix
     std::vector<int64_t> h_graph_row_pre;
-    pgabb::DArray<unsigned long long> counts;  // G + 1 (last: work counter)
+    pgabb::DArray<unsigned long long> counts;  // G, then the work queues' counters
     pgabb::PinnedArray<unsigned long long> hcounts;
     // captured launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int cfg_mode = -1, cfg_waves = 0, cfg_grab = 0, cfg_words = 0;
-    double t_build_ms = 0, t_count_ms = 0;
+    double t_build_ms = 0, t_count_ms = 0, t_tune_ms = 0;
     ~pgabb_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -230,6 +230,17 @@ __global__ void k_graph_row_pre_b(const uint32_t *__restrict__ pos, const int64_
         pre[g] = pos[vbase[g]];
 }
 
+// Work queues of a batch launch: the active rows (grouped by graph) are cut
+// into kBatchQueues contiguous ranges of equal length, each with its own
+// counter; workgroup b starts on range b % kBatchQueues -- its XCD under
+// the round-robin dispatch of workgroups to the 8 XCDs -- and moves on to
+// the next range once its own is drained.  The waves of one XCD then walk
+// the rows of a few graphs at a time, whose lists stay in that XCD's L2;
+// with one counter for all, every XCD held rows of every graph in flight.
+constexpr int kBatchQueues = 8;
+constexpr int kBatchQueueStride = 32;  // counters 256 bytes apart
+constexpr int kBatchQueueWords = kBatchQueues * kBatchQueueStride;
+
 struct BatchArgs {
     const int32_t *rptr;
     const int32_t *col;
@@ -239,8 +250,9 @@ struct BatchArgs {
     int64_t first;  // items [first, last)
     int64_t last;
     int32_t grab;
+    int32_t nq;     // work queues (1 or kBatchQueues)
     unsigned long long *counts;
-    unsigned long long *next;
+    unsigned long long *next;  // nq counters, kBatchQueueStride apart (zero before launch)
 };
 
 template <int MODE, int LDS_WORDS, int WAVES>
@@ -252,13 +264,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
         for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
         wave_lds_sync();
     }
-    for (;;) {
+    const int64_t per = (a.last - a.first + a.nq - 1) / a.nq;
+    const int home = static_cast<int>(blockIdx.x % a.nq);
+    for (int qi = 0; qi < a.nq; ++qi) {
+      const int q = (home + qi) % a.nq;
+      const int64_t q0 = a.first + q * per;
+      const int64_t q1 = min(q0 + per, a.last);
+      for (;;) {
         unsigned long long g0 = 0;
-        if (lane == 0) g0 = atomicAdd(a.next, static_cast<unsigned long long>(a.grab));
+        if (lane == 0) g0 = atomicAdd(&a.next[q * kBatchQueueStride], static_cast<unsigned long long>(a.grab));
         g0 = shfl_t(g0, 0);
-        const int64_t i0 = a.first + static_cast<int64_t>(g0);
-        if (i0 >= a.last) break;
-        const int64_t i1 = min(i0 + a.grab, a.last);
+        const int64_t i0 = q0 + static_cast<int64_t>(g0);
+        if (i0 >= q1) break;
+        const int64_t i1 = min(i0 + a.grab, q1);
         int32_t gcur = a.row_gid[i0];
         uint32_t cnt = 0;
         for (int64_t it = i0; it < i1; ++it) {
@@ -277,6 +295,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
         }
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
         if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);
+      }
     }
 }
 
@@ -347,6 +366,7 @@ BatchArgs batch_args(pgabb_batch *b, int grab) {
     a.first = 0;
     a.last = b->nactive;
     a.grab = grab;
+    a.nq = kBatchQueues;
     a.counts = b->counts.get();
     a.next = b->counts.get() + b->G;
     return a;
@@ -354,38 +374,34 @@ BatchArgs batch_args(pgabb_batch *b, int grab) {
 
 // Everything one count does, on one stream (capturable: no memset nodes).
 void enqueue_count(pgabb_batch *b, int mode, int waves, int grab, hipStream_t s) {
-    k_zero_u64<<<cap_grid(b->G + 1), B, 0, s>>>(b->counts.get(), b->G + 1);
+    k_zero_u64<<<cap_grid(b->G + kBatchQueueWords), B, 0, s>>>(b->counts.get(), b->G + kBatchQueueWords);
     PGABB_HIP(hipGetLastError());
     launch_batch(batch_args(b, grab), mode, words_for(mode, b), waves, s);
     PGABB_HIP(hipMemcpyAsync(b->hcounts.get(), b->counts.get(), sizeof(unsigned long long) * b->G,
                              hipMemcpyDeviceToHost, s));
 }
 
-struct TuneKey {
-    int64_t g_bucket, n_bucket, m_bucket, deg_bucket;
-    bool operator<(const TuneKey &o) const {
-        return std::tie(g_bucket, n_bucket, m_bucket, deg_bucket) <
-               std::tie(o.g_bucket, o.n_bucket, o.m_bucket, o.deg_bucket);
-    }
-};
 struct TuneVal {
     int mode, waves, grab;
 };
-std::mutex g_tune_mu;
-std::map<TuneKey, TuneVal> g_tune_cache;
 
-TuneKey tune_key(const pgabb_batch *b) {
-    return TuneKey{bit_width_u64(static_cast<uint64_t>(b->G)), bit_width_u64(static_cast<uint64_t>(b->max_n)),
-                   bit_width_u64(static_cast<uint64_t>(b->mu)),
-                   bit_width_u64(static_cast<uint64_t>(b->max_out))};
+// Shape class of a batch: bit widths of its graph count, largest graph,
+// edges and longest oriented row.
+std::string tune_key(const pgabb_batch *b) {
+    char key[96];
+    snprintf(key, sizeof key, "batch/G%d/N%d/M%d/D%d", bit_width_u64(static_cast<uint64_t>(b->G)),
+             bit_width_u64(static_cast<uint64_t>(b->max_n)), bit_width_u64(static_cast<uint64_t>(b->mu)),
+             bit_width_u64(static_cast<uint64_t>(b->max_out)));
+    return key;
 }
 
+// The launch shape for this batch: from the persisted tuning cache, else the
+// fastest of the candidates timed on the batch itself (then stored).
 TuneVal autotune(pgabb_batch *b) {
-    const TuneKey key = tune_key(b);
+    const std::string key = tune_key(b);
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return it->second;
+        std::vector<int> v;
+        if (tune_lookup(key, v) && v.size() == 3) return TuneVal{v[0], v[1], v[2]};
     }
     hipStream_t s = b->stream;
     StreamTimer tm;
@@ -404,7 +420,7 @@ TuneVal autotune(pgabb_batch *b) {
     std::vector<std::pair<double, TuneVal>> timed;
     const int modes[] = {kModeBitmap, kModeHash};
     const int wavess[] = {2, 4, 8};
-    const int grabs[] = {1, 4, 16};
+    const int grabs[] = {8, 16, 32};
     for (int mode : modes) {
         if (mode == kModeBitmap && (static_cast<int64_t>(b->max_n) + 31) / 32 > 2304) continue;
         for (int waves : wavess)
@@ -424,8 +440,7 @@ TuneVal autotune(pgabb_batch *b) {
             best = timed[q].second;
         }
     }
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best;
+    tune_store(key, {best.mode, best.waves, best.grab});
     return best;
 }
 
@@ -481,7 +496,7 @@ void batch_build(pgabb_batch *b, const int32_t *n, const int64_t *eoff, const in
 
     b->dvbase.reset(G + 1, s);
     PGABB_HIP(hipMemcpyAsync(b->dvbase.get(), b->vbase.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
-    b->counts.reset(G + 1, s);
+    b->counts.reset(G + kBatchQueueWords, s);
     b->hcounts.reset(static_cast<size_t>(std::max<int64_t>(G, 1)));
     b->rptr.reset(b->total_n + 1, s);
 
@@ -606,7 +621,7 @@ void batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uint64_t *out) {
         const int mode = kModeHash;
         const int waves = 4, grab = 8;
         tm.start(s);
-        k_zero_u64<<<cap_grid(b->G + 1), B, 0, s>>>(b->counts.get(), b->G + 1);
+        k_zero_u64<<<cap_grid(b->G + kBatchQueueWords), B, 0, s>>>(b->counts.get(), b->G + kBatchQueueWords);
         DArray<unsigned long long> ctr(b->G, s);
         k_zero_u64<<<cap_grid(b->G), B, 0, s>>>(ctr.get(), b->G);
         for (int64_t g = 0; g < b->G; ++g) {
@@ -614,6 +629,7 @@ void batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uint64_t *out) {
             a.first = b->h_graph_row_pre[g];
             a.last = b->h_graph_row_pre[g + 1];
             a.next = ctr.get() + g;
+            a.nq = 1;
             launch_batch(a, mode, words_for(mode, b), waves, s);
         }
         PGABB_HIP(hipMemcpyAsync(b->hcounts.get(), b->counts.get(), sizeof(unsigned long long) * b->G,
@@ -628,7 +644,9 @@ void batch_count(pgabb_batch *b, const pgabb_tc_options *opts, uint64_t *out) {
             waves = opts->waves_per_block > 0 ? opts->waves_per_block : 4;
             grab = opts->rows_per_grab > 0 ? opts->rows_per_grab : 4;
         } else {
+            const auto t0 = std::chrono::steady_clock::now();
             const TuneVal tv = autotune(b);
+            b->t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             mode = tv.mode;
             waves = tv.waves;
             grab = tv.grab;
@@ -723,6 +741,16 @@ PGABB_API pgabb_status pgabb_batch_stats(const pgabb_batch *b, int64_t *edges, i
     if (active_rows) *active_rows = b->nactive;
     if (active_edges) *active_edges = b->m_active;
     if (walked) *walked = b->walked;
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_batch_launch_shape(const pgabb_batch *b, int32_t *kernel, int32_t *waves_per_block,
+                                                int32_t *rows_per_grab, double *t_tune_ms) {
+    if (!b) return capture_status(Error{PGABB_EINVAL, "batch is NULL"});
+    if (kernel) *kernel = b->cfg_mode < 0 ? -1 : (b->cfg_mode == kModeBitmap ? PGABB_KERNEL_BITMAP : PGABB_KERNEL_HASH);
+    if (waves_per_block) *waves_per_block = b->cfg_waves;
+    if (rows_per_grab) *rows_per_grab = b->cfg_grab;
+    if (t_tune_ms) *t_tune_ms = b->t_tune_ms;
     return capture_status(Error{PGABB_OK, ""});
 }
 

@@ -115,9 +115,22 @@ __global__ __launch_bounds__(kBB) void k_sv_minid(const int32_t *__restrict__ C,
                                                   int32_t n, int32_t *__restrict__ minid,
                                                   unsigned long long *__restrict__ roots) {
     uint32_t c = 0;
-    for (int64_t v = blockIdx.x * int64_t(kBB) + threadIdx.x; v < n; v += int64_t(gridDim.x) * kBB) {
-        atomicMin(&minid[C[rank[v]]], static_cast<int32_t>(v));
-        c += C[v] == v ? 1u : 0u;
+    const int lane = lane_id();
+    const int64_t stride = int64_t(gridDim.x) * kBB;
+    for (int64_t base = blockIdx.x * int64_t(kBB) + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
+        const int64_t v = base + lane;
+        const bool ok = v < n;
+        const int32_t root = ok ? C[rank[v]] : -1;
+        // one large component holds most vertices: the lanes whose root is
+        // the first lane's send one minimum, the others one atomic each
+        const int32_t r0 = __builtin_amdgcn_readfirstlane(root);
+        const bool same = ok && root == r0;
+        int32_t mv = same ? static_cast<int32_t>(v) : INT32_MAX;
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) mv = min(mv, __shfl_xor(mv, m));
+        if (lane == 0 && r0 >= 0 && mv != INT32_MAX) atomicMin(&minid[r0], mv);
+        if (ok && !same) atomicMin(&minid[root], static_cast<int32_t>(v));
+        c += ok && C[v] == v ? 1u : 0u;
     }
     const unsigned long long sum = wave_sum(static_cast<unsigned long long>(c));
     if (lane_id() == 0 && sum) atomicAdd(roots, sum);

@@ -199,7 +199,7 @@ static pgabb_tc_options default_options() {
 static pgabb_status check_options(const pgabb_tc_options &o) {
     if (o.kernel < PGABB_KERNEL_AUTO || o.kernel > PGABB_KERNEL_SEARCH)
         return set_err(PGABB_EINVAL, "unknown kernel");
-    if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0 || o.queue_run < 0)
+    if (o.num_streams < 0 || o.waves_per_block < 0 || o.rows_per_grab < 0)
         return set_err(PGABB_EINVAL, "negative option");
     if (o.waves_per_block && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
         return set_err(PGABB_EINVAL, "waves_per_block must be 2, 4 or 8");
@@ -308,6 +308,19 @@ PGABB_API pgabb_status pgabb_pagerank(pgabb_graph *g, double damping, double tol
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_graph_4list_counts(const pgabb_graph *g, int64_t *num_lists, int32_t *ijkl,
+                                               uint64_t *counts) {
+    if (!g) return set_err(PGABB_EINVAL, "graph is NULL");
+    const int64_t nq = static_cast<int64_t>(g->quads.size());
+    if (num_lists) *num_lists = nq;
+    for (int64_t q = 0; q < nq; ++q) {
+        if (ijkl)
+            for (int r = 0; r < 4; ++r) ijkl[4 * q + r] = g->quads[q][r];
+        if (counts) counts[q] = g->quad_counts[q];
+    }
+    return set_ok();
+}
+
 PGABB_API pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count) {
     if (!g || !count) return set_err(PGABB_EINVAL, "NULL argument");
     PGABB_TRY
@@ -367,6 +380,13 @@ PGABB_API pgabb_status pgabb_tc_count_batch(pgabb_graph *const *gs, int64_t num_
     PGABB_CATCH
 }
 
+PGABB_API pgabb_status pgabb_tune_cache_reload(void) {
+    PGABB_TRY
+    tune_reload();
+    return set_ok();
+    PGABB_CATCH
+}
+
 PGABB_API uint64_t pgabb_tc_count(pgabb_graph *g) {
     uint64_t c = PGABB_COUNT_ERROR;
     if (pgabb_tc_count_ex(g, nullptr, &c) != PGABB_OK) return PGABB_COUNT_ERROR;
@@ -403,11 +423,18 @@ PGABB_API pgabb_status pgabb_graph_info_get(const pgabb_graph *g, pgabb_graph_in
     info->walked_columns = g->walked_columns;
     info->host_tasks = g->host_tasks;
     info->host_work_share = g->host_work_share;
+    info->t_tune_ms = g->t_tune_ms;
     info->row_items = 0;
     info->col_items = 0;
+    info->walk_bytes_rows = 0;
+    info->walk_bytes_cols = 0;
     for (const pgabb::BlockInfo &b : g->blocks) {
         info->row_items += b.nitems;
         info->col_items += b.ncitems;
+        info->walk_bytes_rows += sizeof(int32_t) * static_cast<uint64_t>(b.walk_hi(pgabb::kOrientRow) -
+                                                                           b.walk_lo(pgabb::kOrientRow));
+        info->walk_bytes_cols += sizeof(int32_t) * static_cast<uint64_t>(b.walk_hi(pgabb::kOrientCol) -
+                                                                           b.walk_lo(pgabb::kOrientCol));
     }
     return set_ok();
 }

@@ -186,6 +186,7 @@ bool radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t
 bool tune_lookup(const std::string &key, std::vector<int> &val);
 void tune_store(const std::string &key, const std::vector<int> &val);
 void tune_forget_all();
+void tune_reload();
 
 // Number of bits needed to hold v (0 for v = 0).
 inline int bit_width_u64(uint64_t v) {

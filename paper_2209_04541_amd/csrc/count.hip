@@ -13,6 +13,8 @@
 #include <chrono>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <string>
 #include <queue>
 #include <vector>
 
@@ -130,9 +132,6 @@ void launch_one(const CountArgs &a, int mode, int lds_words, int waves, hipStrea
     }
 }
 
-__global__ void k_zero_queues(unsigned long long *p, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
-}
 
 }  // namespace
 
@@ -141,36 +140,19 @@ void launch_tc_tasks(const CountArgs &args, const LaunchKind &lk, int waves, hip
     if (args.total <= 0) return;
     CountArgs a = args;
     a.grab = std::max(1, std::min(a.grab, kWave));  // a grab's items fit one wave's lanes
-    a.qrun = queue_run((a.total + a.grab - 1) / a.grab, a.qrun);
     if (lk.nparts == 1) {
         launch_one(a, lk.mode, lk.words, waves, s, grid_override, unroll);
         return;
     }
     // the parts of a split launch run at the default shape (waves and unroll
     // options apply to single launches)
+    unsigned long long *const next0 = a.next;
     for (int q = 0; q < lk.nparts; ++q) {
-        if (q > 0) {
-            // a fill kernel, not a memset node: callers may capture the launch
-            k_zero_queues<<<1, 256, 0, s>>>(a.next, kQueueWords);
-            PGABB_HIP(hipGetLastError());
-        }
+        a.next = next0 + static_cast<size_t>(q) * kQueueWords;  // counters of their own, cleared before
         a.stage_lo = q == 0 ? 0 : lk.hi[q - 1];
         a.stage_hi = lk.hi[q];
         launch_filtered(a, lk.pmode[q], lk.pwords[q], s, grid_override);
     }
-}
-
-int64_t queue_run(int64_t units, int64_t requested) {
-    if (requested > 0) return std::min(requested, std::max<int64_t>(1, (units + kQueues - 1) / kQueues));
-    // Round-robin (runs of one unit).  Measured on R-MAT scale 20 (p = 8) and
-    // scale 24 (p = 32, in core): one contiguous range per queue, which keeps
-    // each XCD on neighbouring items and their blocks in its own L2, made the
-    // kernel 15 % and 7 % slower -- the heaviest items then all sit in one
-    // queue and finish last -- and runs of 4 to 256 units were within 1 % of
-    // round-robin.  Item order (heaviest first) matters more than L2
-    // locality across XCDs here.
-    (void)units;
-    return 1;
 }
 
 int default_grab(int64_t total_items, uint64_t walked) {
@@ -248,10 +230,9 @@ TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &
         const BlockInfo &bi = g->blocks[b];
         const int32_t *c = arena_base + (chunk_dev_off ? chunk_dev_off[b] : bi.chunk_off);
         BlockRef r;
-        r.rptr = c;
+        r.rptr = c + (bi.off_rptr() - bi.chunk_off);
         r.items = c + (bi.off_items() - bi.chunk_off);
         r.col = c + (bi.off_col() - bi.chunk_off);
-        r.cptr = c + (bi.off_cptr() - bi.chunk_off);
         r.citems = c + (bi.off_citems() - bi.chunk_off);
         r.crow = c + (bi.off_crow() - bi.chunk_off);
         r.nitems = bi.nitems;
@@ -302,10 +283,10 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     }
     DArray<TaskDesc> dtd(T, s);
     DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
-    DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kQueueWords, s);  // counts, then queues
+    DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kLaunchQueueWords, s);  // counts, then queues
     PGABB_HIP(hipMemcpyAsync(dtd.get(), td.get(), td.bytes(), hipMemcpyHostToDevice, s));
     PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.get(), pre.bytes(), hipMemcpyHostToDevice, s));
-    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kQueueWords), s));
+    PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kLaunchQueueWords), s));
 
     CountArgs a;
     a.tasks = dtd.get();
@@ -318,7 +299,6 @@ static uint64_t count_in_core(pgabb_graph *g, const pgabb_tc_options &opt) {
     const uint64_t walked = static_cast<uint64_t>(static_cast<double>(walked_entries(g, orient)) * g->task_share);
     a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T], walked);
     a.orient = orient;
-    a.qrun = opt.queue_run;
     const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
     const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
     StreamTimer tm;
@@ -461,127 +441,245 @@ uint64_t count_shard(pgabb_graph *g, const pgabb_tc_options &opt, int32_t shard,
     return total;
 }
 
+namespace {
+
+// The tasks of several in-core graphs as one work list.
+struct MergedTasks {
+    std::vector<TaskDesc> desc;
+    std::vector<int64_t> pre{0};  // items per task, prefix
+    int32_t max_wk = 0, min_wk = INT32_MAX, max_st = 0;
+    uint64_t walked = 0;
+};
+
+MergedTasks merge_tasks(pgabb_graph *const *gs, const std::vector<int64_t> &which, int orient) {
+    MergedTasks m;
+    for (int64_t q : which) {
+        pgabb_graph *g = gs[q];
+        m.walked += walked_entries(g, orient);
+        for (const Task &t : g->tasks) {
+            m.desc.push_back(make_desc(g, g->arena.get(), t, static_cast<int32_t>(m.desc.size()), nullptr));
+            m.pre.push_back(m.pre.back() + task_items(g, t, orient));
+            m.max_wk = std::max(m.max_wk, m.desc.back().width_k);
+            m.min_wk = std::min(m.min_wk, m.desc.back().width_k);
+            m.max_st = std::max(m.max_st, staged_max(g, t, orient));
+        }
+    }
+    return m;
+}
+
+// One counting launch over merged tasks, staged on stream s.  run() counts
+// with a launch shape and returns the launch's device milliseconds; the
+// per-task counts of the last run are read back by fetch().
+class MergedLaunch {
+  public:
+    MergedLaunch(const MergedTasks &m, const pgabb_tc_options &opt, int orient, hipStream_t s)
+        : m_(m), s_(s), T_(static_cast<int32_t>(m.desc.size())) {
+        lk_ = launch_kind(opt.kernel, m.max_st, m.max_wk, m.min_wk);
+        g0_ = default_grab(m.pre.back(), m.walked);
+        if (T_ == 0) return;
+        Staged<TaskDesc> td(T_, s);
+        Staged<int64_t> pre(static_cast<size_t>(T_) + 1, s);
+        std::copy(m.desc.begin(), m.desc.end(), td.get());
+        std::copy(m.pre.begin(), m.pre.end(), pre.get());
+        dtd_.reset(T_, s);
+        dpre_.reset(static_cast<size_t>(T_) + 1, s);
+        dcnt_.reset(static_cast<size_t>(T_) + kLaunchQueueWords, s);
+        PGABB_HIP(hipMemcpyAsync(dtd_.get(), td.get(), td.bytes(), hipMemcpyHostToDevice, s));
+        PGABB_HIP(hipMemcpyAsync(dpre_.get(), pre.get(), pre.bytes(), hipMemcpyHostToDevice, s));
+        a_.tasks = dtd_.get();
+        a_.item_pre = dpre_.get();
+        a_.ntasks = T_;
+        a_.total = m.pre.back();
+        a_.counts = dcnt_.get();
+        a_.next = dcnt_.get() + T_;
+        a_.orient = orient;
+    }
+    int32_t tasks() const { return T_; }
+    int64_t items() const { return a_.total; }
+    int default_grab_() const { return g0_; }
+    const LaunchKind &kind() const { return lk_; }
+    double run(int waves, int grab, int unroll) {
+        if (T_ == 0 || a_.total == 0) return 0.0;
+        PGABB_HIP(hipMemsetAsync(dcnt_.get(), 0, sizeof(unsigned long long) * (T_ + kLaunchQueueWords), s_));
+        a_.grab = grab;
+        tm_.start(s_);
+        launch_tc_tasks(a_, lk_, waves, s_, 0, unroll);
+        tm_.stop(s_);
+        return tm_.ms();
+    }
+    std::vector<uint64_t> fetch() {
+        std::vector<uint64_t> out(T_, 0);
+        if (T_ == 0) return out;
+        Staged<unsigned long long> h(T_, s_);
+        PGABB_HIP(hipMemcpyAsync(h.get(), dcnt_.get(), h.bytes(), hipMemcpyDeviceToHost, s_));
+        PGABB_HIP(hipStreamSynchronize(s_));
+        std::copy(h.get(), h.get() + T_, out.begin());
+        return out;
+    }
+
+  private:
+    const MergedTasks &m_;
+    hipStream_t s_;
+    int32_t T_;
+    LaunchKind lk_;
+    int g0_ = 2;
+    CountArgs a_{};
+    DArray<TaskDesc> dtd_;
+    DArray<int64_t> dpre_;
+    DArray<unsigned long long> dcnt_;
+    StreamTimer tm_;
+};
+
+// Shape class of a graph for the grid search: bit widths of its edges and
+// of its longest oriented row.
+std::string grid_class(const pgabb_graph *g) {
+    char key[96];
+    snprintf(key, sizeof key, "tc_graphs_grid/M%d/D%d", bit_width_u64(static_cast<uint64_t>(g->m)),
+             bit_width_u64(static_cast<uint64_t>(g->max_out)));
+    return key;
+}
+
+}  // namespace
+
 // Counts of several graph objects.  Every graph whose blocks are in device
 // memory joins one counting launch over all of their tasks (each task keeps
 // its own counter, so each graph's per-task counts come back too); a graph
 // whose blocks are streamed from the host store, or that opts ask to stream
-// or count hybrid, is counted on its own.  With tune, the launch shape
-// (waves per workgroup, items per grab, chunks per load batch) is the
-// fastest of a few candidates timed on this launch, remembered by shape
-// class (graph count, tasks, items, walked entries per item, longest staged
-// list) in the persisted tuning cache.
+// or count hybrid, is counted on its own.
+//
+// With tune (no options given), two choices are made by timing and kept in
+// the persisted tuning cache:
+//   1. the grid of each shape class of graphs (bit widths of m' and of the
+//      longest row): p in {1, 2, 4, 8, 16} with nnz-balanced cuts, and p = 8
+//      with uniform cuts, each timed as one launch over the class's graphs
+//      partitioned that way;
+//   2. the launch shape of the whole merged launch (waves per workgroup,
+//      items per grab, chunks per load batch), keyed by graph count, tasks,
+//      items, walked entries per item and longest staged list.
 void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt, bool tune, uint64_t *counts) {
+    const auto t_tune0 = std::chrono::steady_clock::now();
+    double tune_ms = 0;
+    hipStream_t s = library_stream();
+    const int orient = orient_of_option(opt, nullptr);
+    auto in_core = [&](pgabb_graph *g) {
+        const uint64_t block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
+        return !(g->blocks_on_host || (opt.flags & (PGABB_OPT_STREAM | PGABB_OPT_HYBRID)) ||
+                 (opt.device_cap_bytes && block_bytes > opt.device_cap_bytes));
+    };
+    auto after_graph_streams = [&](const std::vector<int64_t> &which) {
+        for (int64_t q : which) {  // launches on the library stream follow each graph's own work
+            hipEvent_t ev = nullptr;
+            PGABB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            PGABB_HIP(hipEventRecord(ev, gs[q]->stream));
+            PGABB_HIP(hipStreamWaitEvent(s, ev, 0));
+            PGABB_HIP(hipEventDestroy(ev));
+        }
+    };
+    if (tune) {
+        // ---- 1. the grid per shape class
+        std::map<std::string, std::vector<int64_t>> classes;
+        for (int64_t q = 0; q < G; ++q) {
+            pgabb_graph *g = gs[q];
+            if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+            if (in_core(g) && g->m > 0) classes[grid_class(g)].push_back(q);
+        }
+        static const int32_t kGridP[] = {1, 2, 4, 8, 16, 8};
+        static const int32_t kGridCut[] = {PGABB_CUT_NNZ, PGABB_CUT_NNZ, PGABB_CUT_NNZ, PGABB_CUT_NNZ,
+                                           PGABB_CUT_NNZ, PGABB_CUT_UNIFORM};
+        for (auto &kv : classes) {
+            std::vector<int> v;
+            int32_t bp = 1, bcut = PGABB_CUT_NNZ;
+            if (tune_lookup(kv.first, v) && v.size() == 2 && v[0] >= 1 && v[0] <= 64 &&
+                (v[1] == PGABB_CUT_NNZ || v[1] == PGABB_CUT_UNIFORM)) {
+                bp = v[0];
+                bcut = v[1];
+            } else {
+                double best = 1e30;
+                int32_t max_n = 1;
+                for (int64_t q : kv.second) max_n = std::max(max_n, gs[q]->n);
+                for (int c = 0; c < 6; ++c) {
+                    if (kGridP[c] > max_n) continue;
+                    for (int64_t q : kv.second) {
+                        pgabb_graph *g = gs[q];
+                        if (g->p != kGridP[c] || g->cut_mode != kGridCut[c])
+                            partition_graph(g, kGridP[c], kGridCut[c], nullptr);
+                    }
+                    after_graph_streams(kv.second);
+                    const MergedTasks mt = merge_tasks(gs, kv.second, orient);
+                    MergedLaunch ml(mt, opt, orient, s);
+                    const int gr = ml.default_grab_();
+                    ml.run(4, gr, 2);  // warm
+                    const double ms = std::min(ml.run(4, gr, 2), ml.run(4, gr, 2));
+                    if (ms < best) {
+                        best = ms;
+                        bp = kGridP[c];
+                        bcut = kGridCut[c];
+                    }
+                }
+                tune_store(kv.first, {bp, bcut});
+            }
+            for (int64_t q : kv.second) {
+                pgabb_graph *g = gs[q];
+                if (g->p != bp || g->cut_mode != bcut) partition_graph(g, bp, bcut, nullptr);
+            }
+        }
+    }
     std::vector<int64_t> merged;
     for (int64_t q = 0; q < G; ++q) {
         pgabb_graph *g = gs[q];
-        ensure_partition(g, opt);
-        const uint64_t block_bytes = static_cast<uint64_t>(g->arena_words) * sizeof(int32_t);
-        const bool alone = g->blocks_on_host || (opt.flags & (PGABB_OPT_STREAM | PGABB_OPT_HYBRID)) ||
-                           (opt.device_cap_bytes && block_bytes > opt.device_cap_bytes);
-        if (alone) counts[q] = count_graph(g, opt);
-        else merged.push_back(q);
+        if (!tune) ensure_partition(g, opt);
+        else if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+        if (in_core(g)) merged.push_back(q);
+        else counts[q] = count_graph(g, opt);
     }
     if (merged.empty()) return;
-    auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = library_stream();
-    const int orient = orient_of_option(opt, nullptr);
-    std::vector<TaskDesc> tdv;
-    std::vector<int64_t> prev(1, 0);
-    int32_t max_wk = 0, min_wk = INT32_MAX, max_st = 0;
-    uint64_t walked = 0;
+    after_graph_streams(merged);
     for (int64_t q : merged) {
         pgabb_graph *g = gs[q];
         g->walked_columns = orient == kOrientCol;
         g->h2d_bytes = 0;
         g->host_tasks = 0;
         g->host_work_share = 0;
-        walked += walked_entries(g, orient);
-        for (const Task &t : g->tasks) {
-            tdv.push_back(make_desc(g, g->arena.get(), t, static_cast<int32_t>(tdv.size()), nullptr));
-            prev.push_back(prev.back() + task_items(g, t, orient));
-            max_wk = std::max(max_wk, tdv.back().width_k);
-            min_wk = std::min(min_wk, tdv.back().width_k);
-            max_st = std::max(max_st, staged_max(g, t, orient));
-        }
-        // the launch runs on the library stream after the graph's own work
-        hipEvent_t ev = nullptr;
-        PGABB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        PGABB_HIP(hipEventRecord(ev, g->stream));
-        PGABB_HIP(hipStreamWaitEvent(s, ev, 0));
-        PGABB_HIP(hipEventDestroy(ev));
     }
-    const int32_t T = static_cast<int32_t>(tdv.size());
-    std::vector<uint64_t> tc(T, 0);
-    double kernel_ms = 0;
-    int launches = 0;
-    if (T > 0) {
-        Staged<TaskDesc> td(T, s);
-        Staged<int64_t> pre(static_cast<size_t>(T) + 1, s);
-        std::copy(tdv.begin(), tdv.end(), td.get());
-        std::copy(prev.begin(), prev.end(), pre.get());
-        DArray<TaskDesc> dtd(T, s);
-        DArray<int64_t> dpre(static_cast<size_t>(T) + 1, s);
-        DArray<unsigned long long> dcnt(static_cast<size_t>(T) + kQueueWords, s);
-        PGABB_HIP(hipMemcpyAsync(dtd.get(), td.get(), td.bytes(), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(dpre.get(), pre.get(), pre.bytes(), hipMemcpyHostToDevice, s));
-        CountArgs a;
-        a.tasks = dtd.get();
-        a.item_pre = dpre.get();
-        a.ntasks = T;
-        a.total = prev.back();
-        a.counts = dcnt.get();
-        a.next = dcnt.get() + T;
-        a.orient = orient;
-        a.qrun = opt.queue_run;
-        const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
-        const int g0 = default_grab(a.total, walked);
-        int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
-        int grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : g0;
-        int unroll = opt.unroll;
-        StreamTimer tm;
-        auto run = [&](int w, int gr, int un) {
-            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (T + kQueueWords), s));
-            a.grab = gr;
-            tm.start(s);
-            launch_tc_tasks(a, lk, w, s, 0, un);
-            tm.stop(s);
-            return tm.ms();
-        };
-        if (tune && lk.nparts == 1 && a.total > 0) {
-            const uint64_t per_item = a.total ? walked / static_cast<uint64_t>(a.total) : 0;
-            char key[160];
-            snprintf(key, sizeof key, "tc_graphs/G%d/T%d/I%d/W%d/S%d/K%d/O%d", bit_width_u64(merged.size()),
-                     bit_width_u64(T), bit_width_u64(a.total), bit_width_u64(per_item), bit_width_u64(max_st),
-                     lk.mode, orient);
-            std::vector<int> v;
-            if (tune_lookup(key, v) && v.size() == 3) {
-                waves = v[0];
-                grab = v[1];
-                unroll = v[2];
-            } else {
-                double best = 1e30;
-                for (int w : {2, 4, 8})
-                    for (int gr : {std::max(1, g0 / 2), g0, std::min(64, 2 * g0)})
-                        for (int un : {2, 4}) {
-                            run(w, gr, un);  // warm
-                            const double ms = std::min(run(w, gr, un), run(w, gr, un));
-                            if (ms < best) {
-                                best = ms;
-                                waves = w;
-                                grab = gr;
-                                unroll = un;
-                            }
+    const MergedTasks mt = merge_tasks(gs, merged, orient);
+    MergedLaunch ml(mt, opt, orient, s);
+    const int g0 = ml.default_grab_();
+    int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
+    int grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : g0;
+    int unroll = opt.unroll;
+    // ---- 2. the launch shape
+    if (tune && ml.kind().nparts == 1 && ml.items() > 0) {
+        const uint64_t per_item = mt.walked / static_cast<uint64_t>(ml.items());
+        char key[160];
+        snprintf(key, sizeof key, "tc_graphs/G%d/T%d/I%d/W%d/S%d/K%d/O%d", bit_width_u64(merged.size()),
+                 bit_width_u64(ml.tasks()), bit_width_u64(ml.items()), bit_width_u64(per_item),
+                 bit_width_u64(mt.max_st), ml.kind().mode, orient);
+        std::vector<int> v;
+        if (tune_lookup(key, v) && v.size() == 3) {
+            waves = v[0];
+            grab = v[1];
+            unroll = v[2];
+        } else {
+            double best = 1e30;
+            for (int w : {2, 4, 8})
+                for (int gr : {std::max(1, g0 / 2), g0, std::min(64, 2 * g0)})
+                    for (int un : {2, 4}) {
+                        ml.run(w, gr, un);  // warm
+                        const double ms = std::min(ml.run(w, gr, un), ml.run(w, gr, un));
+                        if (ms < best) {
+                            best = ms;
+                            waves = w;
+                            grab = gr;
+                            unroll = un;
                         }
-                tune_store(key, {waves, grab, unroll});
-            }
+                    }
+            tune_store(key, {waves, grab, unroll});
         }
-        kernel_ms = run(waves, grab, unroll);
-        launches = lk.nparts;
-        Staged<unsigned long long> hcnt(T, s);
-        PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), hcnt.bytes(), hipMemcpyDeviceToHost, s));
-        PGABB_HIP(hipStreamSynchronize(s));
-        std::copy(hcnt.get(), hcnt.get() + T, tc.begin());
     }
+    if (tune) tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_tune0).count();
+    const auto t0 = std::chrono::steady_clock::now();
+    const double kernel_ms = ml.run(waves, grab, unroll);
+    const std::vector<uint64_t> tc = ml.fetch();
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     size_t at = 0;
     for (int64_t q : merged) {
@@ -594,7 +692,8 @@ void count_graphs(pgabb_graph *const *gs, int64_t G, const pgabb_tc_options &opt
         counts[q] = total;
         g->t_count_ms = ms;
         g->t_kernel_ms = kernel_ms;
-        g->kernel_launches = launches;
+        g->t_tune_ms = tune_ms;
+        g->kernel_launches = ml.kind().nparts;
     }
 }
 

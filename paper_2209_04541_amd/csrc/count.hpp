@@ -5,14 +5,23 @@
 
 namespace pgabb {
 
-// Work queues of a counting launch: grab units are dealt to kQueues counters
-// in runs of CountArgs::qrun consecutive units, run r to queue r % kQueues; a
-// workgroup starts on queue blockIdx % kQueues (its XCD under round-robin
-// dispatch) and moves on to the others once it is empty.
+// Work queues of a counting launch: grab units are dealt round-robin to
+// kQueues counters; a workgroup starts on queue blockIdx % kQueues (its XCD
+// under round-robin dispatch) and moves on to the others once it is empty.
+// (Measured on R-MAT scale 20 at p = 8 and scale 24 at p = 32: one
+// contiguous range of units per queue, which keeps each XCD's waves on
+// neighbouring items and their blocks in its own L2, made the kernel 15 %
+// and 7 % slower -- the heaviest items all sit in one queue -- and runs of 4
+// to 256 units per queue were within 1 % of round-robin.)
 constexpr int kQueues = 8;
 // Counters sit 256 bytes apart so no two share a memory channel's line.
 constexpr int kQueueStride = 32;
 constexpr int kQueueWords = kQueues * kQueueStride;
+// Queue counters of one counting launch: one set per part of a launch split
+// by staged-list length (at most 3 parts), all cleared before the launch, so
+// no clearing runs between the parts.
+constexpr int kMaxParts = 3;
+constexpr int kLaunchQueueWords = kMaxParts * kQueueWords;
 
 struct CountArgs {
     const TaskDesc *tasks;     // device
@@ -21,16 +30,13 @@ struct CountArgs {
     int32_t grab;              // items taken per counter increment
     int64_t total;             // item_pre[ntasks]
     unsigned long long *counts;  // device, indexed by TaskDesc::slot
-    unsigned long long *next;    // device, kQueueWords (zero before launch); queue q at q * kQueueStride
+    unsigned long long *next;    // device, kLaunchQueueWords (zero before launch); queue q of part r at
+                                 // r * kQueueWords + q * kQueueStride
     int32_t orient;              // kOrientRow or kOrientCol (which item lists)
-    int64_t qrun = 0;            // grab units per run dealt to one queue (0 = queue_run's choice)
     int32_t stage_lo = 0;        // items whose staged list has more than stage_lo
     int32_t stage_hi = INT32_MAX;  // and at most stage_hi entries
 };
 
-// Grab units per run dealt to one work queue: `requested` if positive, else
-// 1 (round-robin).
-int64_t queue_run(int64_t units, int64_t requested);
 int choose_lds_words(int32_t mode, int32_t max_stage_len, int32_t max_width_k);
 // Kernel template (staging kind) and LDS words per wave of a counting launch,
 // from the kernel option, the longest staged list and the widths of stripe k
@@ -61,8 +67,8 @@ int64_t task_items(const pgabb_graph *g, const Task &t, int orient);
 // Longest list a task stages (a row of A_jk for column walks, of A_ik for row
 // walks).
 int32_t staged_max(const pgabb_graph *g, const Task &t, int orient);
-// One launch per part (see LaunchKind); a.next is cleared again between
-// them by a fill kernel.
+// One launch per part (see LaunchKind), part r on the queue counters at
+// a.next + r * kQueueWords.
 void launch_tc_tasks(const CountArgs &a, const LaunchKind &lk, int waves, hipStream_t s, int grid_override,
                      int unroll);
 TaskDesc make_desc(const pgabb_graph *g, const int32_t *arena_base, const Task &t, int32_t slot,

@@ -2,6 +2,7 @@
 // and the task (block-list) table.
 #pragma once
 
+#include <array>
 #include <memory>
 #include <vector>
 
@@ -11,24 +12,32 @@ namespace pgabb {
 
 // One block A_ij of the p x p grid, stored as a chunk of int32 words holding
 // the block and its transpose:
-//   [ rptr   : width + 1    ]  dense row offsets over stripe i's row range,
-//                              relative to the start of `col`
 //   [ items  : 3 * nitems   ]  row work items (u, b, e): local row u and the
 //                              run [b, e) of at most kSplitV of its entries,
 //                              as offsets into `col`
+//   [ rptr   : width + 1    ]  dense row offsets over stripe i's row range,
+//                              relative to the start of `col`
 //   [ col    : nnz          ]  local column ids (rank - base of stripe j)
-//   [ cptr   : cwidth + 1   ]  dense column offsets over stripe j's range,
-//                              relative to the start of `crow`
 //   [ citems : 3 * ncitems  ]  column work items (v, b, e), as above per
 //                              column, offsets into `crow`
-//   [ crow   : nnz          ]  local row ids of each column's entries
+//   [ crow   : nnz          ]  local row ids of each column's entries, in
+//                              column order
 // Local ids are rank - base_s, where base_s is stripe s's first rank that
-// can own an edge (isolated vertices rank lowest and own none).  One chunk is
-// the unit of host<->device movement.  Items bound the work of one wave when
-// the block plays A_ij in a task (rows when the row of A_ik is staged,
-// columns when the row of A_jk is staged).
+// can own an edge (isolated vertices rank lowest and own none).  Items bound
+// the work of one wave when the block plays A_ij in a task (rows when the row
+// of A_ik is staged, columns when the row of A_jk is staged).  The chunk is
+// the unit of host<->device movement, and its order puts what each walk
+// reads in one range: a row walk reads items, rptr and col (the edge block's
+// row items and ids, the other blocks' rows); a column walk reads rptr, col,
+// citems and crow.  The transpose's column offsets are needed only while
+// the partition fills the chunk and are not kept.
 constexpr int32_t kSplitV = 32;
 constexpr int32_t kItemWords = 3;
+
+// Which list of a block-list edge (u, v) is staged in LDS: the row u of A_ik
+// (the edge block is walked by rows) or the row v of A_jk (walked by
+// columns).  Both count the same common entries.
+enum Orient : int { kOrientRow = 0, kOrientCol = 1 };
 
 struct BlockInfo {
     int32_t i = 0, j = 0;
@@ -42,12 +51,16 @@ struct BlockInfo {
     int64_t nnz = 0;
     int64_t chunk_off = 0;  // int32 words from the arena start
     int64_t chunk_len = 0;  // int32 words
-    int64_t off_items() const { return chunk_off + width + 1; }
-    int64_t off_col() const { return off_items() + kItemWords * static_cast<int64_t>(nitems); }
-    int64_t off_cptr() const { return off_col() + nnz; }
-    int64_t off_citems() const { return off_cptr() + cwidth + 1; }
+    int64_t off_items() const { return chunk_off; }
+    int64_t off_rptr() const { return off_items() + kItemWords * static_cast<int64_t>(nitems); }
+    int64_t off_col() const { return off_rptr() + width + 1; }
+    int64_t off_citems() const { return off_col() + nnz; }
     int64_t off_crow() const { return off_citems() + kItemWords * static_cast<int64_t>(ncitems); }
     int64_t end() const { return off_crow() + nnz; }
+    // The words of the chunk a walk reads: [walk_lo, walk_hi) (kOrientRow:
+    // items, rptr, col; kOrientCol: rptr, col, citems, crow).
+    int64_t walk_lo(int orient) const { return orient == kOrientCol ? off_rptr() : off_items(); }
+    int64_t walk_hi(int orient) const { return orient == kOrientCol ? end() : off_citems(); }
 };
 
 // Device view of one block.
@@ -55,7 +68,6 @@ struct BlockRef {
     const int32_t *rptr;
     const int32_t *items;
     const int32_t *col;
-    const int32_t *cptr;
     const int32_t *citems;
     const int32_t *crow;
     int32_t nitems;
@@ -75,11 +87,6 @@ struct TaskDesc {
     int32_t width_k;  // columns of stripe k
     int32_t slot;     // index of the task's counter
 };
-
-// Which list of a block-list edge (u, v) is staged in LDS: the row u of A_ik
-// (the edge block is walked by rows) or the row v of A_jk (walked by
-// columns).  Both count the same common entries.
-enum Orient : int { kOrientRow = 0, kOrientCol = 1 };
 
 }  // namespace pgabb
 
@@ -119,6 +126,8 @@ struct pgabb_graph {
     bool blocks_on_host = false;
     std::vector<pgabb::Task> tasks;
     std::vector<uint64_t> task_counts;
+    std::vector<std::array<int32_t, 4>> quads;  // block 4-lists of the last 4-clique count
+    std::vector<uint64_t> quad_counts;          // and their 4-cliques
 
     double t_build_ms = 0, t_partition_ms = 0, t_count_ms = 0, t_kernel_ms = 0;
     // events around the last partition; t_partition_ms is read from them
@@ -129,6 +138,7 @@ struct pgabb_graph {
     uint64_t h2d_bytes = 0;
     int64_t host_tasks = 0;        // tasks the host kernel counted in the last count
     double host_work_share = 0;    // their share of the tasks' estimated work
+    double t_tune_ms = 0;          // tuning time of the last autotuned count of several graphs
 };
 
 namespace pgabb {

@@ -52,9 +52,9 @@ uint64_t intersect_sorted(const int32_t *a, int64_t na, const int32_t *b, int64_
 
 uint64_t host_count_task(const pgabb_graph *g, const int32_t *arena, const Task &t) {
     const BlockInfo &ij = g->blocks[t.bij], &ik = g->blocks[t.bik], &jk = g->blocks[t.bjk];
-    const int32_t *ij_rptr = arena + ij.chunk_off, *ij_col = arena + ij.off_col();
-    const int32_t *ik_rptr = arena + ik.chunk_off, *ik_col = arena + ik.off_col();
-    const int32_t *jk_rptr = arena + jk.chunk_off, *jk_col = arena + jk.off_col();
+    const int32_t *ij_rptr = arena + ij.off_rptr(), *ij_col = arena + ij.off_col();
+    const int32_t *ik_rptr = arena + ik.off_rptr(), *ik_col = arena + ik.off_col();
+    const int32_t *jk_rptr = arena + jk.off_rptr(), *jk_col = arena + jk.off_col();
     // A_ij and A_ik share stripe i's dense row range (same width), so row u
     // of one is row u of the other; the local column v of A_ij is row v of
     // A_jk.

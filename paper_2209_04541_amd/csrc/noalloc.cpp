@@ -30,7 +30,7 @@ namespace pgabb {
 
 namespace {
 
-constexpr size_t kScratchBytes = size_t(8) << 20;
+constexpr size_t kScratchBytes = size_t(4) << 20;
 constexpr int kMaxDevices = 64;
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -70,7 +70,7 @@ size_t noalloc_scratch_bytes() { return kScratchBytes; }
 // per-task and work-queue counters, each region 256-byte aligned.
 size_t noalloc_need(int64_t T) {
     return round_up(sizeof(TaskDesc) * static_cast<size_t>(T)) + round_up(sizeof(int64_t) * static_cast<size_t>(T + 1)) +
-           round_up(sizeof(unsigned long long) * static_cast<size_t>(T + kQueueWords));
+           round_up(sizeof(unsigned long long) * static_cast<size_t>(T + kLaunchQueueWords));
 }
 
 uint64_t count_noalloc(pgabb_graph *g, const pgabb_tc_options &opt) {
@@ -121,7 +121,7 @@ uint64_t count_noalloc(pgabb_graph *g, const pgabb_tc_options &opt) {
         }
         PGABB_HIP(hipMemcpyAsync(dtd, td.data(), sizeof(TaskDesc) * T, hipMemcpyHostToDevice, s));
         PGABB_HIP(hipMemcpyAsync(dpre, pre.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
-        const int64_t ncnt = static_cast<int64_t>(T) + kQueueWords;
+        const int64_t ncnt = static_cast<int64_t>(T) + kLaunchQueueWords;
         k_zero_counts<<<static_cast<unsigned>(std::min<int64_t>((ncnt + 255) / 256, 1024)), 256, 0, s>>>(dcnt, ncnt);
         PGABB_HIP(hipGetLastError());
 
@@ -136,7 +136,6 @@ uint64_t count_noalloc(pgabb_graph *g, const pgabb_tc_options &opt) {
             static_cast<uint64_t>(static_cast<double>(walked_entries(g, orient)) * g->task_share);
         a.grab = opt.rows_per_grab > 0 ? opt.rows_per_grab : default_grab(pre[T], walked);
         a.orient = orient;
-        a.qrun = opt.queue_run;
         const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
         const int waves = opt.waves_per_block > 0 ? opt.waves_per_block : 4;
         launch_tc_tasks(a, lk, waves, s, 0, opt.unroll);

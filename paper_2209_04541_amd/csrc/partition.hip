@@ -423,7 +423,7 @@ __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ sc
                                                  const int64_t *__restrict__ slot_base_dense,
                                                  const int64_t *__restrict__ rptr_off,
                                                  const int32_t *__restrict__ width, int32_t nblk,
-                                                 int32_t *__restrict__ arena,
+                                                 int32_t *__restrict__ rbase,
                                                  uint32_t *__restrict__ flags) {
     extern __shared__ int64_t s_sb[];
     for (int q = threadIdx.x; q < nblk; q += B) s_sb[q] = slot_base_dense[q];
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(B) void k_fill_rptr(const uint32_t *__restrict__ sc
         const int32_t b = block_of_slot(q, s_sb, nblk);
         const int64_t r = q - s_sb[b];
         const uint32_t v = scanned[q] - scanned[s_sb[b]];
-        arena[rptr_off[b] + r] = static_cast<int32_t>(v);
+        rbase[rptr_off[b] + r] = static_cast<int32_t>(v);
         flags[q] = r < width[b] ? (scanned[q + 1] - scanned[q] + kSplitV - 1) / kSplitV : 0u;
     }
 }
@@ -442,7 +442,8 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
                                                   const int64_t *__restrict__ slot_base_dense,
                                                   const int64_t *__restrict__ items_off,
                                                   const int64_t *__restrict__ rptr_off,
-                                                  int32_t nblk, int32_t *__restrict__ arena) {
+                                                  int32_t nblk, const int32_t *__restrict__ rbase,
+                                                  int32_t *__restrict__ arena) {
     extern __shared__ int64_t s_sb[];
     for (int q = threadIdx.x; q < nblk; q += B) s_sb[q] = slot_base_dense[q];
     __syncthreads();
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(B) void k_fill_items(const uint32_t *__restrict__ f
         const uint32_t at = pos[q] - pos[s_sb[b]];
         // the row's entries [start, end) (its dense offsets, written by
         // k_fill_rptr), cut into runs of at most kSplitV
-        const int32_t start = arena[rptr_off[b] + r], end = arena[rptr_off[b] + r + 1];
+        const int32_t start = rbase[rptr_off[b] + r], end = rbase[rptr_off[b] + r + 1];
         int32_t *it = arena + items_off[b] + kItemWords * static_cast<int64_t>(at);
         for (uint32_t c = 0; c < f; ++c) {
             const int32_t rb = start + static_cast<int32_t>(c) * kSplitV;
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
                                                  const int32_t *__restrict__ blk_index,
                                                  const int64_t *__restrict__ rptr_off,
                                                  const int64_t *__restrict__ col_off,
+                                                 const int32_t *__restrict__ rbase,
                                                  int32_t *__restrict__ arena) {
     __shared__ int32_t s_c[kMaxP + 1];
     __shared__ int32_t s_base[kMaxP];
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
         flat_short_rows(row_off, col, n, s_c, p,
                         [&](int32_t x, int32_t si, int32_t j, int64_t e, int32_t y, int64_t lo) {
                             const int32_t b = blk_index[si * p + j];
-                            arena[col_off[b] + arena[rptr_off[b] + (x - s_base[si])] + (e - lo)] = y - s_base[j];
+                            arena[col_off[b] + rbase[rptr_off[b] + (x - s_base[si])] + (e - lo)] = y - s_base[j];
                         });
         return;
     }
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(B) void k_fill_cols(const int64_t *__restrict__ row
         const RowRun r = row_run(col, e0, e1, x, s_c, p);
         if (r.hi > r.lo) {
             const int32_t b = blk_index[r.si * p + r.j];
-            s_dst[w][lane] = col_off[b] + arena[rptr_off[b] + (x - s_base[r.si])] - r.lo;
+            s_dst[w][lane] = col_off[b] + rbase[rptr_off[b] + (x - s_base[r.si])] - r.lo;
         }
         wave_lds_sync();
         const int32_t j0 = r.j - lane;
@@ -693,6 +695,11 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
         }
         const int32_t nblk = static_cast<int32_t>(g->blocks.size());
         g->arena.reset(static_cast<size_t>(g->arena_words), s);
+        // the transposes' dense column offsets, needed only while the chunks
+        // are filled
+        std::vector<int64_t> coff(static_cast<size_t>(nblk) + 1, 0);
+        for (int32_t b = 0; b < nblk; ++b) coff[b + 1] = coff[b] + g->blocks[b].cwidth + 1;
+        DArray<int32_t> ctmp(static_cast<size_t>(std::max<int64_t>(coff[nblk], 1)), s);
 
         // Both passes run the same machinery: per-row run counts at dense
         // slots, one scan (row offsets), per-row item counts, one scan (item
@@ -725,7 +732,7 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
                 bidx[q] = b;
                 sb_dense[b] = nslots;
                 width[b] = rev ? bi.cwidth : bi.width;
-                rptr_off[b] = rev ? bi.off_cptr() : bi.chunk_off;
+                rptr_off[b] = rev ? coff[b] : bi.off_rptr();
                 items_off[b] = rev ? bi.off_citems() : bi.off_items();
                 col_off[b] = rev ? bi.off_crow() : bi.off_col();
                 nslots += static_cast<int64_t>(width[b]) + 1;
@@ -743,17 +750,18 @@ void partition_graph(pgabb_graph *g, int32_t p, int32_t cut_mode, const int32_t 
             PGABB_HIP(hipGetLastError());
             scan_exclusive_u32(slots.get(), slots.get(), nslots + 1, nullptr, s);
             const size_t lds = static_cast<size_t>(nblk) * sizeof(int64_t);
-            k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb, d_ro, d_w, nblk,
-                                                         g->arena.get(), flags.get());
+            int32_t *rbase = rev ? ctmp.get() : g->arena.get();
+            k_fill_rptr<<<cap_grid(nslots), B, lds, s>>>(slots.get(), nslots, d_sb, d_ro, d_w, nblk, rbase,
+                                                         flags.get());
             PGABB_HIP(hipGetLastError());
             PGABB_HIP(hipMemsetAsync(flags.get() + nslots, 0, sizeof(uint32_t), s));
             scan_exclusive_u32(flags.get(), slots.get(), nslots + 1, nullptr, s);  // slots now item positions
             k_fill_items<<<cap_grid(nslots), B, lds, s>>>(flags.get(), slots.get(), nslots, d_sb, d_io, d_ro,
-                                                          nblk, g->arena.get());
+                                                          nblk, rbase, g->arena.get());
             PGABB_HIP(hipGetLastError());
-            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co,
+            k_fill_cols<false><<<lgrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co, rbase,
                                                    g->arena.get());
-            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co,
+            k_fill_cols<true><<<kLongGrid, B, 0, s>>>(off, cl, n, ctp, lst, nl, d_bidx, d_ro, d_co, rbase,
                                                       g->arena.get());
             PGABB_HIP(hipGetLastError());
         }

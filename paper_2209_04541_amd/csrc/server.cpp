@@ -72,6 +72,10 @@ struct pgabb_server {
     int device = 0;
     Clock::time_point t0 = Clock::now();
     uint64_t launches = 0;
+    // counting launches' device time and the entries they walked and edges
+    // they covered (for the launches' roofline)
+    double kernel_ms = 0;
+    uint64_t walked = 0, edges = 0;
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
@@ -166,6 +170,7 @@ static void counter_loop(pgabb_server *s) {
     DArray<int64_t> dpre;
     DArray<unsigned long long> dcnt;
     PinnedArray<unsigned long long> hcnt;
+    StreamTimer ktimer;
     for (;;) {
         std::vector<Request *> batch;
         {
@@ -180,7 +185,7 @@ static void counter_loop(pgabb_server *s) {
         std::vector<int64_t> pre(1, 0);
         std::vector<Request *> live;
         int32_t max_out = 0, max_wk = 0, min_wk = INT32_MAX;
-        uint64_t walked = 0;
+        uint64_t walked = 0, edges = 0;
         for (Request *r : batch) {
             if (r->status != PGABB_OK || !r->g) {
                 finish(s, r);
@@ -190,6 +195,7 @@ static void counter_loop(pgabb_server *s) {
             live.push_back(r);
             pgabb_graph *g = r->g;
             walked += walked_entries(g, orient_of_option(s->opt, nullptr));
+            edges += static_cast<uint64_t>(g->m);
             for (const Task &t : g->tasks) {
                 td.push_back(make_desc(g, g->arena.get(), t, slot, nullptr));
                 pre.push_back(pre.back() + task_items(g, t, orient_of_option(s->opt, nullptr)));
@@ -207,8 +213,8 @@ static void counter_loop(pgabb_server *s) {
             hipStream_t cs = s->count_stream;
             const int32_t T = static_cast<int32_t>(td.size());
             const size_t L = live.size();
-            if (dcnt.size() < L + kQueueWords) {
-                dcnt.reset(std::max<size_t>(2 * L + kQueueWords, 64), cs);
+            if (dcnt.size() < L + kLaunchQueueWords) {
+                dcnt.reset(std::max<size_t>(2 * L + kLaunchQueueWords, 64), cs);
                 hcnt.reset(dcnt.size());
             }
             if (T > 0) {
@@ -222,7 +228,7 @@ static void counter_loop(pgabb_server *s) {
                 PGABB_HIP(hipMemcpyAsync(dtd.get(), htd.get(), htd.bytes(), hipMemcpyHostToDevice, cs));
                 PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, cs));
             }
-            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + kQueueWords), cs));
+            PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * (L + kLaunchQueueWords), cs));
             if (T > 0) {
                 CountArgs a;
                 a.tasks = dtd.get();
@@ -230,16 +236,24 @@ static void counter_loop(pgabb_server *s) {
                 a.ntasks = T;
                 a.grab = s->opt.rows_per_grab > 0 ? s->opt.rows_per_grab : default_grab(pre.back(), walked);
                 a.orient = orient_of_option(s->opt, nullptr);
-                a.qrun = s->opt.queue_run;
                 a.total = pre.back();
                 a.counts = dcnt.get();
                 a.next = dcnt.get() + L;
                 const LaunchKind lk = launch_kind(s->opt.kernel, max_out, max_wk, min_wk);
+                ktimer.start(cs);
                 launch_tc_tasks(a, lk, s->opt.waves_per_block > 0 ? s->opt.waves_per_block : 4, cs, 0,
                                 s->opt.unroll);
+                ktimer.stop(cs);
             }
             PGABB_HIP(hipMemcpyAsync(hcnt.get(), dcnt.get(), sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, cs));
             PGABB_HIP(hipStreamSynchronize(cs));
+            if (T > 0) {
+                const double kms = ktimer.ms();
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->kernel_ms += kms;
+                s->walked += walked;
+                s->edges += edges;
+            }
             for (size_t q = 0; q < L; ++q) live[q]->count = hcnt[q];
             ++s->launches;
         } catch (const Error &e) {
@@ -360,6 +374,16 @@ PGABB_API double pgabb_server_now(const pgabb_server *s) { return s ? s->now() :
 PGABB_API pgabb_status pgabb_server_stats(const pgabb_server *s, uint64_t *launches) {
     if (!s) return capture_status(Error{PGABB_EINVAL, "server is NULL"});
     if (launches) *launches = s->launches;
+    return capture_status(Error{PGABB_OK, ""});
+}
+
+PGABB_API pgabb_status pgabb_server_kernel_stats(pgabb_server *s, double *kernel_ms, uint64_t *walked,
+                                                 uint64_t *edges) {
+    if (!s) return capture_status(Error{PGABB_EINVAL, "server is NULL"});
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (kernel_ms) *kernel_ms = s->kernel_ms;
+    if (walked) *walked = s->walked;
+    if (edges) *edges = s->edges;
     return capture_status(Error{PGABB_OK, ""});
 }
 

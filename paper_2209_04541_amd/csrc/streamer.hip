@@ -21,6 +21,7 @@
 // different streams overlap, and the copies of later windows overlap earlier
 // launches.
 #include <algorithm>
+#include <chrono>
 #include <list>
 #include <map>
 #include <mutex>
@@ -75,8 +76,10 @@ class RangePool {
 
 constexpr uint64_t kAlign = 256;
 
-uint64_t chunk_bytes(const BlockInfo &b) {
-    const uint64_t raw = static_cast<uint64_t>(b.chunk_len) * sizeof(int32_t);
+// Bytes of the part of a block's chunk that a walk in `orient` reads (the
+// unit of copy and of pool space), rounded up to kAlign.
+uint64_t chunk_bytes(const BlockInfo &b, int orient) {
+    const uint64_t raw = static_cast<uint64_t>(b.walk_hi(orient) - b.walk_lo(orient)) * sizeof(int32_t);
     return (raw + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -103,7 +106,7 @@ static void move_blocks_to_host(pgabb_graph *g) {
 // times once the cache holds a small share of them; this order keeps the
 // tasks that share blocks together.  O(T^2) on the host, with per-task
 // missing bytes updated as blocks enter and leave.
-std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap) {
+std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap, int orient) {
     const int32_t T = static_cast<int32_t>(g->tasks.size());
     const int32_t nblk = static_cast<int32_t>(g->blocks.size());
     std::vector<std::vector<int32_t>> users(nblk);  // tasks reading each block (once each)
@@ -115,7 +118,7 @@ std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap) {
             const int32_t b = bs[q];
             if ((q >= 1 && b == bs[0]) || (q == 2 && b == bs[1])) continue;  // a block listed twice
             users[b].push_back(t);
-            miss[t] += chunk_bytes(g->blocks[b]);
+            miss[t] += chunk_bytes(g->blocks[b], orient);
         }
     }
     std::vector<char> done(T, 0), resident(nblk, 0);
@@ -124,16 +127,16 @@ std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap) {
     uint64_t used = 0;
     auto enter = [&](int32_t b) {
         resident[b] = 1;
-        used += chunk_bytes(g->blocks[b]);
+        used += chunk_bytes(g->blocks[b], orient);
         lru.push_back(b);
         pos[b] = std::prev(lru.end());
-        for (int32_t t : users[b]) miss[t] -= chunk_bytes(g->blocks[b]);
+        for (int32_t t : users[b]) miss[t] -= chunk_bytes(g->blocks[b], orient);
     };
     auto leave = [&](int32_t b) {
         resident[b] = 0;
-        used -= chunk_bytes(g->blocks[b]);
+        used -= chunk_bytes(g->blocks[b], orient);
         lru.erase(pos[b]);
-        for (int32_t t : users[b]) miss[t] += chunk_bytes(g->blocks[b]);
+        for (int32_t t : users[b]) miss[t] += chunk_bytes(g->blocks[b], orient);
     };
     std::vector<int32_t> order;
     order.reserve(T);
@@ -154,7 +157,7 @@ std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap) {
                 pos[b] = std::prev(lru.end());
                 continue;
             }
-            const uint64_t need = chunk_bytes(g->blocks[b]);
+            const uint64_t need = chunk_bytes(g->blocks[b], orient);
             auto it = lru.begin();
             while (used + need > cap && it != lru.end()) {
                 const int32_t v = *it++;
@@ -174,20 +177,22 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
 
     // bytes of the blocks these tasks read (all of them for a whole count;
     // fewer for one shard's tasks)
+    // the walk decides which part of each chunk is copied
+    const int orient = orient_of_option(opt, g);
     uint64_t total_bytes = 0;
     {
         std::vector<char> used(nblk, 0);
         for (const Task &t : g->tasks) used[t.bij] = used[t.bik] = used[t.bjk] = 1;
         for (int32_t b = 0; b < nblk; ++b)
-            if (used[b]) total_bytes += chunk_bytes(g->blocks[b]);
+            if (used[b]) total_bytes += chunk_bytes(g->blocks[b], orient);
     }
     uint64_t cap = opt.device_cap_bytes ? opt.device_cap_bytes : total_bytes;
     cap = std::min(cap, total_bytes);
     cap = cap / kAlign * kAlign;
     for (const Task &t : g->tasks) {
-        uint64_t need = chunk_bytes(g->blocks[t.bij]);
-        if (t.bik != t.bij) need += chunk_bytes(g->blocks[t.bik]);
-        if (t.bjk != t.bij && t.bjk != t.bik) need += chunk_bytes(g->blocks[t.bjk]);
+        uint64_t need = chunk_bytes(g->blocks[t.bij], orient);
+        if (t.bik != t.bij) need += chunk_bytes(g->blocks[t.bik], orient);
+        if (t.bjk != t.bij && t.bjk != t.bik) need += chunk_bytes(g->blocks[t.bjk], orient);
         PGABB_REQUIRE(need <= cap, PGABB_ENOMEM,
                       "device cap of %llu bytes cannot hold the %llu bytes of task (%d, %d, %d)",
                       static_cast<unsigned long long>(cap), static_cast<unsigned long long>(need),
@@ -205,7 +210,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     DArray<TaskDesc> ddesc(static_cast<size_t>(T), s);
     DArray<int64_t> dpre(static_cast<size_t>(2 * T + 1), s);
     // counts, then kQueues work counters per window (at most T windows)
-    const size_t ncnt = static_cast<size_t>(T) * (1 + kQueueWords);
+    const size_t ncnt = static_cast<size_t>(T) * (1 + kLaunchQueueWords);
     DArray<unsigned long long> dcnt(ncnt, s);
     PGABB_HIP(hipMemsetAsync(dcnt.get(), 0, sizeof(unsigned long long) * ncnt, s));
     PinnedArray<TaskDesc> hdesc;
@@ -229,7 +234,6 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         max_wk = std::max(max_wk, wk);
         min_wk = std::min(min_wk, wk);
     }
-    const int orient = orient_of_option(opt, g);
     int32_t max_st = 0;
     for (int32_t t = 0; t < T; ++t) max_st = std::max(max_st, staged_max(g, g->tasks[t], orient));
     const LaunchKind lk = launch_kind(opt.kernel, max_st, max_wk, min_wk);
@@ -251,7 +255,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     // under the cap, else the locality order above
     std::vector<int32_t> order(T);
     for (int32_t t = 0; t < T; ++t) order[t] = t;
-    if (total_bytes > cap) order = locality_order(g, cap);
+    if (total_bytes > cap) order = locality_order(g, cap, orient);
 
     uint64_t h2d = 0;
     int32_t next_task = 0;  // position in `order`: the device takes [0, next_task)
@@ -260,18 +264,33 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
 
     // ---- hybrid: the host takes positions [back, T) of `order`, one task
     // at a time from the end; with a fixed share it stops at host_stop (the
-    // device then stops there too), otherwise where the device has come to
+    // device then stops there too).  Otherwise the cut-off is measured: a
+    // host thread takes the next task only if, at the host's measured rate
+    // per thread, it would finish before the device, at its measured rate,
+    // finishes the work still in front of it.  Rates are estimated work
+    // (walked plus staged entries) per second: the device's from its
+    // completed windows, the host's from its completed tasks; until a first
+    // measurement, priors of kDevicePrior and kHostPrior.
+    constexpr double kDevicePrior = 2e11;  // entries/s, one MI355X in-core launch
+    constexpr double kHostPrior = 2e7;     // entries/s per host thread
     std::mutex qmu;
     int32_t back = T;
     int32_t host_stop = T;
     std::vector<uint64_t> host_cnt(T, 0);
     std::vector<std::thread> host;
     double host_work = 0, all_work = 0;
+    std::vector<double> est, wpre;             // estimated work by position, and its prefix
+    std::vector<int32_t> win_end;              // first position after each window
+    const auto t_begin = std::chrono::steady_clock::now();
+    double dev_done_work = 0, dev_done_s = 0;  // under qmu: completed windows' work and time
+    double host_done_work = 0, host_busy_s = 0;
     if (hybrid) {
-        std::vector<double> est(T);
+        est.assign(T, 0);
+        wpre.assign(static_cast<size_t>(T) + 1, 0);
         for (int32_t q = 0; q < T; ++q) {
             est[q] = static_cast<double>(task_work_estimate(g, g->tasks[order[q]], orient));
             all_work += est[q];
+            wpre[q + 1] = wpre[q] + est[q];
         }
         if (opt.host_permille > 0) {
             const double share = all_work * opt.host_permille / 1000.0;
@@ -292,13 +311,26 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                     {
                         std::lock_guard<std::mutex> lk(qmu);
                         if (back <= std::max(next_task, host_stop)) return;
+                        if (opt.host_permille == 0) {
+                            const double dev_rate = dev_done_s > 0 && dev_done_work > 0
+                                                        ? dev_done_work / dev_done_s : kDevicePrior;
+                            const double host_rate = host_busy_s > 0 && host_done_work > 0
+                                                         ? host_done_work / host_busy_s : kHostPrior;
+                            const double device_left = wpre[back - 1] - wpre[next_task];
+                            if (est[back - 1] / host_rate > device_left / dev_rate) return;
+                        }
                         pos = --back;
                     }
+                    const auto h0 = std::chrono::steady_clock::now();
                     const int32_t t = order[pos];
                     host_cnt[t] = host_count_task(g, harena, g->tasks[t]);
+                    const double dt =
+                        std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+                    std::lock_guard<std::mutex> lk(qmu);
+                    host_done_work += est[pos];
+                    host_busy_s += dt;
                 }
             });
-        (void)est;
     }
     auto stop_host = [&]() {
         {
@@ -319,7 +351,14 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         for (;;) {
             // in the hybrid mode at most one window per stream is in flight,
             // so the device claims tasks only as fast as it counts them
-            if (hybrid && win >= nstreams) PGABB_HIP(hipEventSynchronize(done[win - nstreams]));
+            if (hybrid && win >= nstreams) {
+                PGABB_HIP(hipEventSynchronize(done[win - nstreams]));
+                const double s_now =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+                std::lock_guard<std::mutex> lk(qmu);
+                dev_done_work = wpre[win_end[win - nstreams]];
+                dev_done_s = s_now;
+            }
             std::unique_lock<std::mutex> qlk(qmu);
             const int32_t limit = hybrid ? (opt.host_permille > 0 ? host_stop : back) : T;
             if (next_task >= limit) break;
@@ -339,8 +378,8 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                     for (int q = 0; q < ns; ++q) rep = rep || seen[q] == b;
                     if (rep) continue;
                     seen[ns++] = b;
-                    add += chunk_bytes(g->blocks[b]);
-                    if (where[b] == UINT64_MAX) add_new += chunk_bytes(g->blocks[b]);
+                    add += chunk_bytes(g->blocks[b], orient);
+                    if (where[b] == UINT64_MAX) add_new += chunk_bytes(g->blocks[b], orient);
                 }
                 if (!wtasks.empty() && (pinned_bytes + add > cap || new_bytes + add_new > window_new_bytes))
                     break;
@@ -366,7 +405,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                             touch(b);
                             continue;
                         }
-                        const uint64_t need = chunk_bytes(g->blocks[b]);
+                        const uint64_t need = chunk_bytes(g->blocks[b], orient);
                         uint64_t off = rp.alloc(need);
                         while (off == UINT64_MAX) {
                             auto it = lru.begin();
@@ -374,7 +413,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                             if (it == lru.end()) break;
                             const int32_t v = *it;
                             readers.release(v, [&](int32_t w) { PGABB_HIP(hipEventSynchronize(done[w])); });
-                            rp.release(where[v], chunk_bytes(g->blocks[v]));
+                            rp.release(where[v], chunk_bytes(g->blocks[v], orient));
                             where[v] = UINT64_MAX;
                             lru.erase(it);
                             off = rp.alloc(need);
@@ -384,7 +423,11 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                             break;
                         }
                         where[b] = off;
-                        chunk_dev[b] = static_cast<int64_t>(off / sizeof(int32_t));
+                        // the chunk's start, in words from the pool's start, as if the
+                        // whole chunk were there: only [walk_lo, walk_hi) is copied
+                        // and read
+                        chunk_dev[b] = static_cast<int64_t>(off / sizeof(int32_t)) -
+                                       (g->blocks[b].walk_lo(orient) - g->blocks[b].chunk_off);
                         lru.push_back(b);
                         lru_pos[b] = std::prev(lru.end());
                         loads.push_back(b);
@@ -404,8 +447,8 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                           static_cast<unsigned long long>(cap));
             for (int32_t b : loads) {
                 const BlockInfo &bi = g->blocks[b];
-                const size_t bytes = static_cast<size_t>(bi.chunk_len) * sizeof(int32_t);
-                PGABB_HIP(hipMemcpyAsync(pool.get() + where[b], g->host_arena.get() + bi.chunk_off, bytes,
+                const size_t bytes = static_cast<size_t>(bi.walk_hi(orient) - bi.walk_lo(orient)) * sizeof(int32_t);
+                PGABB_HIP(hipMemcpyAsync(pool.get() + where[b], g->host_arena.get() + bi.walk_lo(orient), bytes,
                                          hipMemcpyHostToDevice, copy_s));
                 h2d += bytes;
             }
@@ -450,10 +493,9 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             // a grab sized from the mean would be too coarse for them
             a.grab = grab_opt > 0 ? grab_opt : default_grab(items, 0);
             a.orient = orient;
-            a.qrun = opt.queue_run;
-            a.total = items;
+                a.total = items;
             a.counts = dcnt.get();
-            a.next = dcnt.get() + T + static_cast<size_t>(win) * kQueueWords;
+            a.next = dcnt.get() + T + static_cast<size_t>(win) * kLaunchQueueWords;
             PGABB_HIP(hipEventRecord(k0, st));
             launch_tc_tasks(a, lk, waves, st, 0, opt.unroll);
             PGABB_HIP(hipEventRecord(k1, st));
@@ -461,6 +503,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             for (int32_t ti : wtasks)
                 for (int32_t b : {g->tasks[ti].bij, g->tasks[ti].bik, g->tasks[ti].bjk}) readers.read(b, si, win);
             pre_at += W + 1;
+            if (hybrid) win_end.push_back(next_task);
             ++win;
         }
         for (auto &th : host) th.join();

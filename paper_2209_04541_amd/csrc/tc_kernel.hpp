@@ -41,13 +41,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
             unsigned long long c = 0;
             if (lane == 0) c = atomicAdd(&a.next[q * kQueueStride], 1ull);
             c = shfl_t(c, 0);
-            // round-robin over the queues, or runs of a.qrun consecutive
-            // units per queue when asked (queue_run)
-            int64_t unit = static_cast<int64_t>(c) * kQueues + q;
-            if (a.qrun > 1) {
-                const int64_t run = static_cast<int64_t>(c) / a.qrun;
-                unit = (run * kQueues + q) * a.qrun + (static_cast<int64_t>(c) - run * a.qrun);
-            }
+            const int64_t unit = static_cast<int64_t>(c) * kQueues + q;
             if (unit >= units) break;
             const int64_t g0 = unit * a.grab;
             const int64_t g1 = min(g0 + a.grab, a.total);  // g1 - g0 <= 64

@@ -95,6 +95,12 @@ void tune_store(const std::string &key, const std::vector<int> &val) {
     save_locked();
 }
 
+void tune_reload() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache.clear();
+    g_loaded = false;  // read the file again on next use
+}
+
 void tune_forget_all() {
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache.clear();

@@ -87,7 +87,7 @@ def test_noalloc_equals_count_ex_two_calls():
         assert tasks1 == oracle_tasks(*big, g1)
         assert tasks2 == oracle_tasks(*small, g2)
         assert want1 == oracle.tc(*big) and want2 == oracle.tc(*small)
-        assert P.lib().pgabb_tc_count_noalloc_scratch_bytes() == 8 << 20
+        assert P.lib().pgabb_tc_count_noalloc_scratch_bytes() == 4 << 20
         for rep in range(2):
             with CountingHook() as hook:
                 st1, c1 = noalloc(g1)
@@ -102,7 +102,7 @@ def test_noalloc_equals_count_ex_two_calls():
             assert c2 == want2 and t2 == tasks2
         # options as the regular count takes them, one after another
         for kw in (dict(kernel=P.KERNEL_HASH), dict(by_rows=True), dict(waves_per_block=8, rows_per_grab=3),
-                   dict(queue_run=1), dict(p=16)):
+                   dict(p=16)):
             st, c = noalloc(g1, P.options(**kw))
             assert st == P.OK and c == want1, kw
         # the allocating path does reach the hook (the hook works)
@@ -143,7 +143,7 @@ def test_noalloc_refusals():
         assert noalloc(g) == (P.OK, want)
         g.count(stream_blocks=True)  # blocks now in host memory
         assert noalloc(g)[0] == P.ESTATE
-    # more tasks than the 8 MiB array holds: K_300 at p = 64 has every block
+    # more tasks than the 4 MiB array holds: K_300 at p = 64 has every block
     # non-empty, so all C(66, 3) = 45,760 block-lists are tasks
     ks, kd = np.triu_indices(300, 1)
     with P.Graph(300, ks.astype(np.int32), kd.astype(np.int32)) as g:
