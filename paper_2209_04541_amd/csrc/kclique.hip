@@ -1,21 +1,28 @@
-// 4-cliques (the multi-block pattern family of PGAbB Section 3.2, one
-// intersection level past triangles).  Each 4-clique with ranks
-// a < b < c < d is counted once, at its oriented edge (a, b): c runs over
-// the common out-neighbours of a and b, and d over the entries after c that
-// N+(a), N+(b) and N+(c) share.  The oriented graph is taken as one block
-// (p = 1).
+// 4-cliques by block 4-lists (the multi-block pattern mode of PGAbB Section
+// 3.2, one intersection level past triangles).
 //
-// Rows of up to kCliqueCap entries: one wave owns a row a and stages N+(a)
-// in LDS.  For each b in it, the lanes look the entries of N+(b) up in the
-// staged row and mark the common ones, C, in a bitmask over its positions;
-// then they walk N+(c) for every c in C, flattened over the lanes, and count
-// the entries that land on a marked position after c.  Longer rows: one
-// thread per edge merges N+(a) (from b on) with N+(b) and, at every common
-// entry c, merges the three lists from c on.
+// Each 4-clique with ranks a < b < c < d lies in stripes i <= j <= k <= l and
+// is counted once, in the 4-list (A_ij, A_ik, A_il, A_jk, A_jl, A_kl), at its
+// edge (a, b) of A_ij: c runs over C = A_ik[a] & A_jk[b] (stripe k), d over
+// D = A_il[a] & A_jl[b] (stripe l), and the pair counts when (c, d) is an
+// entry of A_kl.  Every pair of stripes is ordered by rank and blocks keep
+// only edges from lower to higher rank, so d > c > b > a needs no test.
+//
+// One wave takes a work item of A_ij -- row a and a run of at most kSplitV
+// of its entries b (the block's own row items) -- and stages A_ik[a] and
+// A_il[a] in LDS (one list when k = l).  For each b its lanes look the
+// entries of A_jk[b] up in the staged A_ik[a] and mark C in a bitmask over
+// its positions, and those of A_jl[b] in A_il[a] for D; then they walk
+// A_kl[c] for every c in C, flattened over the lanes, and count the entries
+// that land on a marked position of A_il[a].  Items whose staged rows are
+// longer than the LDS region go to a kernel with one thread per (item, b)
+// and plain merges.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <vector>
 
 #include "common.hpp"
 #include "graph.hpp"
@@ -26,30 +33,27 @@ namespace pgabb {
 namespace {
 
 constexpr int kQB = 256;
-constexpr int kCliqueCap = 1024;  // longest row a wave stages
+constexpr int kCliqueCap = 1024;  // longest staged row
 constexpr int kCliqueWaves = 4;
-constexpr int kCliqueSpan = 8;  // b's of a row per work item
 
-// Work items per row: rows of 3 to kCliqueCap entries, kCliqueSpan b's each.
-__global__ __launch_bounds__(kQB) void k_clique_items(const int64_t *__restrict__ row_off, int32_t n,
-                                                       int64_t *__restrict__ items) {
-    for (int64_t a = blockIdx.x * static_cast<int64_t>(kQB) + threadIdx.x; a < n;
-         a += static_cast<int64_t>(gridDim.x) * kQB) {
-        const int64_t d = row_off[a + 1] - row_off[a];
-        items[a] = (d >= 3 && d <= kCliqueCap) ? (d - 2 + kCliqueSpan - 1) / kCliqueSpan : 0;
-    }
-}
-
-struct CliqueLds {
-    int32_t row[kCliqueCap];          // N+(a)
-    int32_t mem[kCliqueCap];          // positions of C in the row
-    uint32_t mask[kCliqueCap / 32];   // C as a bitmask over positions
-    int64_t incl[kWave];              // inclusive prefix of the chunk's list lengths
-    int64_t start[kWave];             // CSR start of each member's list
-    int32_t pos[kWave];               // row position of each member
+// Device view of one block 4-list.
+struct QuadDesc {
+    BlockRef ij, ik, il, jk, jl, kl;
+    int32_t slot;    // counter of the 4-list
+    int32_t same;    // k == l: A_il is A_ik and A_jl is A_jk
 };
 
-// First position in [lo, hi) of the staged row whose value is at least x.
+struct CliqueLds {
+    int32_t rk[kCliqueCap];              // A_ik[a]
+    int32_t rl[kCliqueCap];              // A_il[a] (unused when k = l)
+    int32_t mem[kCliqueCap];             // positions of C in A_ik[a]
+    uint32_t mk[kCliqueCap / 32];        // C as a bitmask over A_ik[a]
+    uint32_t ml[kCliqueCap / 32];        // D as a bitmask over A_il[a]
+    int64_t incl[kWave];                 // inclusive prefix of the chunk's list lengths
+    int64_t start[kWave];                // start of each member's list in A_kl's col
+};
+
+// First position in [lo, hi) of a sorted LDS list whose value is at least x.
 __device__ __forceinline__ int32_t lds_lower_bound(const int32_t *row, int32_t lo, int32_t hi, int32_t x) {
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
@@ -59,150 +63,217 @@ __device__ __forceinline__ int32_t lds_lower_bound(const int32_t *row, int32_t l
     return lo;
 }
 
-__global__ __launch_bounds__(kCliqueWaves *kWave) void k_four_cliques_rows(const int64_t *__restrict__ row_off,
-                                                                            const int32_t *__restrict__ col,
-                                                                            int32_t n,
-                                                                            const int64_t *__restrict__ item_pre,
-                                                                            unsigned long long *__restrict__ next,
-                                                                            unsigned long long *__restrict__ total) {
+// The 4-list holding item q: the last t with pre[t] <= q.
+__device__ __forceinline__ int32_t quad_of(gptr<int64_t> pre, int32_t nq, int64_t q) {
+    int32_t lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Staged items: one wave per item from a work counter.  Counts go to the
+// 4-lists' counters (a wave's count of one item, once).
+__global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDesc *__restrict__ quads,
+                                                                     const int64_t *__restrict__ item_pre,
+                                                                     int32_t nq,
+                                                                     unsigned long long *__restrict__ next,
+                                                                     unsigned long long *__restrict__ counts) {
     __shared__ CliqueLds s_lds[kCliqueWaves];
     CliqueLds &L = s_lds[threadIdx.x / kWave];
     const int lane = lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
-    gptr<int64_t> ro = as_global(row_off);
-    gptr<int32_t> cl = as_global(col);
-    gptr<int64_t> ip = as_global(item_pre);
-    const int64_t nitems = ip[n];
-    unsigned long long cnt = 0;
+    const gptr<int64_t> ip = as_global(item_pre);
+    const int64_t nitems = ip[nq];
     for (;;) {
         unsigned long long q0 = 0;
         if (lane == 0) q0 = atomicAdd(next, 1ull);
         q0 = shfl_t(q0, 0);
         if (q0 >= static_cast<unsigned long long>(nitems)) break;
         const int64_t q = static_cast<int64_t>(q0);
-        int32_t a = 0, ahi = n - 1;  // the row holding item q: the last with item_pre <= q
-        while (a < ahi) {
-            const int32_t mid = (a + ahi + 1) >> 1;
-            if (ip[mid] <= q) a = mid;
-            else ahi = mid - 1;
-        }
-        const int64_t a0 = ro[a];
-        const int32_t d = static_cast<int32_t>(ro[a + 1] - a0);
-        const int32_t i_lo = static_cast<int32_t>(q - ip[a]) * kCliqueSpan;
-        const int32_t i_hi = min(i_lo + kCliqueSpan, d - 2);
-        for (int x = lane; x < d; x += kWave) L.row[x] = cl[a0 + x];
+        const int32_t t = __builtin_amdgcn_readfirstlane(quad_of(ip, nq, q));
+        const QuadDesc &Q = quads[t];
+        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * (q - ip[t]);
+        const int32_t a = it[0], eb = it[1], ee = it[2];
+        const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
+        const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
+        const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
+        if (dk == 0 || dl == 0 || dk > kCliqueCap || dl > kCliqueCap) continue;  // none, or the long kernel's
+        const gptr<int32_t> ikc = as_global(Q.ik.col), ilc = as_global(Q.il.col);
+        for (int x = lane; x < dk; x += kWave) L.rk[x] = ikc[k0 + x];
+        if (!Q.same)
+            for (int x = lane; x < dl; x += kWave) L.rl[x] = ilc[l0 + x];
         wave_lds_sync();
-        const int32_t top = L.row[d - 1];
-        const int nwords = (d + 31) >> 5;
-        for (int32_t i = i_lo; i < i_hi; ++i) {
-            const int32_t b = L.row[i];
-            const int64_t b0 = ro[b];
-            const int64_t db = ro[b + 1] - b0;
-            if (db < 2) continue;
-            for (int w = lane; w < nwords; w += kWave) L.mask[w] = 0;
+        const int32_t *rl = Q.same ? L.rk : L.rl;
+        uint32_t *ml = Q.same ? L.mk : L.ml;
+        const int32_t topk = L.rk[dk - 1], topl = rl[dl - 1];
+        const int nwk = (dk + 31) >> 5, nwl = (dl + 31) >> 5;
+        const gptr<int32_t> ijc = as_global(Q.ij.col);
+        const gptr<int32_t> jkr = as_global(Q.jk.rptr), jkc = as_global(Q.jk.col);
+        const gptr<int32_t> jlr = as_global(Q.jl.rptr), jlc = as_global(Q.jl.col);
+        const gptr<int32_t> klr = as_global(Q.kl.rptr), klc = as_global(Q.kl.col);
+        unsigned long long cnt = 0;
+        for (int32_t e = eb; e < ee; ++e) {
+            const int32_t b = ijc[e];
+            const int32_t bk0 = jkr[b], dbk = jkr[b + 1] - bk0;
+            const int32_t bl0 = jlr[b], dbl = jlr[b + 1] - bl0;
+            if (dbk == 0 || dbl == 0) continue;
+            for (int w = lane; w < nwk; w += kWave) L.mk[w] = 0;
+            if (!Q.same)
+                for (int w = lane; w < nwl; w += kWave) L.ml[w] = 0;
             wave_lds_sync();
-            for (int64_t t = lane; t < db; t += kWave) {
-                const int32_t x = cl[b0 + t];
-                if (x > top) break;  // the list is sorted
-                const int32_t j = lds_lower_bound(L.row, i + 1, d, x);
-                if (j < d && L.row[j] == x) atomicOr(&L.mask[j >> 5], 1u << (j & 31));
+            for (int32_t x0 = 0; x0 < dbk; x0 += kWave) {  // C: A_jk[b] in A_ik[a]
+                const int32_t x = x0 + lane;
+                if (x < dbk) {
+                    const int32_t v = jkc[bk0 + x];
+                    if (v <= topk) {
+                        const int32_t j = lds_lower_bound(L.rk, 0, dk, v);
+                        if (j < dk && L.rk[j] == v) atomicOr(&L.mk[j >> 5], 1u << (j & 31));
+                    }
+                }
+            }
+            if (!Q.same) {
+                for (int32_t x0 = 0; x0 < dbl; x0 += kWave) {  // D: A_jl[b] in A_il[a]
+                    const int32_t x = x0 + lane;
+                    if (x < dbl) {
+                        const int32_t v = jlc[bl0 + x];
+                        if (v <= topl) {
+                            const int32_t j = lds_lower_bound(L.rl, 0, dl, v);
+                            if (j < dl && L.rl[j] == v) atomicOr(&L.ml[j >> 5], 1u << (j & 31));
+                        }
+                    }
+                }
             }
             wave_lds_sync();
-            int32_t nc = 0;  // members of C, listed in row order
-            for (int32_t j0 = i + 1; j0 < d; j0 += kWave) {
+            int32_t nc = 0;  // members of C, in row order
+            for (int32_t j0 = 0; j0 < dk; j0 += kWave) {
                 const int32_t j = j0 + lane;
-                const bool in = j < d && ((L.mask[j >> 5] >> (j & 31)) & 1u);
+                const bool in = j < dk && ((L.mk[j >> 5] >> (j & 31)) & 1u);
                 const uint64_t bal = __ballot(in);
                 if (in) L.mem[nc + __popcll(bal & below)] = j;
                 nc += __popcll(bal);
             }
             wave_lds_sync();
-            if (nc < 2) continue;
+            if (nc == 0) continue;
+            // walk A_kl[c] for c in C; an entry counts when it is in D
             for (int32_t m0 = 0; m0 < nc; m0 += kWave) {
-                const int32_t k = m0 + lane;
+                const int32_t mi = m0 + lane;
                 int64_t len = 0, st = 0;
-                int32_t pc = 0;
-                if (k < nc) {
-                    pc = L.mem[k];
-                    const int32_t c = L.row[pc];
-                    st = ro[c];
-                    len = ro[c + 1] - st;
+                if (mi < nc) {
+                    const int32_t c = L.rk[L.mem[mi]];
+                    st = klr[c];
+                    len = klr[c + 1] - st;
                 }
                 const int64_t incl = wave_inclusive_scan(len);
                 const int64_t tot = shfl_t(incl, kWave - 1);
                 wave_lds_sync();  // the previous chunk's lookups are done
                 L.incl[lane] = incl;
                 L.start[lane] = st;
-                L.pos[lane] = pc;
                 wave_lds_sync();
                 int lo = 0;
                 for (int64_t f = 0; f < tot; f += kWave) {
-                    const int64_t q = f + lane;
-                    if (q >= tot) continue;
-                    while (L.incl[lo] <= q) ++lo;  // lists hold q in order; q < tot = incl[63]
-                    const int32_t y = cl[L.start[lo] + (q - (lo ? L.incl[lo - 1] : 0))];
-                    if (y > top) continue;
-                    const int32_t j2 = lds_lower_bound(L.row, L.pos[lo] + 1, d, y);
-                    if (j2 < d && L.row[j2] == y && ((L.mask[j2 >> 5] >> (j2 & 31)) & 1u)) ++cnt;
+                    const int64_t g = f + lane;
+                    if (g >= tot) continue;
+                    while (L.incl[lo] <= g) ++lo;  // lists hold g in order; g < tot = incl[63]
+                    const int32_t y = klc[L.start[lo] + (g - (lo ? L.incl[lo - 1] : 0))];
+                    if (y > topl) continue;
+                    const int32_t j2 = lds_lower_bound(rl, 0, dl, y);
+                    if (j2 < dl && rl[j2] == y && ((ml[j2 >> 5] >> (j2 & 31)) & 1u)) ++cnt;
                 }
             }
-            wave_lds_sync();  // before the next b clears the mask
+            wave_lds_sync();  // before the next b clears the masks
         }
-        wave_lds_sync();  // before the next row is staged
+        cnt = wave_sum(cnt);
+        if (lane == 0 && cnt) atomicAdd(&counts[Q.slot], cnt);
+        wave_lds_sync();  // before the next item is staged
     }
-    cnt = wave_sum(cnt);
-    if (lane == 0 && cnt) atomicAdd(total, cnt);
 }
 
-__global__ __launch_bounds__(kQB) void k_four_cliques(const int64_t *__restrict__ row_off,
-                                                       const int32_t *__restrict__ col, int32_t n, int64_t m,
-                                                       unsigned long long *__restrict__ total) {
-    gptr<int64_t> ro = as_global(row_off);
-    gptr<int32_t> cl = as_global(col);
-    unsigned long long cnt = 0;
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(kQB) + threadIdx.x; e < m;
-         e += static_cast<int64_t>(gridDim.x) * kQB) {
-        int32_t lo = 0, hi = n - 1;  // row a of e: the last row whose offset is at most e
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (ro[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        if (ro[lo + 1] - ro[lo] <= kCliqueCap) continue;  // the row waves take it
-        const int32_t b = cl[e];
-        const int64_t ea = ro[lo + 1], eb = ro[b + 1];
-        int64_t i = e + 1, j = ro[b];
-        while (i < ea && j < eb) {
-            const int32_t x = cl[i], y = cl[j];
-            if (x < y) {
-                ++i;
-            } else if (y < x) {
-                ++j;
-            } else {  // c = x: count the entries after c common to N+(a), N+(b), N+(c)
-                int64_t p = ro[x];
-                const int64_t pe = ro[x + 1];
-                int64_t u = i + 1, v = j + 1;
-                while (p < pe && u < ea && v < eb) {
-                    const int32_t X = cl[p], Y = cl[u], Z = cl[v];
-                    const int32_t M = max(X, max(Y, Z));
-                    if (X == M && Y == M && Z == M) {
-                        ++cnt;
-                        ++p;
-                        ++u;
-                        ++v;
-                    } else {
-                        p += X < M;
-                        u += Y < M;
-                        v += Z < M;
-                    }
-                }
-                ++i;
-                ++j;
-            }
+// First position of the sorted list x[0, n) whose value exceeds v.
+__device__ __forceinline__ int32_t upper_pos(gptr<int32_t> x, int32_t n, int32_t v) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (x[mid] <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The common entries of three sorted lists.
+__device__ __forceinline__ unsigned long long three_way(gptr<int32_t> x, int32_t nx, gptr<int32_t> y, int32_t ny,
+                                                        gptr<int32_t> z, int32_t nz) {
+    unsigned long long c = 0;
+    int32_t p = 0, u = 0, v = 0;
+    while (p < nx && u < ny && v < nz) {
+        const int32_t X = x[p], Y = y[u], Z = z[v];
+        const int32_t M = max(X, max(Y, Z));
+        if (X == M && Y == M && Z == M) {
+            ++c;
+            ++p;
+            ++u;
+            ++v;
+        } else {
+            p += X < M;
+            u += Y < M;
+            v += Z < M;
         }
     }
-    cnt = wave_sum(cnt);
-    if (lane_id() == 0 && cnt) atomicAdd(total, cnt);
+    return c;
+}
+
+// Items whose staged rows exceed the LDS region: one thread per (item, b).
+__global__ __launch_bounds__(kQB) void k_quad_long(const QuadDesc *__restrict__ quads,
+                                                    const int64_t *__restrict__ item_pre, int32_t nq,
+                                                    unsigned long long *__restrict__ counts) {
+    const gptr<int64_t> ip = as_global(item_pre);
+    const int64_t nitems = ip[nq];
+    for (int64_t g = blockIdx.x * int64_t(kQB) + threadIdx.x; g < nitems * kSplitV; g += int64_t(gridDim.x) * kQB) {
+        const int64_t q = g / kSplitV;
+        const int32_t r = static_cast<int32_t>(g - q * kSplitV);
+        const int32_t t = quad_of(ip, nq, q);
+        const QuadDesc &Q = quads[t];
+        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * (q - ip[t]);
+        const int32_t a = it[0], e = it[1] + r;
+        if (e >= it[2]) continue;
+        const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
+        const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
+        const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
+        if (dk == 0 || dl == 0 || (dk <= kCliqueCap && dl <= kCliqueCap)) continue;  // the staged kernel's
+        const int32_t b = as_global(Q.ij.col)[e];
+        const gptr<int32_t> jkr = as_global(Q.jk.rptr), jlr = as_global(Q.jl.rptr), klr = as_global(Q.kl.rptr);
+        const gptr<int32_t> ak = as_global(Q.ik.col) + k0, al = as_global(Q.il.col) + l0;
+        const gptr<int32_t> bk = as_global(Q.jk.col) + jkr[b], bl = as_global(Q.jl.col) + jlr[b];
+        const int32_t dbk = jkr[b + 1] - jkr[b], dbl = jlr[b + 1] - jlr[b];
+        unsigned long long c = 0;
+        // entries of A_ik[a] up to the first of A_jk[b] cannot be common
+        int32_t x = dbk ? upper_pos(ak, dk, bk[0] - 1) : dk, y = 0;
+        while (x < dk && y < dbk) {
+            if (ak[x] < bk[y]) {
+                ++x;
+            } else if (bk[y] < ak[x]) {
+                ++y;
+            } else {  // c in C: entries of A_kl[c] also in A_il[a] and A_jl[b]
+                const int32_t cv = ak[x];
+                // with k = l, d > c: the merges of A_il[a] and A_jl[b] start
+                // after c (A_kl[c] holds only entries above c)
+                const int32_t ul = Q.same ? x + 1 : 0;
+                const int32_t vl = Q.same ? y + 1 : 0;
+                c += three_way(as_global(Q.kl.col) + klr[cv], klr[cv + 1] - klr[cv], al + ul, dl - ul, bl + vl,
+                               dbl - vl);
+                ++x;
+                ++y;
+            }
+        }
+        if (c) atomicAdd(&counts[Q.slot], c);
+    }
+}
+
+__global__ void k_zero_u64q(unsigned long long *p, int64_t n) {
+    for (int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; q < n; q += int64_t(gridDim.x) * blockDim.x)
+        p[q] = 0ull;
 }
 
 }  // namespace
@@ -210,34 +281,99 @@ __global__ __launch_bounds__(kQB) void k_four_cliques(const int64_t *__restrict_
 uint64_t four_cliques(pgabb_graph *g) {
     hipStream_t s = g->stream;
     const auto t0 = std::chrono::steady_clock::now();
-    const int64_t m = g->m;
-    uint64_t result = 0;
+    if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
+    PGABB_REQUIRE(!g->blocks_on_host, PGABB_ESTATE,
+                  "the graph's blocks are held in host memory (streamed); the 4-clique count needs them in "
+                  "device memory: partition the graph again");
     g->t_kernel_ms = 0;
     g->kernel_launches = 0;
-    if (m > 0) {
-        DArray<unsigned long long> tot(2, s);  // count, item counter
-        PGABB_HIP(hipMemsetAsync(tot.get(), 0, 2 * sizeof(unsigned long long), s));
-        const unsigned grid = std::min<unsigned>(grid_for(m, kQB), 256u * 16u);
-        // work items of the staged rows: kCliqueSpan b's of one row each
-        DArray<int64_t> item_pre(static_cast<size_t>(g->n) + 1, s);
-        k_clique_items<<<grid_for(g->n, kQB), kQB, 0, s>>>(g->row_off.get(), g->n, item_pre.get());
+    g->quads.clear();
+    g->quad_counts.clear();
+    const int32_t p = g->p;
+    // ---- the 4-lists: i <= j <= k <= l with six non-empty blocks, heaviest
+    // first (edges of the list's blocks)
+    auto blk = [&](int32_t x, int32_t y) { return g->block_of[static_cast<size_t>(x) * p + y]; };
+    std::vector<std::pair<int64_t, std::array<int32_t, 4>>> lists;
+    for (int32_t i = 0; i < p; ++i)
+        for (int32_t j = i; j < p; ++j) {
+            if (blk(i, j) < 0) continue;
+            for (int32_t k = j; k < p; ++k) {
+                if (blk(i, k) < 0 || blk(j, k) < 0) continue;
+                for (int32_t l = k; l < p; ++l) {
+                    const int32_t b6[6] = {blk(i, j), blk(i, k), blk(i, l), blk(j, k), blk(j, l), blk(k, l)};
+                    bool ok = true;
+                    int64_t w = 0;
+                    for (int32_t b : b6) {
+                        ok = ok && b >= 0;
+                        if (b >= 0) w += g->blocks[b].nnz;
+                    }
+                    if (ok) lists.push_back({w, {i, j, k, l}});
+                }
+            }
+        }
+    std::stable_sort(lists.begin(), lists.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    const int32_t NQ = static_cast<int32_t>(lists.size());
+    uint64_t result = 0;
+    if (NQ > 0) {
+        const int32_t *arena = g->arena.get();
+        auto ref = [&](int32_t b) {
+            const BlockInfo &bi = g->blocks[b];
+            BlockRef r;
+            r.rptr = arena + bi.off_rptr();
+            r.items = arena + bi.off_items();
+            r.col = arena + bi.off_col();
+            r.citems = arena + bi.off_citems();
+            r.crow = arena + bi.off_crow();
+            r.nitems = bi.nitems;
+            r.ncitems = bi.ncitems;
+            return r;
+        };
+        Staged<QuadDesc> hq(NQ, s);
+        Staged<int64_t> hpre(static_cast<size_t>(NQ) + 1, s);
+        hpre[0] = 0;
+        for (int32_t q = 0; q < NQ; ++q) {
+            const auto &L = lists[q].second;
+            QuadDesc &d = hq[q];
+            d.ij = ref(blk(L[0], L[1]));
+            d.ik = ref(blk(L[0], L[2]));
+            d.il = ref(blk(L[0], L[3]));
+            d.jk = ref(blk(L[1], L[2]));
+            d.jl = ref(blk(L[1], L[3]));
+            d.kl = ref(blk(L[2], L[3]));
+            d.slot = q;
+            d.same = L[2] == L[3];
+            hpre[q + 1] = hpre[q] + g->blocks[blk(L[0], L[1])].nitems;
+            g->quads.push_back(L);
+        }
+        DArray<QuadDesc> dq(NQ, s);
+        DArray<int64_t> dpre(static_cast<size_t>(NQ) + 1, s);
+        DArray<unsigned long long> dcnt(static_cast<size_t>(NQ) + 1, s);  // counts, then the work counter
+        PGABB_HIP(hipMemcpyAsync(dq.get(), hq.get(), hq.bytes(), hipMemcpyHostToDevice, s));
+        PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, s));
+        k_zero_u64q<<<std::min<unsigned>(grid_for(NQ + 1, 256), 1024u), 256, 0, s>>>(dcnt.get(), NQ + 1);
         PGABB_HIP(hipGetLastError());
-        scan_exclusive_i64(item_pre.get(), item_pre.get(), g->n, item_pre.get() + g->n, s);
-        const int rgrid = 256 * 4;
+        const int64_t nitems = hpre[NQ];
+        int32_t max_row = 0;
+        for (const auto &b : g->blocks) max_row = std::max(max_row, b.max_row);
+        const bool long_rows = max_row > kCliqueCap;
         StreamTimer tm;
         tm.start(s);
-        k_four_cliques_rows<<<rgrid, kCliqueWaves * kWave, 0, s>>>(g->row_off.get(), g->col.get(), g->n,
-                                                                    item_pre.get(), tot.get() + 1, tot.get());
-        if (g->max_out > kCliqueCap)
-            k_four_cliques<<<grid, kQB, 0, s>>>(g->row_off.get(), g->col.get(), g->n, m, tot.get());
-        PGABB_HIP(hipGetLastError());
+        if (nitems > 0) {
+            const unsigned grid = static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
+            k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), NQ, dcnt.get() + NQ, dcnt.get());
+            if (long_rows)
+                k_quad_long<<<std::min<unsigned>(grid_for(nitems * kSplitV, kQB), 256u * 16u), kQB, 0, s>>>(
+                    dq.get(), dpre.get(), NQ, dcnt.get());
+            PGABB_HIP(hipGetLastError());
+        }
         tm.stop(s);
-        Staged<unsigned long long> h(1, s);
-        PGABB_HIP(hipMemcpyAsync(h.get(), tot.get(), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        Staged<unsigned long long> h(NQ, s);
+        PGABB_HIP(hipMemcpyAsync(h.get(), dcnt.get(), h.bytes(), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
-        result = h[0];
+        g->quad_counts.assign(h.get(), h.get() + NQ);
+        for (int32_t q = 0; q < NQ; ++q) result += h[q];
         g->t_kernel_ms = tm.ms();
-        g->kernel_launches = g->max_out > kCliqueCap ? 2 : 1;
+        g->kernel_launches = nitems > 0 ? (long_rows ? 2 : 1) : 0;
     }
     g->t_count_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return result;

@@ -1,5 +1,6 @@
 """GPU parity of the 4-clique count against the CPU oracle, through the C
 ABI: exact equality."""
+import itertools
 import math
 import sys
 
@@ -81,3 +82,83 @@ def test_rows_longer_than_the_lds_region():
 def test_empty():
     for n in (0, 3):
         assert gpu_four(n, np.zeros(0, np.int32), np.zeros(0, np.int32))[0] == 0
+
+
+def check_lists(n, s, d, p, cut_mode=P.CUT_NNZ, want=None):
+    """Count over a p x p partition; every 4-list's count against the
+    oracle's per-stripe counts under the same cuts (or want(rank, cuts))."""
+    with P.Graph(n, s, d) as g:
+        g.partition(p, cut_mode=cut_mode)
+        got = g.four_cliques()
+        ijkl, cnt = g.four_clique_lists()
+        row_off, col, rank = g.export_csr()
+        cuts = g.cuts()
+        Q = oracle.four_clique_blocks(n, row_off, col, cuts) if want is None else want(rank, cuts)
+        info = g.info()
+    assert got == int(Q.sum())
+    seen = np.zeros_like(Q)
+    for (i, j, k, l), c in zip(ijkl, cnt):
+        assert i <= j <= k <= l
+        assert c == Q[i, j, k, l], (i, j, k, l)
+        seen[i, j, k, l] = 1
+    # a 4-list left out (one of its six blocks empty) holds no 4-clique
+    assert int(Q[seen == 0].sum()) == 0
+    return got, info
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 8])
+def test_block_lists_rmat(p):
+    n, s, d = gen.rmat(13, 16, gen.seed(67, p))
+    got, info = check_lists(n, s, d, p)
+    say("4-lists rmat13 p", p, got, info["t_kernel_ms"])
+    assert got == oracle.four_cliques(n, s, d)
+
+
+@pytest.mark.parametrize("p", [2, 7])
+def test_block_lists_uniform_cuts_and_closed_forms(p):
+    n, s, d = gen.rgg(6000, 24.0, gen.seed(67, 20 + p))
+    check_lists(n, s, d, p, cut_mode=P.CUT_UNIFORM)
+    for (g, _), want in ((graphs.complete(40), math.comb(40, 4)), (graphs.cocktail_party(9), 16 * math.comb(9, 4)),
+                         (graphs.complete_tripartite(5, 6, 7), 0)):
+        got, _ = check_lists(*graphs.messy(*g, seed=p), p)
+        assert got == want
+
+
+@pytest.mark.parametrize("p", [1, 4])
+def test_block_lists_long_rows(p):
+    """K_1100 plus a pendant K_30: at p = 1 the rows of K_1100 exceed the
+    LDS region and take the merge kernel; at p = 4 they are cut into
+    stripes."""
+    a, b = np.triu_indices(1100, 1)
+    c, e = np.triu_indices(30, 1)
+    s = np.concatenate([a, c + 1100, [0, 7]]).astype(np.int32)
+    d = np.concatenate([b, e + 1100, [1100, 1101]]).astype(np.int32)
+
+    def closed_form(rank, cuts):
+        # a 4-list's count: for each clique, the product over its stripes of
+        # C(members in the stripe, multiplicity) (the two pendant edges close
+        # no 4-clique)
+        pp = len(cuts) - 1
+        st = np.searchsorted(cuts, rank, side="right") - 1
+        sizes = [np.bincount(st[:1100], minlength=pp), np.bincount(st[1100:], minlength=pp)]
+        Q = np.zeros((pp,) * 4, np.uint64)
+        for q in itertools.combinations_with_replacement(range(pp), 4):
+            mult = np.bincount(q, minlength=pp)
+            Q[q] = sum(math.prod(math.comb(int(sz[t]), int(mult[t])) for t in range(pp)) for sz in sizes)
+        return Q
+
+    got, info = check_lists(1130, s, d, p, want=closed_form)
+    say("4-lists K_1100 p", p, got, info["t_kernel_ms"], info["kernel_launches"])
+    assert got == math.comb(1100, 4) + math.comb(30, 4)
+    if p == 1:
+        assert info["kernel_launches"] == 2
+
+
+def test_block_lists_streamed_graph_is_refused():
+    n, s, d = gen.rmat(10, 8, gen.seed(68, 0))
+    with P.Graph(n, s, d) as g:
+        g.partition(3)
+        g.count(stream_blocks=True)
+        with pytest.raises(P.PgabbError) as ei:
+            g.four_cliques()
+        assert ei.value.status == P.ESTATE
