@@ -31,6 +31,10 @@ KERNEL_SOURCES = ["paper_2209_04541_amd/csrc/tc_device.hpp", "paper_2209_04541_a
                   "paper_2209_04541_amd/csrc/wave.hpp", "paper_2209_04541_amd/csrc/count.hpp"]
 
 
+# device code of the batch kernel
+BATCH_SOURCES = ["paper_2209_04541_amd/csrc/batch.hip", "paper_2209_04541_amd/csrc/tc_device.hpp",
+                 "paper_2209_04541_amd/csrc/wave.hpp"]
+
 # device code of the edge-support kernel
 SUPPORT_SOURCES = ["paper_2209_04541_amd/csrc/support.hip", "paper_2209_04541_amd/csrc/wave.hpp"]
 
@@ -421,9 +425,14 @@ def bench_support(args):
         inf = g.info()
         truss[str(k)] = {"edges": left, "rounds": rounds, "t_ms": inf["t_count_ms"],
                          "t_support_kernels_ms": inf["t_kernel_ms"]}
-    c4 = g.four_cliques()
+    c4 = g.four_cliques()  # one block (p = 1)
     inf = g.info()
     cliques = {"four_cliques": c4, "t_ms": inf["t_count_ms"], "t_kernel_ms": inf["t_kernel_ms"]}
+    g.partition(8)  # block 4-lists of the 8 x 8 grid
+    c4_8 = g.four_cliques()
+    inf = g.info()
+    cliques["p8"] = {"four_cliques": c4_8, "t_ms": inf["t_count_ms"], "t_kernel_ms": inf["t_kernel_ms"],
+                     "four_lists": len(g.four_clique_lists()[0])}
     g.close()
     m = info["m"]
     T = tri
@@ -459,7 +468,7 @@ def bench_support(args):
         "ktruss": truss,
         "cliques": cliques,
     })
-    out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T
+    out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T and c4 == c4_8
     if not args.no_cpu_baseline:
         import oracle
         t1 = time.perf_counter()
@@ -595,7 +604,8 @@ def bench_batch(args):
     alg = 4 * st["walked"] + 16 * st["active_edges"] + 16 * st["active_rows"]
     achieved = alg / (ms / 1e3) / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": measured_traffic("traffic_tc_batch_10k.json", BATCH_SOURCES)}
     out.update({"algorithmic_bytes_per_launch": alg, "walked_entries": st["walked"],
                 "edges": st["edges"], "active_rows": st["active_rows"]})
     # parity: every graph's count against the oracle's stored count

@@ -8,8 +8,8 @@
 // entry of A_kl.  Every pair of stripes is ordered by rank and blocks keep
 // only edges from lower to higher rank, so d > c > b > a needs no test.
 //
-// One wave takes a work item of A_ij -- row a and a run of at most kSplitV
-// of its entries b (the block's own row items) -- and stages A_ik[a] and
+// One wave takes a work item of A_ij -- row a and a run of at most 8 of its
+// entries b (a part of one of the block's own row items) -- and stages A_ik[a] and
 // A_il[a] in LDS (one list when k = l).  For each b its lanes look the
 // entries of A_jk[b] up in the staged A_ik[a] and mark C in a bitmask over
 // its positions, and those of A_jl[b] in A_il[a] for D; then they walk
@@ -35,6 +35,11 @@ namespace {
 constexpr int kQB = 256;
 constexpr int kCliqueCap = 1024;  // longest staged row
 constexpr int kCliqueWaves = 4;
+// A wave's work item is a run of at most kQuadSpan entries b of one of
+// A_ij's row items (each row item is cut into kSplitV / kQuadSpan parts):
+// rows of high-degree vertices then spread over several waves.
+constexpr int kQuadSpan = 8;
+constexpr int kQuadParts = kSplitV / kQuadSpan;
 
 // Device view of one block 4-list.
 struct QuadDesc {
@@ -95,8 +100,12 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDe
         const int64_t q = static_cast<int64_t>(q0);
         const int32_t t = __builtin_amdgcn_readfirstlane(quad_of(ip, nq, q));
         const QuadDesc &Q = quads[t];
-        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * (q - ip[t]);
-        const int32_t a = it[0], eb = it[1], ee = it[2];
+        const int64_t r = (q - ip[t]) / kQuadParts;  // row item, and its part
+        const int32_t part = static_cast<int32_t>((q - ip[t]) - r * kQuadParts);
+        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * r;
+        const int32_t a = it[0];
+        const int32_t eb = it[1] + part * kQuadSpan, ee = min(eb + kQuadSpan, it[2]);
+        if (eb >= ee) continue;
         const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
         const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
         const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
@@ -230,14 +239,17 @@ __global__ __launch_bounds__(kQB) void k_quad_long(const QuadDesc *__restrict__ 
                                                     unsigned long long *__restrict__ counts) {
     const gptr<int64_t> ip = as_global(item_pre);
     const int64_t nitems = ip[nq];
-    for (int64_t g = blockIdx.x * int64_t(kQB) + threadIdx.x; g < nitems * kSplitV; g += int64_t(gridDim.x) * kQB) {
-        const int64_t q = g / kSplitV;
-        const int32_t r = static_cast<int32_t>(g - q * kSplitV);
+    for (int64_t g = blockIdx.x * int64_t(kQB) + threadIdx.x; g < nitems * kQuadSpan;
+         g += int64_t(gridDim.x) * kQB) {
+        const int64_t q = g / kQuadSpan;  // work item (a part of a row item), and its b
+        const int32_t rb = static_cast<int32_t>(g - q * kQuadSpan);
         const int32_t t = quad_of(ip, nq, q);
         const QuadDesc &Q = quads[t];
-        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * (q - ip[t]);
-        const int32_t a = it[0], e = it[1] + r;
-        if (e >= it[2]) continue;
+        const int64_t r = (q - ip[t]) / kQuadParts;
+        const int32_t part = static_cast<int32_t>((q - ip[t]) - r * kQuadParts);
+        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * r;
+        const int32_t a = it[0], e = it[1] + part * kQuadSpan + rb;
+        if (e >= it[2] || rb + part * kQuadSpan >= kSplitV) continue;
         const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
         const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
         const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
@@ -342,7 +354,7 @@ uint64_t four_cliques(pgabb_graph *g) {
             d.kl = ref(blk(L[2], L[3]));
             d.slot = q;
             d.same = L[2] == L[3];
-            hpre[q + 1] = hpre[q] + g->blocks[blk(L[0], L[1])].nitems;
+            hpre[q + 1] = hpre[q] + static_cast<int64_t>(kQuadParts) * g->blocks[blk(L[0], L[1])].nitems;
             g->quads.push_back(L);
         }
         DArray<QuadDesc> dq(NQ, s);
@@ -362,7 +374,7 @@ uint64_t four_cliques(pgabb_graph *g) {
             const unsigned grid = static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
             k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), NQ, dcnt.get() + NQ, dcnt.get());
             if (long_rows)
-                k_quad_long<<<std::min<unsigned>(grid_for(nitems * kSplitV, kQB), 256u * 16u), kQB, 0, s>>>(
+                k_quad_long<<<std::min<unsigned>(grid_for(nitems * kQuadSpan, kQB), 256u * 16u), kQB, 0, s>>>(
                     dq.get(), dpre.get(), NQ, dcnt.get());
             PGABB_HIP(hipGetLastError());
         }
