@@ -9,14 +9,18 @@
 // only edges from lower to higher rank, so d > c > b > a needs no test.
 //
 // One wave takes a work item of A_ij -- row a and a run of at most 8 of its
-// entries b (a part of one of the block's own row items) -- and stages A_ik[a] and
-// A_il[a] in LDS (one list when k = l).  For each b its lanes look the
-// entries of A_jk[b] up in the staged A_ik[a] and mark C in a bitmask over
-// its positions, and those of A_jl[b] in A_il[a] for D; then they walk
-// A_kl[c] for every c in C, flattened over the lanes, and count the entries
-// that land on a marked position of A_il[a].  Items whose staged rows are
-// longer than the LDS region go to a kernel with one thread per (item, b)
-// and plain merges.
+// entries b (a part of one of the block's own row items) -- and stages
+// A_ik[a] and A_il[a] (one list when k = l) in an open-addressing hash table
+// in LDS.  For each b its lanes look the entries of A_jk[b] and A_jl[b] up in
+// the table and mark the ones found (C and D) by setting the stored key's top
+// bit; then, for the marked keys of stripe k (C), they walk A_kl[c]
+// flattened over the lanes and count the entries whose key is marked (in D),
+// and finally clear the marks.  Blocks hold column ids local to their stripe,
+// so when k < l the ids of stripe l enter the table shifted by the width of
+// stripe k: keys of A_ik[a] lie below that width and keys of A_il[a] above
+// it, and an entry of A_kl[c] (stripe l, shifted too) can only match a key
+// of A_il[a].  Items whose staged rows hold more than kStageCap entries go to
+// a kernel with one thread per (item, b) and plain merges.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +30,7 @@
 
 #include "common.hpp"
 #include "graph.hpp"
+#include "tc_device.hpp"
 #include "wave.hpp"
 
 namespace pgabb {
@@ -33,39 +38,32 @@ namespace pgabb {
 namespace {
 
 constexpr int kQB = 256;
-constexpr int kCliqueCap = 1024;  // longest staged row
+constexpr int kStageCap = 1024;  // entries a wave stages (both rows)
+constexpr int kTableLg = 11;     // hash slots of a wave: at most 2^11
 constexpr int kCliqueWaves = 4;
+constexpr int kQuadUnroll = 2;   // walk chunks in flight
 // A wave's work item is a run of at most kQuadSpan entries b of one of
 // A_ij's row items (each row item is cut into kSplitV / kQuadSpan parts):
 // rows of high-degree vertices then spread over several waves.
 constexpr int kQuadSpan = 8;
 constexpr int kQuadParts = kSplitV / kQuadSpan;
+// A marked key has its top bit set.  Vertex ids are below 2^31 - 1, so a
+// marked key is never -1, the empty slot.
+constexpr int32_t kMarkBit = INT32_MIN;
+constexpr int32_t kKeyBits = 0x7FFFFFFF;
 
 // Device view of one block 4-list.
 struct QuadDesc {
     BlockRef ij, ik, il, jk, jl, kl;
     int32_t slot;    // counter of the 4-list
     int32_t same;    // k == l: A_il is A_ik and A_jl is A_jk
+    int32_t lshift;  // k < l: width of stripe k, added to stripe l's ids in the table; else 0
+    int32_t pad;
 };
 
-struct CliqueLds {
-    int32_t rk[kCliqueCap];              // A_ik[a]
-    int32_t rl[kCliqueCap];              // A_il[a] (unused when k = l)
-    int32_t mem[kCliqueCap];             // positions of C in A_ik[a]
-    uint32_t mk[kCliqueCap / 32];        // C as a bitmask over A_ik[a]
-    uint32_t ml[kCliqueCap / 32];        // D as a bitmask over A_il[a]
-    int64_t incl[kWave];                 // inclusive prefix of the chunk's list lengths
-    int64_t start[kWave];                // start of each member's list in A_kl's col
-};
-
-// First position in [lo, hi) of a sorted LDS list whose value is at least x.
-__device__ __forceinline__ int32_t lds_lower_bound(const int32_t *row, int32_t lo, int32_t hi, int32_t x) {
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (row[mid] < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+// Whether a wave stages row a of A_ik (dk entries) and of A_il (dl).
+__device__ __forceinline__ bool quad_staged(int32_t dk, int32_t dl, int32_t same) {
+    return (same ? dk : dk + dl) <= kStageCap;
 }
 
 // The 4-list holding item q: the last t with pre[t] <= q.
@@ -79,19 +77,84 @@ __device__ __forceinline__ int32_t quad_of(gptr<int64_t> pre, int32_t nq, int64_
     return lo;
 }
 
+// Marks the entries of the sorted list x[0, n) found in the table, each
+// looked up as its id plus `add` (ids above top cannot be there).  Every
+// lane of the wave calls this.
+__device__ __forceinline__ void quad_mark(int32_t *H, int shift, uint32_t tmask, gptr<int32_t> x, int32_t n,
+                                          int32_t top, int32_t add, int lane) {
+    for (int32_t x0 = 0; x0 < n; x0 += kWave) {
+        const int32_t i = x0 + lane;
+        const int32_t u = i < n ? x[i] : -1;
+        bool go = u >= 0 && u <= top;
+        const int32_t v = u + add;
+        uint32_t h = hash_slot(v, shift, tmask);
+        while (__ballot(go) != 0) {
+            const int32_t sv = H[h];
+            if (go && sv == v) H[h] = v | kMarkBit;
+            go = go && sv != -1 && (sv & kKeyBits) != v;
+            h = (h + 1) & tmask;
+        }
+        if (__ballot(u > top) != 0) break;  // the rest of the list is above top too
+    }
+}
+
+// Loads elements base + q * 64 + lane (q < U) of the flattened walk over the
+// lists held by the wave's lanes (lane l: list col[pb .. pb + len), at
+// position pre of the walk); past total a lane gets -1.  The lane whose list
+// holds an element is found without a search: every list that starts inside
+// the batch writes its lane at its first position in `own` (64 * U words,
+// zero between calls), and a running maximum over the lanes fills the
+// positions in between; `carry` (lane + 1 of the list holding the element
+// before the batch) starts at 0 for a new walk.  Lists are short next to a
+// batch here (often dozens per 64 elements), so this beats advancing one list
+// at a time.
+template <int U>
+__device__ __forceinline__ void quad_walk_load(int32_t (&w)[U], int32_t base, int32_t total, int32_t pre,
+                                               int32_t len, int32_t pb, uint32_t &carry, int32_t *own,
+                                               gptr<int32_t> col, int lane) {
+    const int32_t p = pre - base;
+    if (len > 0 && p >= 0 && p < U * kWave) own[p] = lane + 1;
+    wave_lds_sync();
+    uint32_t o[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        o[q] = static_cast<uint32_t>(own[q * kWave + lane]);
+        own[q * kWave + lane] = 0;
+    }
+    wave_lds_sync();
+    const int32_t rel = pb - pre;  // element e of the walk is col[rel + e] for the lane's list
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        const uint32_t sl = max(wave_max_scan_dpp(o[q]), carry);
+        carry = __builtin_amdgcn_readlane(sl, kWave - 1);
+        const int32_t e = base + q * kWave + lane;
+        const bool inb = e < total;
+        const int32_t off = __shfl(rel, static_cast<int>(sl) - 1);
+        const int32_t x = col[inb ? off + e : 0];
+        w[q] = inb ? x : -1;
+    }
+}
+
 // Staged items: one wave per item from a work counter.  Counts go to the
-// 4-lists' counters (a wave's count of one item, once).
+// 4-lists' counters, one atomic per run of items of the same list a wave
+// takes.
 __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDesc *__restrict__ quads,
                                                                      const int64_t *__restrict__ item_pre,
                                                                      int32_t nq,
                                                                      unsigned long long *__restrict__ next,
                                                                      unsigned long long *__restrict__ counts) {
-    __shared__ CliqueLds s_lds[kCliqueWaves];
-    CliqueLds &L = s_lds[threadIdx.x / kWave];
+    __shared__ int32_t s_table[kCliqueWaves][1 << kTableLg];
+    __shared__ int32_t s_own[kCliqueWaves][kQuadUnroll * kWave];
+    int32_t *H = s_table[threadIdx.x / kWave];
+    int32_t *own = s_own[threadIdx.x / kWave];
     const int lane = lane_id();
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+#pragma unroll
+    for (int q = 0; q < kQuadUnroll; ++q) own[q * kWave + lane] = 0;
+    wave_lds_sync();
     const gptr<int64_t> ip = as_global(item_pre);
     const int64_t nitems = ip[nq];
+    unsigned long long acc = 0;  // this lane's share of the current list's count
+    int32_t acc_slot = -1;
     for (;;) {
         unsigned long long q0 = 0;
         if (lane == 0) q0 = atomicAdd(next, 1ull);
@@ -109,95 +172,95 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDe
         const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
         const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
         const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
-        if (dk == 0 || dl == 0 || dk > kCliqueCap || dl > kCliqueCap) continue;  // none, or the long kernel's
+        if (dk == 0 || dl == 0 || !quad_staged(dk, dl, Q.same)) continue;  // none, or the long kernel's
+        if (t != acc_slot) {
+            const unsigned long long w = wave_sum(acc);
+            if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
+            acc = 0;
+            acc_slot = t;
+        }
         const gptr<int32_t> ikc = as_global(Q.ik.col), ilc = as_global(Q.il.col);
-        for (int x = lane; x < dk; x += kWave) L.rk[x] = ikc[k0 + x];
-        if (!Q.same)
-            for (int x = lane; x < dl; x += kWave) L.rl[x] = ilc[l0 + x];
+        // table of 2^lg >= 4 x the staged entries slots (64 .. 2^kTableLg)
+        const int32_t nst = Q.same ? dk : dk + dl;
+        int lg = 6;
+        while ((1 << lg) < 4 * nst && lg < kTableLg) ++lg;
+        const int32_t T = 1 << lg;
+        const uint32_t tmask = static_cast<uint32_t>(T - 1);
+        const int shift = 24 - lg;
+        for (int32_t s0 = lane; s0 < T; s0 += kWave) H[s0] = -1;
         wave_lds_sync();
-        const int32_t *rl = Q.same ? L.rk : L.rl;
-        uint32_t *ml = Q.same ? L.mk : L.ml;
-        const int32_t topk = L.rk[dk - 1], topl = rl[dl - 1];
-        const int nwk = (dk + 31) >> 5, nwl = (dl + 31) >> 5;
+        for (int32_t x = lane; x < nst; x += kWave) {
+            const int32_t v = x < dk ? ikc[k0 + x] : ilc[l0 + x - dk] + Q.lshift;
+            uint32_t h = hash_slot(v, shift, tmask);
+            while (atomicCAS(&H[h], -1, v) != -1) h = (h + 1) & tmask;
+        }
+        wave_lds_sync();
+        const int32_t topk = ikc[k0 + dk - 1], topl = ilc[l0 + dl - 1];
+        const int32_t lshift = Q.lshift;
         const gptr<int32_t> ijc = as_global(Q.ij.col);
         const gptr<int32_t> jkr = as_global(Q.jk.rptr), jkc = as_global(Q.jk.col);
         const gptr<int32_t> jlr = as_global(Q.jl.rptr), jlc = as_global(Q.jl.col);
         const gptr<int32_t> klr = as_global(Q.kl.rptr), klc = as_global(Q.kl.col);
-        unsigned long long cnt = 0;
+        uint32_t cnt = 0;
         for (int32_t e = eb; e < ee; ++e) {
             const int32_t b = ijc[e];
             const int32_t bk0 = jkr[b], dbk = jkr[b + 1] - bk0;
             const int32_t bl0 = jlr[b], dbl = jlr[b + 1] - bl0;
             if (dbk == 0 || dbl == 0) continue;
-            for (int w = lane; w < nwk; w += kWave) L.mk[w] = 0;
-            if (!Q.same)
-                for (int w = lane; w < nwl; w += kWave) L.ml[w] = 0;
+            quad_mark(H, shift, tmask, jkc + bk0, dbk, topk, 0, lane);  // C (and D when k = l)
+            if (!Q.same) quad_mark(H, shift, tmask, jlc + bl0, dbl, topl, Q.lshift, lane);  // D
             wave_lds_sync();
-            for (int32_t x0 = 0; x0 < dbk; x0 += kWave) {  // C: A_jk[b] in A_ik[a]
-                const int32_t x = x0 + lane;
-                if (x < dbk) {
-                    const int32_t v = jkc[bk0 + x];
-                    if (v <= topk) {
-                        const int32_t j = lds_lower_bound(L.rk, 0, dk, v);
-                        if (j < dk && L.rk[j] == v) atomicOr(&L.mk[j >> 5], 1u << (j & 31));
-                    }
+            // walk A_kl[c] for the marked keys c of stripe k, 64 slots at a time
+            for (int32_t s0 = 0; s0 < T; s0 += kWave) {
+                const int32_t sv = H[s0 + lane];
+                const bool in = sv < -1 && (sv & kKeyBits) <= topk;
+                if (__ballot(in) == 0) continue;
+                int32_t pb = 0, len = 0;
+                if (in) {
+                    const int32_t c = sv & kKeyBits;
+                    pb = klr[c];
+                    len = klr[c + 1] - pb;
                 }
-            }
-            if (!Q.same) {
-                for (int32_t x0 = 0; x0 < dbl; x0 += kWave) {  // D: A_jl[b] in A_il[a]
-                    const int32_t x = x0 + lane;
-                    if (x < dbl) {
-                        const int32_t v = jlc[bl0 + x];
-                        if (v <= topl) {
-                            const int32_t j = lds_lower_bound(L.rl, 0, dl, v);
-                            if (j < dl && L.rl[j] == v) atomicOr(&L.ml[j >> 5], 1u << (j & 31));
+                const int32_t incl = wave_inclusive_scan(len);
+                const int32_t pre = incl - len;
+                const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                if (total == 0) continue;
+                uint32_t carry = 0;
+                int32_t w[kQuadUnroll];
+                quad_walk_load<kQuadUnroll>(w, 0, total, pre, len, pb, carry, own, klc, lane);
+                for (int32_t base = 0; base < total; base += kQuadUnroll * kWave) {
+                    int32_t wn[kQuadUnroll];
+                    quad_walk_load<kQuadUnroll>(wn, base + kQuadUnroll * kWave, total, pre, len, pb, carry, own, klc,
+                                                lane);
+#pragma unroll
+                    for (int u = 0; u < kQuadUnroll; ++u) {
+                        bool go = w[u] >= 0 && w[u] <= topl;
+                        const int32_t y = w[u] + lshift;  // its key in the table
+                        uint32_t h = hash_slot(y, shift, tmask);
+                        uint32_t hit = 0;
+                        while (__ballot(go) != 0) {
+                            const int32_t hv = H[h];
+                            hit |= (go && hv == (y | kMarkBit)) ? 1u : 0u;
+                            go = go && hv != -1 && (hv & kKeyBits) != y;
+                            h = (h + 1) & tmask;
                         }
+                        cnt += hit;
+                        w[u] = wn[u];
                     }
                 }
             }
-            wave_lds_sync();
-            int32_t nc = 0;  // members of C, in row order
-            for (int32_t j0 = 0; j0 < dk; j0 += kWave) {
-                const int32_t j = j0 + lane;
-                const bool in = j < dk && ((L.mk[j >> 5] >> (j & 31)) & 1u);
-                const uint64_t bal = __ballot(in);
-                if (in) L.mem[nc + __popcll(bal & below)] = j;
-                nc += __popcll(bal);
+            wave_lds_sync();  // the walk's reads are done: clear the marks
+            for (int32_t s0 = lane; s0 < T; s0 += kWave) {
+                const int32_t sv = H[s0];
+                if (sv < -1) H[s0] = sv & kKeyBits;
             }
             wave_lds_sync();
-            if (nc == 0) continue;
-            // walk A_kl[c] for c in C; an entry counts when it is in D
-            for (int32_t m0 = 0; m0 < nc; m0 += kWave) {
-                const int32_t mi = m0 + lane;
-                int64_t len = 0, st = 0;
-                if (mi < nc) {
-                    const int32_t c = L.rk[L.mem[mi]];
-                    st = klr[c];
-                    len = klr[c + 1] - st;
-                }
-                const int64_t incl = wave_inclusive_scan(len);
-                const int64_t tot = shfl_t(incl, kWave - 1);
-                wave_lds_sync();  // the previous chunk's lookups are done
-                L.incl[lane] = incl;
-                L.start[lane] = st;
-                wave_lds_sync();
-                int lo = 0;
-                for (int64_t f = 0; f < tot; f += kWave) {
-                    const int64_t g = f + lane;
-                    if (g >= tot) continue;
-                    while (L.incl[lo] <= g) ++lo;  // lists hold g in order; g < tot = incl[63]
-                    const int32_t y = klc[L.start[lo] + (g - (lo ? L.incl[lo - 1] : 0))];
-                    if (y > topl) continue;
-                    const int32_t j2 = lds_lower_bound(rl, 0, dl, y);
-                    if (j2 < dl && rl[j2] == y && ((ml[j2 >> 5] >> (j2 & 31)) & 1u)) ++cnt;
-                }
-            }
-            wave_lds_sync();  // before the next b clears the masks
         }
-        cnt = wave_sum(cnt);
-        if (lane == 0 && cnt) atomicAdd(&counts[Q.slot], cnt);
+        acc += cnt;
         wave_lds_sync();  // before the next item is staged
     }
+    const unsigned long long w = wave_sum(acc);
+    if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
 }
 
 // First position of the sorted list x[0, n) whose value exceeds v.
@@ -253,7 +316,7 @@ __global__ __launch_bounds__(kQB) void k_quad_long(const QuadDesc *__restrict__ 
         const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
         const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
         const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
-        if (dk == 0 || dl == 0 || (dk <= kCliqueCap && dl <= kCliqueCap)) continue;  // the staged kernel's
+        if (dk == 0 || dl == 0 || quad_staged(dk, dl, Q.same)) continue;  // the staged kernel's
         const int32_t b = as_global(Q.ij.col)[e];
         const gptr<int32_t> jkr = as_global(Q.jk.rptr), jlr = as_global(Q.jl.rptr), klr = as_global(Q.kl.rptr);
         const gptr<int32_t> ak = as_global(Q.ik.col) + k0, al = as_global(Q.il.col) + l0;
@@ -354,6 +417,8 @@ uint64_t four_cliques(pgabb_graph *g) {
             d.kl = ref(blk(L[2], L[3]));
             d.slot = q;
             d.same = L[2] == L[3];
+            d.lshift = d.same ? 0 : g->cuts[L[2] + 1] - g->cuts[L[2]];
+            d.pad = 0;
             hpre[q + 1] = hpre[q] + static_cast<int64_t>(kQuadParts) * g->blocks[blk(L[0], L[1])].nitems;
             g->quads.push_back(L);
         }
@@ -367,11 +432,14 @@ uint64_t four_cliques(pgabb_graph *g) {
         const int64_t nitems = hpre[NQ];
         int32_t max_row = 0;
         for (const auto &b : g->blocks) max_row = std::max(max_row, b.max_row);
-        const bool long_rows = max_row > kCliqueCap;
+        // some row too long to stage (with p > 1, two rows of a 4-list may
+        // share the table)
+        const bool long_rows = (p == 1 ? max_row : 2 * max_row) > kStageCap;
         StreamTimer tm;
         tm.start(s);
         if (nitems > 0) {
-            const unsigned grid = static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
+            const unsigned grid =
+                static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
             k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), NQ, dcnt.get() + NQ, dcnt.get());
             if (long_rows)
                 k_quad_long<<<std::min<unsigned>(grid_for(nitems * kQuadSpan, kQB), 256u * 16u), kQB, 0, s>>>(

@@ -64,6 +64,19 @@ __device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
     return x;
 }
 
+// Inclusive running maximum of 32-bit values across the 64 lanes of a wave
+// (all lanes active), with the lane moves of wave_scan_dpp; a lane whose
+// shifted source lies outside its row takes 0.
+__device__ __forceinline__ uint32_t wave_max_scan_dpp(uint32_t x) {
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, false)));  // row_shr:1
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, false)));  // row_shr:2
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, false)));  // row_shr:4
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, false)));  // row_shr:8
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false)));  // row_bcast:15
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false)));  // row_bcast:31
+    return x;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave (all lanes active).
 template <class T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
