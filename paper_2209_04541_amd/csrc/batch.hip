@@ -258,8 +258,13 @@ struct BatchArgs {
 template <int MODE, int LDS_WORDS, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
     __shared__ int32_t lds_all[WAVES][LDS_WORDS];
+    __shared__ int32_t own_all[WAVES][2 * kWave];  // the walk's list positions (two chunks in flight)
     const int lane = lane_id();
     int32_t *lds = lds_all[threadIdx.x >> 6];
+    int32_t *own = own_all[threadIdx.x >> 6];
+    own[lane] = 0;
+    own[kWave + lane] = 0;
+    wave_lds_sync();
     if (MODE == kModeBitmap) {
         for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
         wave_lds_sync();
@@ -291,7 +296,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
             const int32_t nv = static_cast<int32_t>(a.vbase[gid + 1] - vb);
             const int32_t u = a.rows[it];
             cnt += tc_item<MODE, LDS_WORDS>(a.rptr, a.col, u, a.rptr, a.col, a.col, a.rptr[u],
-                                            a.rptr[u + 1], nv, lds, static_cast<int32_t>(vb));
+                                            a.rptr[u + 1], nv, lds, own, static_cast<int32_t>(vb));
         }
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
         if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);

@@ -98,43 +98,6 @@ __device__ __forceinline__ void quad_mark(int32_t *H, int shift, uint32_t tmask,
     }
 }
 
-// Loads elements base + q * 64 + lane (q < U) of the flattened walk over the
-// lists held by the wave's lanes (lane l: list col[pb .. pb + len), at
-// position pre of the walk); past total a lane gets -1.  The lane whose list
-// holds an element is found without a search: every list that starts inside
-// the batch writes its lane at its first position in `own` (64 * U words,
-// zero between calls), and a running maximum over the lanes fills the
-// positions in between; `carry` (lane + 1 of the list holding the element
-// before the batch) starts at 0 for a new walk.  Lists are short next to a
-// batch here (often dozens per 64 elements), so this beats advancing one list
-// at a time.
-template <int U>
-__device__ __forceinline__ void quad_walk_load(int32_t (&w)[U], int32_t base, int32_t total, int32_t pre,
-                                               int32_t len, int32_t pb, uint32_t &carry, int32_t *own,
-                                               gptr<int32_t> col, int lane) {
-    const int32_t p = pre - base;
-    if (len > 0 && p >= 0 && p < U * kWave) own[p] = lane + 1;
-    wave_lds_sync();
-    uint32_t o[U];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-        o[q] = static_cast<uint32_t>(own[q * kWave + lane]);
-        own[q * kWave + lane] = 0;
-    }
-    wave_lds_sync();
-    const int32_t rel = pb - pre;  // element e of the walk is col[rel + e] for the lane's list
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-        const uint32_t sl = max(wave_max_scan_dpp(o[q]), carry);
-        carry = __builtin_amdgcn_readlane(sl, kWave - 1);
-        const int32_t e = base + q * kWave + lane;
-        const bool inb = e < total;
-        const int32_t off = __shfl(rel, static_cast<int>(sl) - 1);
-        const int32_t x = col[inb ? off + e : 0];
-        w[q] = inb ? x : -1;
-    }
-}
-
 // Staged items: one wave per item from a work counter.  Counts go to the
 // 4-lists' counters, one atomic per run of items of the same list a wave
 // takes.
@@ -227,11 +190,11 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDe
                 if (total == 0) continue;
                 uint32_t carry = 0;
                 int32_t w[kQuadUnroll];
-                quad_walk_load<kQuadUnroll>(w, 0, total, pre, len, pb, carry, own, klc, lane);
+                walk_load<kQuadUnroll>(w, 0, total, pre, len, pb, carry, own, klc, lane);
                 for (int32_t base = 0; base < total; base += kQuadUnroll * kWave) {
                     int32_t wn[kQuadUnroll];
-                    quad_walk_load<kQuadUnroll>(wn, base + kQuadUnroll * kWave, total, pre, len, pb, carry, own, klc,
-                                                lane);
+                    walk_load<kQuadUnroll>(wn, base + kQuadUnroll * kWave, total, pre, len, pb, carry, own, klc,
+                                           lane);
 #pragma unroll
                     for (int u = 0; u < kQuadUnroll; ++u) {
                         bool go = w[u] >= 0 && w[u] <= topl;

@@ -70,36 +70,42 @@ struct Staging {
     int32_t *table = nullptr;   // hash table, after the filter
 };
 
-// Loads elements base + q*64 + lane (q < UNROLL) of the flattened walk over
-// the lists of one group of up to 64 ids; past the group's end a lane gets
-// -1.  Lane l of the group holds its list's start pb and its prefix pre;
-// each lane tracks the lane sg whose list holds its element.  Element
-// numbers only grow from call to call, so sg only moves forward.  Every call
-// issues exactly UNROLL loads (past the end, of element 0 of wk_col, which
-// exists whenever a walk does), so the compiler can wait for one batch while
-// the next is in flight.
+// Loads elements base + q * 64 + lane (q < UNROLL) of the flattened walk over
+// the lists of one group of up to 64 ids (lane l: list wk_col[pb .. pb +
+// len), at position pre of the walk); past the group's end a lane gets -1.
+// The lane whose list holds an element is found without a search: every
+// list that starts inside the batch writes its lane + 1 at its first
+// position in `own` (64 * UNROLL words of the wave's LDS, zero between
+// calls, and left zero), and a running maximum over the lanes fills the
+// positions in between; `carry` (lane + 1 of the list holding the element
+// before the batch) starts at 0 for a new group.  Walked lists are short
+// next to a batch on skewed graphs (a batch often crosses several), where
+// advancing one list per step cost more.  Every call issues exactly UNROLL
+// loads (past the end, of element 0 of wk_col, which exists whenever a walk
+// does), so the compiler can wait for one batch while the next is in
+// flight.
 template <int UNROLL>
-__device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, int32_t total,
-                                          int32_t pre, int32_t pb, int &sg, gptr<int32_t> wk_col,
-                                          int lane) {
+__device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, int32_t total, int32_t pre,
+                                          int32_t len, int32_t pb, uint32_t &carry, int32_t *__restrict__ own,
+                                          gptr<int32_t> wk_col, int lane) {
+    const int32_t p = pre - base;
+    if (len > 0 && p >= 0 && p < UNROLL * kWave) own[p] = lane + 1;
+    wave_lds_sync();
+    uint32_t o[UNROLL];
 #pragma unroll
     for (int q = 0; q < UNROLL; ++q) {
+        o[q] = static_cast<uint32_t>(own[q * kWave + lane]);
+        own[q * kWave + lane] = 0;
+    }
+    wave_lds_sync();
+    const int32_t rel = pb - pre;  // element e of the walk is wk_col[rel + e] for the lane's list
+#pragma unroll
+    for (int q = 0; q < UNROLL; ++q) {
+        const uint32_t sl = max(wave_max_scan_dpp(o[q]), carry);
+        carry = __builtin_amdgcn_readlane(sl, kWave - 1);
         const int32_t e = base + q * kWave + lane;
         const bool inb = e < total;
-        const int32_t es = inb ? e : total - 1;
-        // advance to the largest lane whose list starts at or before es.  The
-        // shuffle runs on every lane (a shuffle under a partial mask does not
-        // read the masked lanes' values) and the exit test is wave-wide.  A
-        // lane below its target always advances, so the loop ends after at
-        // most 63 advancing rounds.
-        for (;;) {
-            const int nx = sg < kWave - 1 ? sg + 1 : sg;
-            const int32_t pn = __shfl(pre, nx);
-            const bool adv = (sg < kWave - 1) & (pn <= es);
-            sg += adv ? 1 : 0;
-            if (__ballot(adv) == 0) break;
-        }
-        const int32_t off = __shfl(pb - pre, sg);  // element e of the walk is wk_col[off + e]
+        const int32_t off = __shfl(rel, static_cast<int>(sl) - 1);
         const int32_t x = wk_col[inb ? off + e : 0];
         w[q] = inb ? x : -1;
     }
@@ -152,7 +158,7 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
                                               gptr<int32_t> wk_col, gptr<int32_t> ids, int32_t ib,
                                               int32_t ie, int32_t g0, int32_t gn, int32_t id,
                                               int32_t *__restrict__ lds, int32_t wbase, int lane,
-                                              bool &staged) {
+                                              bool &staged, int32_t *__restrict__ own) {
     uint32_t cnt = 0;
     for (;;) {  // groups of up to 64 walked lists
         int32_t pb = 0, len = 0;
@@ -163,9 +169,9 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t pre = incl - len;
         const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-        int sgl = 0;
+        uint32_t carry = 0;
         int32_t w[UNROLL];
-        walk_load<UNROLL>(w, 0, total, pre, pb, sgl, wk_col, lane);
+        walk_load<UNROLL>(w, 0, total, pre, len, pb, carry, own, wk_col, lane);
 
         if (!staged && total > 0) {
             staged = true;
@@ -192,7 +198,7 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
 
         for (int32_t base = 0; base < total; base += UNROLL * kWave) {
             int32_t wn[UNROLL];
-            walk_load<UNROLL>(wn, base + UNROLL * kWave, total, pre, pb, sgl, wk_col, lane);
+            walk_load<UNROLL>(wn, base + UNROLL * kWave, total, pre, len, pb, carry, own, wk_col, lane);
             probe_batch<PM, UNROLL>(w, cnt, lds, stg, st_col, sb, se, wbase);
 #pragma unroll
             for (int q = 0; q < UNROLL; ++q) w[q] = wn[q];
@@ -212,9 +218,10 @@ __device__ __forceinline__ uint32_t walk_item(Staging stg, gptr<int32_t> st_col,
 // sum_x |S & L_x| (the sum over lanes is the item's count).  With the edge
 // block walked by rows this is S = A_ik[u], L_v = A_jk[v] for v in A_ij[u];
 // walked by columns, S = A_jk[v], L_u = A_ik[u] for u with (u, v) in A_ij.
-// `lds` holds LDS_WORDS int32 words private to the wave.  Column ids of both
-// lists lie in [wbase, wbase + width_k).  Every lane of the wave must call
-// this with the same arguments.
+// `lds` holds LDS_WORDS int32 words private to the wave and `own` 64 *
+// UNROLL more, zero on entry and left zero (the walk's list positions).
+// Column ids of both lists lie in [wbase, wbase + width_k).  Every lane of
+// the wave must call this with the same arguments.
 //
 // Hash staging: S goes into an open-addressing table (load <= 2/3) and into
 // a bit filter with about eight bits per entry; a probe reads the filter
@@ -235,7 +242,7 @@ __device__ __forceinline__ uint32_t tc_item_core(const int32_t *__restrict__ st_
                                                  const int32_t *__restrict__ wk_col_,
                                                  const int32_t *__restrict__ ids_, int32_t ib, int32_t ie,
                                                  int32_t width_k, int32_t *__restrict__ lds,
-                                                 int32_t wbase = 0) {
+                                                 int32_t *__restrict__ own, int32_t wbase = 0) {
     const int lane = lane_id();
     if (ib >= ie) return 0u;
     const gptr<int32_t> st_col = as_global(st_col_);
@@ -278,13 +285,13 @@ __device__ __forceinline__ uint32_t tc_item_core(const int32_t *__restrict__ st_
     bool staged = false;
     if (mode == kModeHash)
         cnt = walk_item<kModeHash, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                           lds, wbase, lane, staged);
+                                           lds, wbase, lane, staged, own);
     else if (mode == kModeBitmap)
         cnt = walk_item<kModeBitmap, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                             lds, wbase, lane, staged);
+                                             lds, wbase, lane, staged, own);
     else
         cnt = walk_item<kModeSearch, UNROLL>(stg, st_col, sb, se, wk_rptr, wk_col, ids, ib, ie, ib, gn, id,
-                                             lds, wbase, lane, staged);
+                                             lds, wbase, lane, staged, own);
 
     // ---- leave the LDS clean for the next row of this wave
     if (!staged) return cnt;
@@ -314,10 +321,11 @@ __device__ __forceinline__ uint32_t tc_item(const int32_t *__restrict__ st_rptr,
                                             const int32_t *__restrict__ wk_rptr,
                                             const int32_t *__restrict__ wk_col,
                                             const int32_t *__restrict__ ids, int32_t ib, int32_t ie,
-                                            int32_t width_k, int32_t *__restrict__ lds, int32_t wbase = 0) {
+                                            int32_t width_k, int32_t *__restrict__ lds,
+                                            int32_t *__restrict__ own, int32_t wbase = 0) {
     const gptr<int32_t> rp = as_global(st_rptr);
     return tc_item_core<MODE, LDS_WORDS, UNROLL>(st_col, rp[srow], rp[srow + 1], wk_rptr, wk_col, ids, ib, ie,
-                                                 width_k, lds, wbase);
+                                                 width_k, lds, own, wbase);
 }
 
 }  // namespace pgabb

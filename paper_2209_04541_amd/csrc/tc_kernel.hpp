@@ -24,9 +24,14 @@ namespace pgabb {
 template <int MODE, int LDS_WORDS, int WAVES, int UNROLL, int ORIENT, bool FILTER = false>
 __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
     __shared__ int32_t lds_all[WAVES][LDS_WORDS];
+    __shared__ int32_t own_all[WAVES][UNROLL * kWave];  // the walk's list positions
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     int32_t *lds = lds_all[w];
+    int32_t *own = own_all[w];
+#pragma unroll
+    for (int q = 0; q < UNROLL; ++q) own[q * kWave + lane] = 0;
+    wave_lds_sync();
     if (MODE == kModeBitmap) {
         for (int q = lane; q < LDS_WORDS; q += kWave) lds[q] = 0;
         wave_lds_sync();
@@ -103,10 +108,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                 const auto &T = tasks[t];
                 if (ORIENT == kOrientRow)
                     cnt += tc_item_core<MODE, LDS_WORDS, UNROLL>(T.ik.col, sbl, sel, T.jk.rptr, T.jk.col, T.ij.col,
-                                                                 bl, el, T.width_k, lds);
+                                                                 bl, el, T.width_k, lds, own);
                 else
                     cnt += tc_item_core<MODE, LDS_WORDS, UNROLL>(T.jk.col, sbl, sel, T.ik.rptr, T.ik.col, T.ij.crow,
-                                                                 bl, el, T.width_k, lds);
+                                                                 bl, el, T.width_k, lds, own);
             }
             flush();
         }
