@@ -36,7 +36,8 @@ BATCH_SOURCES = ["paper_2209_04541_amd/csrc/batch.hip", "paper_2209_04541_amd/cs
                  "paper_2209_04541_amd/csrc/wave.hpp"]
 
 # device code of the edge-support kernel
-SUPPORT_SOURCES = ["paper_2209_04541_amd/csrc/support.hip", "paper_2209_04541_amd/csrc/wave.hpp"]
+SUPPORT_SOURCES = ["paper_2209_04541_amd/csrc/support.hip", "paper_2209_04541_amd/csrc/tc_device.hpp",
+                   "paper_2209_04541_amd/csrc/wave.hpp"]
 
 
 def kernel_digest(sources=KERNEL_SOURCES):
@@ -441,10 +442,10 @@ def bench_support(args):
     walked = int((deg * (deg - 1) // 2).sum())
     kernel_ms = float(np.mean([i["t_kernel_ms"] for i in infos]))
     # algorithmic bytes: walked entries (4 B each); per edge, as an in-edge
-    # its CSR position, row and row end (16 B) and as a staged entry its
-    # value (4 B), and the read and write of its two counter flushes (16 B);
-    # per triangle one atomic on the walked edge (8 B: read and write)
-    alg = 4 * walked + 36 * m + 8 * T
+    # its CSR position and walk length (8 B) and as a staged entry its value
+    # (4 B), and the read and write of its two counter flushes (16 B); per
+    # triangle one atomic on the walked edge (8 B: read and write)
+    alg = 4 * walked + 28 * m + 8 * T
     achieved = alg / (kernel_ms / 1e3) / 1e9
     gold = golden("block")
     out_line = base_line(args, m / (ms / 1e3), "edges/s", ms, {

@@ -13,11 +13,12 @@
 // lanes, 64 in-edges at a time, looking each walked entry up in the table.
 // This reads sum_a d+(a) (d+(a) - 1) / 2 entries, against sum over edges
 // (a, b) of d+(b) when every N+(b) is walked from the lower end (3.6 x more
-// on R-MAT scale 20).  A hit counts (b, c) in LDS (flushed once per owner),
-// (a, b) in a per-in-edge LDS counter (flushed once per 64 in-edges) and
+// on R-MAT scale 20).  A hit counts (b, c) in LDS (flushed once per unit),
+// (a, b) in a per-in-edge LDS counter (flushed once per unit) and
 // (a, c), the walked entry, with a device atomic.  Work units are runs of at
-// most 256 in-edges of one owner, so an owner with many in-edges spreads
-// over several waves (each stages N+(b) and flushes its own counters);
+// most 64 in-edges of one owner (one per lane), so an owner with many
+// in-edges spreads over many waves (each stages N+(b) and flushes its own
+// counters; 64 measured faster than 128 – 1024);
 // units are listed from the highest rank down (the hubs, whose in-edges are
 // many, start first), only for owners with both in-edges and a non-empty
 // row, and dealt round-robin to eight work counters.  Rows longer than the
@@ -41,7 +42,7 @@ constexpr int kSupCap = 682;      // longest row staged in LDS (table load <= 2/
 constexpr int kSupTableLg = 10;   // at most 1024 hash slots
 constexpr int kSupB = 256;
 constexpr int kSupUnroll = 2;     // walk chunks in flight
-constexpr int kSupUnitEdges = 256;  // in-edges per work unit
+constexpr int kSupUnitEdges = kWave;  // in-edges per work unit (one per lane)
 constexpr int kSupQueues = 8;       // work counters, kSupQueueStride words apart
 constexpr int kSupQueueStride = 32;
 
@@ -210,23 +211,13 @@ __global__ __launch_bounds__(kSupWaves *kWave) void k_edge_support(const int64_t
             wave_lds_sync();
         }
         const int32_t hi_b = cl[b0 + d - 1];  // no c above N+(b)'s last entry can match
-        // groups of 64 in-edges; each group's positions and walk lengths are
-        // loaded while the previous group is walked
-        uint32_t eab_n = 0;
-        int32_t len_n = 0;
-        if (lane < nin) {
-            eab_n = ip[i0 + lane];
-            len_n = il[i0 + lane];
-        }
-        for (int64_t c0 = 0; c0 < nin; c0 += kWave) {
-            const int64_t k = c0 + lane;
-            const uint32_t eab = eab_n;
-            const int32_t len = len_n;
-            eab_n = 0;
-            len_n = 0;
-            if (k + kWave < nin) {
-                eab_n = ip[i0 + k + kWave];
-                len_n = il[i0 + k + kWave];
+        {  // the unit's in-edges, one per lane: position of (a, b) and its walk's length
+            const int64_t k = lane;
+            uint32_t eab = 0;
+            int32_t len = 0;
+            if (k < nin) {
+                eab = ip[i0 + k];
+                len = il[i0 + k];
             }
             const int32_t incl = wave_inclusive_scan(len);
             const int32_t pre = incl - len;
@@ -288,7 +279,7 @@ __global__ __launch_bounds__(kSupWaves *kWave) void k_edge_support(const int64_t
             if (acc) atomicAdd(&L.hits[acc_lo], acc);
             wave_lds_sync();
             if (k < nin && L.hits[lane]) atomicAdd(&support[eab], L.hits[lane]);
-            wave_lds_sync();  // before the next group resets the counters
+            wave_lds_sync();  // before the next unit resets the counters
         }
         if (staged) {
             wave_lds_sync();
