@@ -395,19 +395,20 @@ pgabb_status pgabb_tc_vertex_counts(pgabb_graph *g, uint64_t *per_vertex, uint32
 /*
  * The k-truss (the peeling algorithm named in PGAbB Section 3.2): the
  * largest subgraph in which every edge lies in at least k - 2 triangles of
- * the subgraph (unique; k <= 2 keeps every edge).  Computed by rounds: each
- * round counts the triangles of every remaining edge (the pass of
- * pgabb_tc_edge_support on the graph of the remaining edges) and keeps the
- * edges with at least k - 2; the rounds end when one keeps every edge.
+ * the subgraph (unique; k <= 2 keeps every edge).  Computed by peeling in
+ * rounds: one pass of pgabb_tc_edge_support counts the triangles of every
+ * edge; each round removes the remaining edges with fewer than k - 2 and
+ * takes the triangles they close off the counts of the other edges; the
+ * rounds end when none is removed.
  *   k         : k >= 0
  *   keep      : optional; m' bytes, keep[e] = 1 for the oriented edge at CSR
  *               position e (pgabb_graph_export_csr) if it is in the k-truss,
  *               else 0.  Host memory, or device memory with
  *               PGABB_SUPPORT_ON_DEVICE; complete when the call returns.
  *   num_edges : optional; edges of the k-truss
- *   rounds    : optional; support passes run
- * pgabb_graph_info_get then reports the call's time (t_count_ms), the
- * support kernels' time and the rounds as launches.
+ *   rounds    : optional; rounds that removed edges
+ * pgabb_graph_info_get then reports the call's time (t_count_ms), the time
+ * of the support and peeling kernels, and the rounds as launches.
  * Errors: EINVAL (NULL graph, k < 0, unknown flags, m' >= 2^32), ENOMEM,
  * EDEVICE.
  */

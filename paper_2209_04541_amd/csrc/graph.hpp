@@ -155,6 +155,10 @@ std::vector<int32_t> task_shards(const pgabb_graph *g, int32_t nshards);
 // Triangles containing each oriented edge, into out[m'] (device or host
 // memory); returns the triangle count.
 uint64_t edge_support(pgabb_graph *g, uint32_t *out, bool out_on_device);
+// In-edges of every vertex of the oriented graph: in_off (n + 1 offsets from
+// the kept in-degrees) and in_pos (the CSR positions of the edges, grouped by
+// their higher end, each group ascending in the lower end).
+void in_edges(pgabb_graph *g, DArray<int64_t> &in_off, DArray<uint32_t> &in_pos);
 // Triangles at each vertex, by input id, into out[n] (device or host
 // memory); returns the triangle count.
 uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);

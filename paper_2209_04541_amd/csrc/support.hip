@@ -295,6 +295,21 @@ __global__ __launch_bounds__(kSupWaves *kWave) void k_edge_support(const int64_t
 
 }  // namespace
 
+void in_edges(pgabb_graph *g, DArray<int64_t> &in_off, DArray<uint32_t> &in_pos) {
+    hipStream_t s = g->stream;
+    const int64_t m = g->m;
+    const int32_t n = g->n;
+    DArray<uint32_t> key(static_cast<size_t>(m), s), key_alt(static_cast<size_t>(m), s);
+    DArray<uint32_t> pos(static_cast<size_t>(m), s), pos_alt(static_cast<size_t>(m), s);
+    in_off.reset(static_cast<size_t>(n) + 1, s);
+    k_sup_pairs<<<grid_for(m, kSupB), kSupB, 0, s>>>(g->col.get(), m, key.get(), pos.get());
+    k_sup_widen<<<grid_for(n, kSupB), kSupB, 0, s>>>(g->indeg.get(), n, in_off.get());
+    PGABB_HIP(hipGetLastError());
+    scan_exclusive_i64(in_off.get(), in_off.get(), n, in_off.get() + n, s);
+    const bool alt = radix_sort_u32(key.get(), key_alt.get(), pos.get(), pos_alt.get(), m, g->nb, s);
+    in_pos = std::move(alt ? pos_alt : pos);
+}
+
 uint64_t edge_support(pgabb_graph *g, uint32_t *out, bool out_on_device) {
     hipStream_t s = g->stream;
     const auto t0 = std::chrono::steady_clock::now();
@@ -317,18 +332,12 @@ uint64_t edge_support(pgabb_graph *g, uint32_t *out, bool out_on_device) {
         // (stable, so ascending in the lower end), offsets from the kept
         // in-degrees
         DArray<int32_t> rest(static_cast<size_t>(m), s);
-        DArray<uint32_t> key(static_cast<size_t>(m), s), key_alt(static_cast<size_t>(m), s);
-        DArray<uint32_t> pos(static_cast<size_t>(m), s), pos_alt(static_cast<size_t>(m), s);
-        DArray<int64_t> in_off(static_cast<size_t>(n) + 1, s);
         k_sup_rest<<<grid_for(m, kSupB), kSupB, 0, s>>>(g->row_off.get(), n, m, rest.get());
-        k_sup_pairs<<<grid_for(m, kSupB), kSupB, 0, s>>>(g->col.get(), m, key.get(), pos.get());
-        k_sup_widen<<<grid_for(n, kSupB), kSupB, 0, s>>>(g->indeg.get(), n, in_off.get());
         PGABB_HIP(hipGetLastError());
-        scan_exclusive_i64(in_off.get(), in_off.get(), n, in_off.get() + n, s);
-        const bool alt = radix_sort_u32(key.get(), key_alt.get(), pos.get(), pos_alt.get(), m, g->nb, s);
-        const uint32_t *in_pos = alt ? pos_alt.get() : pos.get();
-        key.release();
-        key_alt.release();
+        DArray<int64_t> in_off;
+        DArray<uint32_t> in_pos_arr;
+        in_edges(g, in_off, in_pos_arr);
+        const uint32_t *in_pos = in_pos_arr.get();
         DArray<int32_t> in_len(static_cast<size_t>(m), s);
         k_sup_in_len<<<grid_for(m, kSupB), kSupB, 0, s>>>(in_pos, rest.get(), m, in_len.get());
         PGABB_HIP(hipGetLastError());
