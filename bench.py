@@ -434,6 +434,14 @@ def bench_support(args):
     inf = g.info()
     cliques["p8"] = {"four_cliques": c4_8, "t_ms": inf["t_count_ms"], "t_kernel_ms": inf["t_kernel_ms"],
                      "four_lists": len(g.four_clique_lists()[0])}
+    # the same 4-lists with the blocks streamed from the host store through
+    # a device cache of a quarter of the store
+    cap = inf["block_bytes"] // 4
+    c4_s = g.four_cliques(device_cap_bytes=cap)
+    inf = g.info()
+    cliques["p8_streamed"] = {"four_cliques": c4_s, "device_cap_bytes": cap, "t_ms": inf["t_count_ms"],
+                              "t_kernel_ms": inf["t_kernel_ms"], "h2d_bytes": inf["h2d_bytes"],
+                              "launches": inf["kernel_launches"]}
     g.close()
     m = info["m"]
     T = tri
@@ -469,7 +477,7 @@ def bench_support(args):
         "ktruss": truss,
         "cliques": cliques,
     })
-    out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T and c4 == c4_8
+    out_line["parity"] = out_line["parity"] and tri_v == T and tv_sum == 3 * T and c4 == c4_8 == c4_s
     if not args.no_cpu_baseline:
         import oracle
         t1 = time.perf_counter()

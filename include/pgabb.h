@@ -423,13 +423,31 @@ pgabb_status pgabb_tc_ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, uint32_t 
  * i <= j <= k <= l, with six non-empty blocks is a task, heaviest first.
  * Each 4-clique a < b < c < d (ranks) is counted once, in the 4-list of its
  * stripes, at its edge (a, b) of A_ij: the pairs c in A_ik[a] & A_jk[b],
- * d in A_il[a] & A_jl[b] with (c, d) in A_kl.  pgabb_graph_info_get then
- * reports the call's time, kernel time and launches; pgabb_graph_4list_counts
- * the 4-lists and their counts.
- * Errors: EINVAL (NULL argument), ESTATE (blocks held in host memory by a
- * streamed count), ENOMEM, EDEVICE.
+ * d in A_il[a] & A_jl[b] with (c, d) in A_kl.  Blocks in device memory are
+ * read in place; blocks that a streamed count moved to the pinned host store
+ * are streamed as by pgabb_count_4cliques_streamed under that count's
+ * device cap (all blocks when it had none).  pgabb_graph_info_get then
+ * reports the call's time, kernel time, launches and host-to-device bytes;
+ * pgabb_graph_4list_counts the 4-lists and their counts.
+ * Errors: EINVAL (NULL argument), ENOMEM, EDEVICE.
  */
 pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count);
+
+/*
+ * The same count with the blocks streamed from the pinned host store (the
+ * device arena moves there first if it is still on the device, as in a
+ * streamed triangle count; Section 4.4) through a device block cache of at
+ * most device_cap_bytes: consecutive 4-lists (heaviest first) form a window
+ * while the union of their six blocks' row parts (row items, row offsets,
+ * columns) fits the cap; each window's missing blocks are copied, least
+ * recently used blocks outside the window leaving first, then the window is
+ * counted.  Copies and launches of a window run in order on the graph's
+ * stream.
+ *   device_cap_bytes : > 0; bytes of device block cache
+ * Errors: EINVAL (NULL argument, device_cap_bytes == 0), ENOMEM (the cap
+ * cannot hold the six blocks of some 4-list, or allocation), EDEVICE.
+ */
+pgabb_status pgabb_count_4cliques_streamed(pgabb_graph *g, uint64_t device_cap_bytes, uint64_t *count);
 
 /*
  * The block 4-lists of the last pgabb_count_4cliques on g, in processing

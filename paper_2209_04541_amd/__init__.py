@@ -109,6 +109,7 @@ def lib():
             "pgabb_tc_vertex_counts": (st, [vp, vp, u32, ctypes.POINTER(u64)]),
             "pgabb_tc_ktruss": (st, [vp, i32, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_count_4cliques": (st, [vp, ctypes.POINTER(u64)]),
+            "pgabb_count_4cliques_streamed": (st, [vp, u64, ctypes.POINTER(u64)]),
             "pgabb_graph_4list_counts": (st, [vp, ctypes.POINTER(i64), vp, vp]),
             "pgabb_components": (st, [vp, vp, u32, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "pgabb_pagerank": (st, [vp, ctypes.c_double, ctypes.c_double, i32, vp, u32, ctypes.POINTER(i32),
@@ -376,10 +377,15 @@ class Graph:
                                               ctypes.c_void_p(cnt.ctypes.data)))
         return ijkl[:L], cnt[:L]
 
-    def four_cliques(self):
-        """Sets of four pairwise adjacent vertices."""
+    def four_cliques(self, device_cap_bytes=0):
+        """Sets of four pairwise adjacent vertices; with device_cap_bytes > 0
+        the blocks stream from the host store through a cache of that size."""
         c = ctypes.c_uint64()
-        _check(lib().pgabb_count_4cliques(self._h, ctypes.byref(c)))
+        if device_cap_bytes:
+            _check(lib().pgabb_count_4cliques_streamed(self._h, ctypes.c_uint64(int(device_cap_bytes)),
+                                                       ctypes.byref(c)))
+        else:
+            _check(lib().pgabb_count_4cliques(self._h, ctypes.byref(c)))
         return int(c.value)
 
     def task_shards(self, num_shards):

@@ -324,7 +324,16 @@ PGABB_API pgabb_status pgabb_graph_4list_counts(const pgabb_graph *g, int64_t *n
 PGABB_API pgabb_status pgabb_count_4cliques(pgabb_graph *g, uint64_t *count) {
     if (!g || !count) return set_err(PGABB_EINVAL, "NULL argument");
     PGABB_TRY
-    *count = four_cliques(g);
+    *count = four_cliques(g, 0);
+    return set_ok();
+    PGABB_CATCH
+}
+
+PGABB_API pgabb_status pgabb_count_4cliques_streamed(pgabb_graph *g, uint64_t device_cap_bytes, uint64_t *count) {
+    if (!g || !count) return set_err(PGABB_EINVAL, "NULL argument");
+    if (device_cap_bytes == 0) return set_err(PGABB_EINVAL, "device_cap_bytes must be positive");
+    PGABB_TRY
+    *count = four_cliques(g, device_cap_bytes);
     return set_ok();
     PGABB_CATCH
 }

@@ -124,6 +124,7 @@ struct pgabb_graph {
     pgabb::DArray<int32_t> arena;        // device block storage (in-core)
     pgabb::PinnedArray<int32_t> host_arena;  // host block store (streamed)
     bool blocks_on_host = false;
+    uint64_t host_store_cap = 0;  // device cap of the streamed count that moved the blocks to the host
     std::vector<pgabb::Task> tasks;
     std::vector<uint64_t> task_counts;
     std::vector<std::array<int32_t, 4>> quads;  // block 4-lists of the last 4-clique count
@@ -166,7 +167,13 @@ uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device);
 // (keep may be null); returns their number.
 int64_t ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, bool on_device, int32_t *rounds);
 // Sets of four pairwise adjacent vertices.
-uint64_t four_cliques(pgabb_graph *g);
+// device_cap_bytes > 0: the blocks are streamed from the pinned host store
+// (moved there first if needed) through a block cache of at most that many
+// bytes; 0: in device memory, or streamed under the cap of the count that
+// moved them to the host.
+uint64_t four_cliques(pgabb_graph *g, uint64_t device_cap_bytes);
+// Moves the device block arena to the pinned host store (once per partition).
+void move_blocks_to_host(pgabb_graph *g);
 // Connected components by Shiloach-Vishkin over the device blocks:
 // label[v] = smallest input id of v's component; returns the number of
 // components.

@@ -26,10 +26,12 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <list>
 #include <vector>
 
 #include "common.hpp"
 #include "graph.hpp"
+#include "range_pool.hpp"
 #include "tc_device.hpp"
 #include "wave.hpp"
 
@@ -136,11 +138,11 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDe
         const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
         const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
         if (dk == 0 || dl == 0 || !quad_staged(dk, dl, Q.same)) continue;  // none, or the long kernel's
-        if (t != acc_slot) {
+        if (Q.slot != acc_slot) {  // counts gather per 4-list (its slot among all the count's lists)
             const unsigned long long w = wave_sum(acc);
             if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
             acc = 0;
-            acc_slot = t;
+            acc_slot = Q.slot;
         }
         const gptr<int32_t> ikc = as_global(Q.ik.col), ilc = as_global(Q.il.col);
         // table of 2^lg >= 4 x the staged entries slots (64 .. 2^kTableLg)
@@ -316,22 +318,100 @@ __global__ void k_zero_u64q(unsigned long long *p, int64_t n) {
 
 }  // namespace
 
-uint64_t four_cliques(pgabb_graph *g) {
+namespace {
+
+// Bytes of the row part of a block's chunk (row items, row offsets,
+// columns: what the 4-clique kernels read), rounded to the pool alignment.
+constexpr uint64_t kQuadAlign = 256;
+uint64_t quad_chunk_bytes(const BlockInfo &b) {
+    const uint64_t raw = static_cast<uint64_t>(b.walk_hi(kOrientRow) - b.walk_lo(kOrientRow)) * sizeof(int32_t);
+    return (raw + kQuadAlign - 1) / kQuadAlign * kQuadAlign;
+}
+
+// Device view of a block whose row part starts at `base` (device words).
+BlockRef quad_ref(const BlockInfo &bi, const int32_t *base) {
+    BlockRef r;
+    const int64_t lo = bi.walk_lo(kOrientRow);
+    r.rptr = base + (bi.off_rptr() - lo);
+    r.items = base + (bi.off_items() - lo);
+    r.col = base + (bi.off_col() - lo);
+    r.citems = nullptr;  // the 4-clique kernels walk rows only
+    r.crow = nullptr;
+    r.nitems = bi.nitems;
+    r.ncitems = bi.ncitems;
+    return r;
+}
+
+// Counts the 4-lists lists[first, last) (their blocks at the given device
+// bases), adding to dcnt[slot]; dcnt[NQ] is the work counter.
+void quad_launch(pgabb_graph *g, const std::vector<std::array<int32_t, 4>> &lists, int32_t first, int32_t last,
+                 const std::vector<const int32_t *> &base, unsigned long long *dcnt, int32_t NQ, double &kernel_ms,
+                 int64_t &launches) {
+    hipStream_t s = g->stream;
+    const int32_t p = g->p;
+    const int32_t W = last - first;
+    auto blk = [&](int32_t x, int32_t y) { return g->block_of[static_cast<size_t>(x) * p + y]; };
+    Staged<QuadDesc> hq(W, s);
+    Staged<int64_t> hpre(static_cast<size_t>(W) + 1, s);
+    hpre[0] = 0;
+    int32_t max_row = 0;
+    for (int32_t q = 0; q < W; ++q) {
+        const auto &L = lists[first + q];
+        QuadDesc &d = hq[q];
+        const int32_t b6[6] = {blk(L[0], L[1]), blk(L[0], L[2]), blk(L[0], L[3]),
+                               blk(L[1], L[2]), blk(L[1], L[3]), blk(L[2], L[3])};
+        BlockRef *r6[6] = {&d.ij, &d.ik, &d.il, &d.jk, &d.jl, &d.kl};
+        for (int x = 0; x < 6; ++x) {
+            *r6[x] = quad_ref(g->blocks[b6[x]], base[b6[x]]);
+            max_row = std::max(max_row, g->blocks[b6[x]].max_row);
+        }
+        d.slot = first + q;
+        d.same = L[2] == L[3];
+        d.lshift = d.same ? 0 : g->cuts[L[2] + 1] - g->cuts[L[2]];
+        d.pad = 0;
+        hpre[q + 1] = hpre[q] + static_cast<int64_t>(kQuadParts) * g->blocks[b6[0]].nitems;
+    }
+    const int64_t nitems = hpre[W];
+    if (nitems == 0) return;
+    DArray<QuadDesc> dq(W, s);
+    DArray<int64_t> dpre(static_cast<size_t>(W) + 1, s);
+    PGABB_HIP(hipMemcpyAsync(dq.get(), hq.get(), hq.bytes(), hipMemcpyHostToDevice, s));
+    PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, s));
+    k_zero_u64q<<<1, 64, 0, s>>>(dcnt + NQ, 1);  // the work counter
+    // some row too long to stage (with p > 1, two rows of a 4-list may
+    // share the table)
+    const bool long_rows = (p == 1 ? max_row : 2 * max_row) > kStageCap;
+    StreamTimer tm;
+    tm.start(s);
+    const unsigned grid =
+        static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
+    k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), W, dcnt + NQ, dcnt);
+    if (long_rows)
+        k_quad_long<<<std::min<unsigned>(grid_for(nitems * kQuadSpan, kQB), 256u * 16u), kQB, 0, s>>>(
+            dq.get(), dpre.get(), W, dcnt);
+    PGABB_HIP(hipGetLastError());
+    tm.stop(s);
+    PGABB_HIP(hipStreamSynchronize(s));  // the descriptors and the blocks may go once this returns
+    kernel_ms += tm.ms();
+    launches += long_rows ? 2 : 1;
+}
+
+}  // namespace
+
+uint64_t four_cliques(pgabb_graph *g, uint64_t device_cap_bytes) {
     hipStream_t s = g->stream;
     const auto t0 = std::chrono::steady_clock::now();
     if (g->p == 0) partition_graph(g, 1, PGABB_CUT_NNZ, nullptr);
-    PGABB_REQUIRE(!g->blocks_on_host, PGABB_ESTATE,
-                  "the graph's blocks are held in host memory (streamed); the 4-clique count needs them in "
-                  "device memory: partition the graph again");
     g->t_kernel_ms = 0;
     g->kernel_launches = 0;
+    g->h2d_bytes = 0;
     g->quads.clear();
     g->quad_counts.clear();
     const int32_t p = g->p;
     // ---- the 4-lists: i <= j <= k <= l with six non-empty blocks, heaviest
     // first (edges of the list's blocks)
     auto blk = [&](int32_t x, int32_t y) { return g->block_of[static_cast<size_t>(x) * p + y]; };
-    std::vector<std::pair<int64_t, std::array<int32_t, 4>>> lists;
+    std::vector<std::pair<int64_t, std::array<int32_t, 4>>> ranked;
     for (int32_t i = 0; i < p; ++i)
         for (int32_t j = i; j < p; ++j) {
             if (blk(i, j) < 0) continue;
@@ -345,78 +425,142 @@ uint64_t four_cliques(pgabb_graph *g) {
                         ok = ok && b >= 0;
                         if (b >= 0) w += g->blocks[b].nnz;
                     }
-                    if (ok) lists.push_back({w, {i, j, k, l}});
+                    if (ok) ranked.push_back({w, {i, j, k, l}});
                 }
             }
         }
-    std::stable_sort(lists.begin(), lists.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-    const int32_t NQ = static_cast<int32_t>(lists.size());
+    std::stable_sort(ranked.begin(), ranked.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    const int32_t NQ = static_cast<int32_t>(ranked.size());
+    for (const auto &x : ranked) g->quads.push_back(x.second);
     uint64_t result = 0;
     if (NQ > 0) {
-        const int32_t *arena = g->arena.get();
-        auto ref = [&](int32_t b) {
-            const BlockInfo &bi = g->blocks[b];
-            BlockRef r;
-            r.rptr = arena + bi.off_rptr();
-            r.items = arena + bi.off_items();
-            r.col = arena + bi.off_col();
-            r.citems = arena + bi.off_citems();
-            r.crow = arena + bi.off_crow();
-            r.nitems = bi.nitems;
-            r.ncitems = bi.ncitems;
-            return r;
-        };
-        Staged<QuadDesc> hq(NQ, s);
-        Staged<int64_t> hpre(static_cast<size_t>(NQ) + 1, s);
-        hpre[0] = 0;
-        for (int32_t q = 0; q < NQ; ++q) {
-            const auto &L = lists[q].second;
-            QuadDesc &d = hq[q];
-            d.ij = ref(blk(L[0], L[1]));
-            d.ik = ref(blk(L[0], L[2]));
-            d.il = ref(blk(L[0], L[3]));
-            d.jk = ref(blk(L[1], L[2]));
-            d.jl = ref(blk(L[1], L[3]));
-            d.kl = ref(blk(L[2], L[3]));
-            d.slot = q;
-            d.same = L[2] == L[3];
-            d.lshift = d.same ? 0 : g->cuts[L[2] + 1] - g->cuts[L[2]];
-            d.pad = 0;
-            hpre[q + 1] = hpre[q] + static_cast<int64_t>(kQuadParts) * g->blocks[blk(L[0], L[1])].nitems;
-            g->quads.push_back(L);
-        }
-        DArray<QuadDesc> dq(NQ, s);
-        DArray<int64_t> dpre(static_cast<size_t>(NQ) + 1, s);
+        const int32_t nblk = static_cast<int32_t>(g->blocks.size());
         DArray<unsigned long long> dcnt(static_cast<size_t>(NQ) + 1, s);  // counts, then the work counter
-        PGABB_HIP(hipMemcpyAsync(dq.get(), hq.get(), hq.bytes(), hipMemcpyHostToDevice, s));
-        PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, s));
         k_zero_u64q<<<std::min<unsigned>(grid_for(NQ + 1, 256), 1024u), 256, 0, s>>>(dcnt.get(), NQ + 1);
         PGABB_HIP(hipGetLastError());
-        const int64_t nitems = hpre[NQ];
-        int32_t max_row = 0;
-        for (const auto &b : g->blocks) max_row = std::max(max_row, b.max_row);
-        // some row too long to stage (with p > 1, two rows of a 4-list may
-        // share the table)
-        const bool long_rows = (p == 1 ? max_row : 2 * max_row) > kStageCap;
-        StreamTimer tm;
-        tm.start(s);
-        if (nitems > 0) {
-            const unsigned grid =
-                static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
-            k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), NQ, dcnt.get() + NQ, dcnt.get());
-            if (long_rows)
-                k_quad_long<<<std::min<unsigned>(grid_for(nitems * kQuadSpan, kQB), 256u * 16u), kQB, 0, s>>>(
-                    dq.get(), dpre.get(), NQ, dcnt.get());
-            PGABB_HIP(hipGetLastError());
+        double kernel_ms = 0;
+        int64_t launches = 0;
+        const bool streamed = device_cap_bytes > 0 || g->blocks_on_host;
+        if (!streamed) {
+            std::vector<const int32_t *> base(nblk);
+            for (int32_t b = 0; b < nblk; ++b) base[b] = g->arena.get() + g->blocks[b].walk_lo(kOrientRow);
+            quad_launch(g, g->quads, 0, NQ, base, dcnt.get(), NQ, kernel_ms, launches);
+        } else {
+            // ---- streamed: the blocks move from the host store through a
+            // cache of at most `cap` bytes.  Consecutive 4-lists form a
+            // window while the union of their blocks fits the cap; the
+            // window's missing blocks are copied (least recently used blocks
+            // outside the window leave first; if the free ranges are too
+            // fragmented the cache starts over), then the window is counted.
+            if (!g->blocks_on_host) move_blocks_to_host(g);
+            if (device_cap_bytes == 0) device_cap_bytes = g->host_store_cap;
+            std::vector<uint64_t> bytes(nblk);
+            uint64_t total = 0;
+            for (int32_t b = 0; b < nblk; ++b) total += bytes[b] = quad_chunk_bytes(g->blocks[b]);
+            uint64_t cap = device_cap_bytes ? std::min(device_cap_bytes, total) : total;
+            cap = cap / kQuadAlign * kQuadAlign;
+            auto list_blocks = [&](int32_t q, int32_t (&b6)[6]) {
+                const auto &L = g->quads[q];
+                const int32_t x[6] = {blk(L[0], L[1]), blk(L[0], L[2]), blk(L[0], L[3]),
+                                      blk(L[1], L[2]), blk(L[1], L[3]), blk(L[2], L[3])};
+                for (int y = 0; y < 6; ++y) b6[y] = x[y];
+            };
+            DArray<uint8_t> pool(static_cast<size_t>(cap), s);
+            RangePool rp(cap);
+            std::vector<uint64_t> off(nblk, UINT64_MAX);  // pool offset of resident blocks
+            std::list<int32_t> lru;                       // resident blocks, least recently used first
+            std::vector<std::list<int32_t>::iterator> where(nblk, lru.end());
+            std::vector<int32_t> mark(nblk, -1);          // window that uses the block
+            std::vector<const int32_t *> base(nblk, nullptr);
+            const int32_t *host = g->host_arena.get();
+            constexpr int32_t kMaxWindow = 512;  // 4-lists per launch
+            int32_t q = 0, win = 0;
+            while (q < NQ) {
+                // the window: lists [q, e) whose blocks fit together
+                std::vector<int32_t> wb;
+                uint64_t need = 0;
+                int32_t e = q;
+                while (e < NQ && e - q < kMaxWindow) {
+                    int32_t b6[6];
+                    list_blocks(e, b6);
+                    uint64_t add = 0;
+                    std::vector<int32_t> fresh;
+                    for (int32_t b : b6)
+                        if (mark[b] != win && std::find(fresh.begin(), fresh.end(), b) == fresh.end()) {
+                            fresh.push_back(b);
+                            add += bytes[b];
+                        }
+                    if (need + add > cap) {
+                        PGABB_REQUIRE(e > q, PGABB_ENOMEM,
+                                      "device cap of %llu bytes cannot hold the %llu bytes of 4-list (%d, %d, %d, %d)",
+                                      static_cast<unsigned long long>(cap), static_cast<unsigned long long>(add),
+                                      g->quads[e][0], g->quads[e][1], g->quads[e][2], g->quads[e][3]);
+                        break;
+                    }
+                    for (int32_t b : fresh) {
+                        mark[b] = win;
+                        wb.push_back(b);
+                    }
+                    need += add;
+                    ++e;
+                }
+                // make the window's blocks resident
+                for (int pass = 0; pass < 2; ++pass) {
+                    bool ok = true;
+                    for (int32_t b : wb) {
+                        if (off[b] != UINT64_MAX) {
+                            lru.splice(lru.end(), lru, where[b]);  // most recently used
+                            continue;
+                        }
+                        uint64_t o = rp.alloc(bytes[b]);
+                        while (o == UINT64_MAX) {  // evict blocks outside the window
+                            auto it = lru.begin();
+                            while (it != lru.end() && mark[*it] == win) ++it;
+                            if (it == lru.end()) break;
+                            rp.release(off[*it], bytes[*it]);
+                            off[*it] = UINT64_MAX;
+                            base[*it] = nullptr;
+                            where[*it] = lru.end();
+                            lru.erase(it);
+                            o = rp.alloc(bytes[b]);
+                        }
+                        if (o == UINT64_MAX) {
+                            ok = false;
+                            break;
+                        }
+                        off[b] = o;
+                        const BlockInfo &bi = g->blocks[b];
+                        const int64_t lo = bi.walk_lo(kOrientRow);
+                        const uint64_t raw = static_cast<uint64_t>(bi.walk_hi(kOrientRow) - lo) * sizeof(int32_t);
+                        uint8_t *dst = pool.get() + o;
+                        if (raw) PGABB_HIP(hipMemcpyAsync(dst, host + lo, raw, hipMemcpyHostToDevice, s));
+                        g->h2d_bytes += raw;
+                        base[b] = reinterpret_cast<const int32_t *>(dst);
+                        where[b] = lru.insert(lru.end(), b);
+                    }
+                    if (ok) break;
+                    // fragmented: drop every block and place the window from an empty cache
+                    PGABB_REQUIRE(pass == 0, PGABB_EDEVICE, "4-clique block cache could not place a window");
+                    for (int32_t b : lru) {
+                        off[b] = UINT64_MAX;
+                        base[b] = nullptr;
+                        where[b] = lru.end();
+                    }
+                    lru.clear();
+                    rp = RangePool(cap);
+                }
+                quad_launch(g, g->quads, q, e, base, dcnt.get(), NQ, kernel_ms, launches);
+                q = e;
+                ++win;
+            }
         }
-        tm.stop(s);
         Staged<unsigned long long> h(NQ, s);
         PGABB_HIP(hipMemcpyAsync(h.get(), dcnt.get(), h.bytes(), hipMemcpyDeviceToHost, s));
         PGABB_HIP(hipStreamSynchronize(s));
         g->quad_counts.assign(h.get(), h.get() + NQ);
-        for (int32_t q = 0; q < NQ; ++q) result += h[q];
-        g->t_kernel_ms = tm.ms();
-        g->kernel_launches = nitems > 0 ? (long_rows ? 2 : 1) : 0;
+        for (int32_t x = 0; x < NQ; ++x) result += h[x];
+        g->t_kernel_ms = kernel_ms;
+        g->kernel_launches = launches;
     }
     g->t_count_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return result;

@@ -28,6 +28,7 @@
 #include <thread>
 
 #include "block_readers.hpp"
+#include "range_pool.hpp"
 #include "common.hpp"
 #include "count.hpp"
 #include "graph.hpp"
@@ -36,43 +37,6 @@
 namespace pgabb {
 
 namespace {
-
-// First-fit allocator over [0, cap) with coalescing of free ranges.
-class RangePool {
-  public:
-    explicit RangePool(uint64_t cap) { free_[0] = cap; }
-    // Returns offset or UINT64_MAX.
-    uint64_t alloc(uint64_t bytes) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const uint64_t off = it->first;
-                const uint64_t rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                return off;
-            }
-        }
-        return UINT64_MAX;
-    }
-    void release(uint64_t off, uint64_t bytes) {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;
-};
 
 constexpr uint64_t kAlign = 256;
 
@@ -86,7 +50,7 @@ uint64_t chunk_bytes(const BlockInfo &b, int orient) {
 }  // namespace
 
 // Moves the device arena to a pinned host store (once per partition).
-static void move_blocks_to_host(pgabb_graph *g) {
+void move_blocks_to_host(pgabb_graph *g) {
     if (g->blocks_on_host) return;
     hipStream_t s = g->stream;
     g->host_arena.reset(static_cast<size_t>(g->arena_words));
@@ -187,6 +151,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             if (used[b]) total_bytes += chunk_bytes(g->blocks[b], orient);
     }
     uint64_t cap = opt.device_cap_bytes ? opt.device_cap_bytes : total_bytes;
+    g->host_store_cap = opt.device_cap_bytes;
     cap = std::min(cap, total_bytes);
     cap = cap / kAlign * kAlign;
     for (const Task &t : g->tasks) {

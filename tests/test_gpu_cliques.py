@@ -154,11 +154,65 @@ def test_block_lists_long_rows(p):
         assert info["kernel_launches"] == 2
 
 
-def test_block_lists_streamed_graph_is_refused():
-    n, s, d = gen.rmat(10, 8, gen.seed(68, 0))
+def test_block_lists_streamed_host_store():
+    """A streamed triangle count moves the blocks to the host store; the
+    4-clique count then streams them (under that count's cap) and every
+    4-list's count equals the in-core one."""
+    n, s, d = gen.rmat(12, 16, gen.seed(68, 0))
     with P.Graph(n, s, d) as g:
-        g.partition(3)
-        g.count(stream_blocks=True)
-        with pytest.raises(P.PgabbError) as ei:
-            g.four_cliques()
-        assert ei.value.status == P.ESTATE
+        g.partition(5)
+        want = g.four_cliques()
+        _, want_cnt = g.four_clique_lists()
+        tri = g.count(stream_blocks=True, device_cap_bytes=g.info()["block_bytes"] // 2)
+        got = g.four_cliques()
+        _, cnt = g.four_clique_lists()
+        info = g.info()
+    assert tri == oracle.tc(n, s, d)
+    assert got == want == oracle.four_cliques(n, s, d)
+    assert np.array_equal(cnt, want_cnt)
+    assert info["h2d_bytes"] > 0
+
+
+@pytest.mark.parametrize("p", [3, 8])
+def test_block_lists_streamed_caps(p):
+    """Caps halved from the whole store down to the first that cannot hold
+    some 4-list's six blocks (ENOMEM): every count on the way equals the
+    in-core one, list by list, and smaller caps copy more."""
+    n, s, d = gen.rmat(13, 16, gen.seed(69, p))
+    with P.Graph(n, s, d) as g:
+        g.partition(p)
+        want = g.four_cliques()
+        _, want_cnt = g.four_clique_lists()
+        cap = g.info()["block_bytes"]
+        copied = []
+        for _ in range(12):
+            try:
+                got = g.four_cliques(device_cap_bytes=cap)
+            except P.PgabbError as e:
+                assert e.status == P.ENOMEM
+                break
+            _, cnt = g.four_clique_lists()
+            assert got == want
+            assert np.array_equal(cnt, want_cnt)
+            copied.append(g.info()["h2d_bytes"])
+            cap //= 2
+        else:
+            raise AssertionError("no cap was too small")
+    say("4-lists streamed p", p, "bytes copied per cap", copied)
+    assert len(copied) >= 2 and copied[-1] > copied[0]
+    assert want == oracle.four_cliques(n, s, d)
+
+
+def test_block_lists_streamed_long_rows():
+    """K_1100 plus a pendant K_30 over 2 x 2 blocks, streamed under three
+    quarters of the store: the merge kernel reads streamed blocks too."""
+    a, b = np.triu_indices(1100, 1)
+    c, e = np.triu_indices(30, 1)
+    s = np.concatenate([a, c + 1100, [0, 7]]).astype(np.int32)
+    d = np.concatenate([b, e + 1100, [1100, 1101]]).astype(np.int32)
+    with P.Graph(1130, s, d) as g:
+        g.partition(2)
+        got = g.four_cliques(device_cap_bytes=g.info()["block_bytes"] * 3 // 4)
+        info = g.info()
+    assert got == math.comb(1100, 4) + math.comb(30, 4)
+    assert info["kernel_launches"] >= 2
