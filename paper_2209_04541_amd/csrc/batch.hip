@@ -282,21 +282,35 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
         const int64_t i0 = q0 + static_cast<int64_t>(g0);
         if (i0 >= q1) break;
         const int64_t i1 = min(i0 + a.grab, q1);
-        int32_t gcur = a.row_gid[i0];
+        const int32_t nrow = static_cast<int32_t>(i1 - i0);  // at most 64
+        // the grab's row headers, lane l holding row i0 + l: graph, row,
+        // bounds of N+(u), and the graph's vertex range, in two round trips
+        int32_t h_gid = 0, h_u = 0, h_sb = 0, h_se = 0, h_vb = 0, h_nv = 0;
+        if (lane < nrow) {
+            h_gid = a.row_gid[i0 + lane];
+            h_u = a.rows[i0 + lane];
+        }
+        if (lane < nrow) {
+            h_sb = a.rptr[h_u];
+            h_se = a.rptr[h_u + 1];
+            const int64_t vb = a.vbase[h_gid];
+            h_vb = static_cast<int32_t>(vb);
+            h_nv = static_cast<int32_t>(a.vbase[h_gid + 1] - vb);
+        }
+        int32_t gcur = __builtin_amdgcn_readfirstlane(h_gid);
         uint32_t cnt = 0;
-        for (int64_t it = i0; it < i1; ++it) {
-            const int32_t gid = a.row_gid[it];
+        for (int32_t l = 0; l < nrow; ++l) {
+            const int32_t gid = __builtin_amdgcn_readlane(h_gid, l);
             if (gid != gcur) {
                 const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
                 if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);
                 cnt = 0;
                 gcur = gid;
             }
-            const int64_t vb = a.vbase[gid];
-            const int32_t nv = static_cast<int32_t>(a.vbase[gid + 1] - vb);
-            const int32_t u = a.rows[it];
-            cnt += tc_item<MODE, LDS_WORDS>(a.rptr, a.col, u, a.rptr, a.col, a.col, a.rptr[u],
-                                            a.rptr[u + 1], nv, lds, own, static_cast<int32_t>(vb));
+            const int32_t sb = __builtin_amdgcn_readlane(h_sb, l), se = __builtin_amdgcn_readlane(h_se, l);
+            cnt += tc_item_core<MODE, LDS_WORDS>(a.col, sb, se, a.rptr, a.col, a.col, sb, se,
+                                                 __builtin_amdgcn_readlane(h_nv, l), lds, own,
+                                                 __builtin_amdgcn_readlane(h_vb, l));
         }
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
         if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);
