@@ -285,7 +285,16 @@ __global__ __launch_bounds__(kBB) void k_pr_update(double *__restrict__ r, const
     }
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) e += __shfl_xor(e, m);
-    if (lane_id() == 0 && e != 0.0) unsafeAtomicAdd(err, e);
+    // one atomic per workgroup: the launch keeps its grid small, so the
+    // additions to the one address stay few
+    __shared__ double s_part[kBB / kWave];
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBB / kWave; ++w) t += s_part[w];
+        if (t != 0.0) unsafeAtomicAdd(err, t);
+    }
 }
 
 __global__ __launch_bounds__(kBB) void k_pr_init(double *__restrict__ r, int32_t n, double v) {
@@ -458,7 +467,8 @@ int32_t pagerank(pgabb_graph *g, double damping, double tol, int32_t max_iter, d
             if (sg.total > 0)
                 k_pr_pull<<<bsp_grid(sg.total), kBB, 0, s>>>(sg.segs.get(), sg.pre.get(), sg.n, contrib.get(), acc.get());
             zero_words(reinterpret_cast<unsigned long long *>(derr.get()), 1, s);  // +0.0 is all zero bits
-            k_pr_update<<<bsp_grid(n), kBB, 0, s>>>(r.get(), acc.get(), n, teleport, damping, derr.get());
+            k_pr_update<<<std::min(bsp_grid(n), 512u), kBB, 0, s>>>(r.get(), acc.get(), n, teleport, damping,
+                                                                   derr.get());
             PGABB_HIP(hipGetLastError());
             tm.stop(s);
             PGABB_HIP(hipMemcpyAsync(herr.get(), derr.get(), sizeof(double), hipMemcpyDeviceToHost, s));
