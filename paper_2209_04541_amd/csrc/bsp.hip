@@ -77,6 +77,19 @@ struct BspSeg {
     int32_t base_y;  // rank of local id 0 on the entry side
 };
 
+// Sum of v over the workgroup (kBB threads, all of which call this),
+// returned to thread 0.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v) {
+    __shared__ unsigned long long s_part[kBB / kWave];
+    v = wave_sum(v);
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBB / kWave; ++w) t += s_part[w];
+    return t;
+}
+
 // Last segment s with pre[s] <= q (pre[0] = 0 <= q < pre[nseg]).
 __device__ __forceinline__ int32_t find_seg(const int64_t *__restrict__ pre, int32_t nseg, int64_t q) {
     int32_t lo = 0, hi = nseg - 1;
@@ -96,8 +109,9 @@ __global__ __launch_bounds__(kBB) void k_sv_init(int32_t *__restrict__ C, int32_
 // Hooking: for every edge (u, v) with C(u) != C(v), the larger of the two
 // (a root after the previous linking pass) is hooked under the smaller if it
 // still is a root.  Parents only ever decrease (C(x) <= x), so the pointers
-// form a forest whatever order the hooks land in.  *hooks counts the hooks
-// made (an item of several hooks adds each).
+// form a forest whatever order the hooks land in.  *hooks becomes nonzero
+// when a hook was made (a wave adds its hooks only while it reads zero
+// there, so the word takes few atomics).
 __global__ __launch_bounds__(kBB) void k_sv_hook(const BspSeg *__restrict__ segs, const int64_t *__restrict__ pre,
                                                  int32_t nseg, int32_t *__restrict__ C,
                                                  unsigned long long *__restrict__ hooks,
@@ -123,7 +137,7 @@ __global__ __launch_bounds__(kBB) void k_sv_hook(const BspSeg *__restrict__ segs
         }
     });
     const unsigned long long sum = wave_sum(static_cast<unsigned long long>(h));
-    if (lane_id() == 0 && sum) atomicAdd(hooks, sum);
+    if (lane_id() == 0 && sum && __atomic_load_n(hooks, __ATOMIC_RELAXED) == 0) atomicAdd(hooks, sum);
 }
 
 // Linking: every vertex points to the root of its tree (pointer jumping to
@@ -164,8 +178,8 @@ __global__ __launch_bounds__(kBB) void k_sv_minid(const int32_t *__restrict__ C,
         if (ok && !same) atomicMin(&minid[root], static_cast<int32_t>(v));
         c += ok && C[v] == v ? 1u : 0u;
     }
-    const unsigned long long sum = wave_sum(static_cast<unsigned long long>(c));
-    if (lane_id() == 0 && sum) atomicAdd(roots, sum);
+    const unsigned long long sum = block_sum(static_cast<unsigned long long>(c));
+    if (threadIdx.x == 0 && sum) atomicAdd(roots, sum);  // one atomic per workgroup, at most 512
 }
 
 __global__ void k_zero_words(unsigned long long *__restrict__ p, int32_t n) {
@@ -422,7 +436,7 @@ int64_t components(pgabb_graph *g, int32_t *label, bool on_device, int32_t *iter
         tm.start(s);
         k_fill_i32<<<bsp_grid(n), kBB, 0, s>>>(minid.get(), INT32_MAX, n);
         zero_words(ctr.get() + 1, 1, s);
-        k_sv_minid<<<bsp_grid(n), kBB, 0, s>>>(C.get(), g->rank.get(), n, minid.get(), ctr.get() + 1);
+        k_sv_minid<<<std::min(bsp_grid(n), 512u), kBB, 0, s>>>(C.get(), g->rank.get(), n, minid.get(), ctr.get() + 1);
         k_sv_label<<<bsp_grid(n), kBB, 0, s>>>(C.get(), g->rank.get(), minid.get(), n, dst);
         PGABB_HIP(hipGetLastError());
         tm.stop(s);
