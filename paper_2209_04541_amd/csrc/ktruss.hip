@@ -38,19 +38,12 @@ constexpr int kPeelWaves = 4;
 
 enum : uint8_t { kLive = 0, kDying = 1, kDead = 2 };
 
-// Lower end (row) of every oriented edge.
-__global__ __launch_bounds__(kKB) void k_kt_rows(const int64_t *__restrict__ row_off, int32_t n, int64_t m,
+// Lower end (row) of every oriented edge, a thread per row.
+__global__ __launch_bounds__(kKB) void k_kt_rows(const int64_t *__restrict__ row_off, int32_t n,
                                                   int32_t *__restrict__ lo_end) {
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(kKB) + threadIdx.x; e < m;
-         e += static_cast<int64_t>(gridDim.x) * kKB) {
-        int32_t lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (row_off[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        lo_end[e] = lo;
-    }
+    for (int64_t a = blockIdx.x * static_cast<int64_t>(kKB) + threadIdx.x; a < n;
+         a += static_cast<int64_t>(gridDim.x) * kKB)
+        for (int64_t e = row_off[a]; e < row_off[a + 1]; ++e) lo_end[e] = static_cast<int32_t>(a);
 }
 
 // Lower end of the edge in every in-edge slot.
@@ -266,7 +259,7 @@ int64_t ktruss(pgabb_graph *g, int32_t k, uint8_t *keep, bool on_device, int32_t
             DArray<int64_t> in_off;
             DArray<uint32_t> in_pos;
             in_edges(g, in_off, in_pos);
-            k_kt_rows<<<grid_for(m, kKB), kKB, 0, s>>>(g->row_off.get(), n, m, lo_end.get());
+            k_kt_rows<<<grid_for(n, kKB), kKB, 0, s>>>(g->row_off.get(), n, lo_end.get());
             k_kt_in_nb<<<grid_for(m, kKB), kKB, 0, s>>>(in_pos.get(), lo_end.get(), m, in_nb.get());
             PGABB_HIP(hipGetLastError());
             DArray<uint32_t> front(static_cast<size_t>(m), s);

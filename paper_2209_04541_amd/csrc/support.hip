@@ -54,19 +54,14 @@ struct SupportLds {
     int32_t own[kSupUnroll * kWave];    // list positions of the flattened walk
 };
 
-// Entries after every CSR position in its row (row a: the last row whose
-// offset is at most e): the length of the walk an in-edge at e starts.
-__global__ __launch_bounds__(kSupB) void k_sup_rest(const int64_t *__restrict__ row_off, int32_t n, int64_t m,
+// Entries after every CSR position in its row (a thread per row): the
+// length of the walk an in-edge at that position starts.
+__global__ __launch_bounds__(kSupB) void k_sup_rest(const int64_t *__restrict__ row_off, int32_t n,
                                                      int32_t *__restrict__ rest) {
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(kSupB) + threadIdx.x; e < m;
-         e += static_cast<int64_t>(gridDim.x) * kSupB) {
-        int32_t lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (row_off[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        rest[e] = static_cast<int32_t>(row_off[lo + 1] - e - 1);
+    for (int64_t a = blockIdx.x * static_cast<int64_t>(kSupB) + threadIdx.x; a < n;
+         a += static_cast<int64_t>(gridDim.x) * kSupB) {
+        const int64_t end = row_off[a + 1];
+        for (int64_t e = row_off[a]; e < end; ++e) rest[e] = static_cast<int32_t>(end - e - 1);
     }
 }
 
@@ -332,7 +327,7 @@ uint64_t edge_support(pgabb_graph *g, uint32_t *out, bool out_on_device) {
         // (stable, so ascending in the lower end), offsets from the kept
         // in-degrees
         DArray<int32_t> rest(static_cast<size_t>(m), s);
-        k_sup_rest<<<grid_for(m, kSupB), kSupB, 0, s>>>(g->row_off.get(), n, m, rest.get());
+        k_sup_rest<<<grid_for(n, kSupB), kSupB, 0, s>>>(g->row_off.get(), n, rest.get());
         PGABB_HIP(hipGetLastError());
         DArray<int64_t> in_off;
         DArray<uint32_t> in_pos_arr;

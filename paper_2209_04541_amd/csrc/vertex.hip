@@ -16,24 +16,23 @@ namespace {
 
 constexpr int kVB = 256;
 
-// Adds each edge's count to both of its ends (ranks).  The row of CSR
-// position e is the last row whose offset is at most e.
+// Adds each edge's count to both of its ends (ranks): a thread per row sums
+// its row's counts for the row's own vertex and adds each count to the
+// column's vertex.
 __global__ __launch_bounds__(kVB) void k_vertex_sums(const int64_t *__restrict__ row_off,
                                                       const int32_t *__restrict__ col,
-                                                      const uint32_t *__restrict__ sup, int32_t n, int64_t m,
+                                                      const uint32_t *__restrict__ sup, int32_t n,
                                                       unsigned long long *__restrict__ tv) {
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(kVB) + threadIdx.x; e < m;
-         e += static_cast<int64_t>(gridDim.x) * kVB) {
-        const uint32_t c = sup[e];
-        if (!c) continue;
-        int32_t lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (row_off[mid] <= e) lo = mid;
-            else hi = mid - 1;
+    for (int64_t r = blockIdx.x * static_cast<int64_t>(kVB) + threadIdx.x; r < n;
+         r += static_cast<int64_t>(gridDim.x) * kVB) {
+        unsigned long long own = 0;
+        for (int64_t e = row_off[r]; e < row_off[r + 1]; ++e) {
+            const uint32_t c = sup[e];
+            if (!c) continue;
+            own += c;
+            atomicAdd(&tv[col[e]], static_cast<unsigned long long>(c));
         }
-        atomicAdd(&tv[lo], static_cast<unsigned long long>(c));
-        atomicAdd(&tv[col[e]], static_cast<unsigned long long>(c));
+        if (own) atomicAdd(&tv[r], own);
     }
 }
 
@@ -71,7 +70,7 @@ uint64_t vertex_counts(pgabb_graph *g, uint64_t *out, bool out_on_device) {
         triangles = edge_support(g, sup.get(), true);  // kernel time and launches of the support pass
         DArray<unsigned long long> tv(static_cast<size_t>(n), s);
         PGABB_HIP(hipMemsetAsync(tv.get(), 0, sizeof(unsigned long long) * static_cast<size_t>(n), s));
-        k_vertex_sums<<<grid_for(m, kVB), kVB, 0, s>>>(g->row_off.get(), g->col.get(), sup.get(), n, m, tv.get());
+        k_vertex_sums<<<grid_for(n, kVB), kVB, 0, s>>>(g->row_off.get(), g->col.get(), sup.get(), n, tv.get());
         DArray<uint64_t> own;
         uint64_t *dst = out;
         if (!out_on_device) {
