@@ -299,7 +299,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_batch(BatchArgs a) {
         }
         int32_t gcur = __builtin_amdgcn_readfirstlane(h_gid);
         uint32_t cnt = 0;
-        for (int32_t l = 0; l < nrow; ++l) {
+        // rows of at most kTinyCap entries: walked together, graph by graph
+        const bool lv = lane < nrow;
+        uint64_t tiny = __ballot(lv && h_se > h_sb && h_se - h_sb <= kTinyCap);
+        uint64_t rest = __ballot(lv && h_se - h_sb > kTinyCap);
+        while (tiny) {
+            const int32_t gid = __builtin_amdgcn_readlane(h_gid, __builtin_ctzll(tiny));
+            const uint64_t mg = tiny & __ballot(h_gid == gid);
+            tiny &= ~mg;
+            if (gid != gcur) {
+                const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));
+                if (lane == 0 && s) atomicAdd(&a.counts[gcur], s);
+                cnt = 0;
+                gcur = gid;
+            }
+            cnt += tiny_items<2>(mg, h_sb, h_se, h_sb, h_se, a.col, a.col, a.rptr, a.col, own, lane);
+        }
+        while (rest) {
+            const int l = __builtin_ctzll(rest);
+            rest &= rest - 1;
             const int32_t gid = __builtin_amdgcn_readlane(h_gid, l);
             if (gid != gcur) {
                 const unsigned long long s = wave_sum(static_cast<unsigned long long>(cnt));

@@ -111,6 +111,101 @@ __device__ __forceinline__ void walk_load(int32_t (&w)[UNROLL], int32_t base, in
     }
 }
 
+// Items whose staged list has at most this many entries are walked together
+// (tiny_items).
+constexpr int kTinyCap = 4;
+
+// Counts the items of the lanes in `m` (one task or graph, staged lists of
+// at most kTinyCap entries; lane l: ids[b .. e) are its walked lists' ids and
+// st_col[sb .. se) its staged list) in one walk instead of one after
+// another.  The items' walked lists are flattened over the lanes 64 at a
+// time, each list lane finding its item with the scattered lookup and taking
+// the item's staged entries (held in registers, -2 padding no element
+// matches); the lists' elements are then flattened over the lanes again and
+// each is compared with its list's staged entries.  On hypersparse blocks an
+// item walks a handful of entries, which a wave walking one item at a time
+// spreads over a few of its lanes.
+template <int UNROLL>
+__device__ __forceinline__ uint32_t tiny_items(uint64_t m, int32_t b, int32_t e, int32_t sb, int32_t se,
+                                               const int32_t *st_col_, const int32_t *ids_,
+                                               const int32_t *wk_rptr_, const int32_t *wk_col_, int32_t *own,
+                                               int lane) {
+    const gptr<int32_t> st_col = as_global(st_col_), ids = as_global(ids_);
+    const gptr<int32_t> wk_rptr = as_global(wk_rptr_), wk_col = as_global(wk_col_);
+    const bool in = (m >> lane) & 1ull;
+    int32_t s[kTinyCap];
+#pragma unroll
+    for (int t = 0; t < kTinyCap; ++t) s[t] = (in && t < se - sb) ? st_col[sb + t] : -2;
+    const int32_t nl = in ? e - b : 0;  // walked lists of the lane's item
+    const int32_t incl1 = wave_inclusive_scan(nl);
+    const int32_t pre1 = incl1 - nl;
+    const int32_t nlists = __builtin_amdgcn_readlane(incl1, kWave - 1);
+    const int32_t idbase = b - pre1;  // list slot j of the item is ids[idbase + j]
+    uint32_t cnt = 0;
+    uint32_t carry1 = 0;
+    for (int32_t j0 = 0; j0 < nlists; j0 += kWave) {
+        // the item of list slot j0 + lane
+        const int32_t p = pre1 - j0;
+        if (nl > 0 && p >= 0 && p < kWave) own[p] = lane + 1;
+        wave_lds_sync();
+        const uint32_t o = static_cast<uint32_t>(own[lane]);
+        own[lane] = 0;
+        wave_lds_sync();
+        const uint32_t il1 = max(wave_max_scan_dpp(o), carry1);
+        carry1 = __builtin_amdgcn_readlane(il1, kWave - 1);
+        const int il = static_cast<int>(il1) - 1;
+        const int32_t j = j0 + lane;
+        const int32_t ib = __shfl(idbase, il);
+        int32_t ls[kTinyCap];
+#pragma unroll
+        for (int t = 0; t < kTinyCap; ++t) ls[t] = __shfl(s[t], il);
+        int32_t pb = 0, len = 0;
+        if (j < nlists) {
+            const int32_t id = ids[ib + j];
+            pb = wk_rptr[id];
+            len = wk_rptr[id + 1] - pb;
+        }
+        // the elements of these lists, flattened over the lanes
+        const int32_t incl = wave_inclusive_scan(len);
+        const int32_t pre = incl - len;
+        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        const int32_t rel = pb - pre;  // element x of the run is wk_col[rel + x] for the lane's list
+        uint32_t carry = 0;
+        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
+            const int32_t p2 = pre - base;
+            if (len > 0 && p2 >= 0 && p2 < UNROLL * kWave) own[p2] = lane + 1;
+            wave_lds_sync();
+            uint32_t o2[UNROLL];
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                o2[q] = static_cast<uint32_t>(own[q * kWave + lane]);
+                own[q * kWave + lane] = 0;
+            }
+            wave_lds_sync();
+            int32_t y[UNROLL], sl[UNROLL];
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                const uint32_t sl1 = max(wave_max_scan_dpp(o2[q]), carry);
+                carry = __builtin_amdgcn_readlane(sl1, kWave - 1);
+                sl[q] = static_cast<int>(sl1) - 1;
+                const int32_t x = base + q * kWave + lane;
+                const bool inb = x < total;
+                const int32_t off = __shfl(rel, sl[q]);
+                const int32_t v = wk_col[inb ? off + x : 0];
+                y[q] = inb ? v : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                uint32_t hit = 0;
+#pragma unroll
+                for (int t = 0; t < kTinyCap; ++t) hit |= y[q] == __shfl(ls[t], sl[q]) ? 1u : 0u;
+                cnt += hit;
+            }
+        }
+    }
+    return cnt;
+}
+
 // Adds to cnt the hits of the UNROLL elements in w (-1 = none) against S.
 // Hash probes are predicated: a wave-uniform loop runs while any lane is
 // still searching, with no per-lane branches.
