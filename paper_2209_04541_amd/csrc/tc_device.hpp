@@ -206,6 +206,151 @@ __device__ __forceinline__ uint32_t tiny_items(uint64_t m, int32_t b, int32_t e,
     return cnt;
 }
 
+// Items with small staged lists and few walked lists are walked together
+// too (packed_items): staged lists of at most kPackS entries, at most
+// kPackLists walked lists.
+constexpr int kPackS = 64;
+constexpr int kPackLists = 8;
+
+// Hash slot of value w of the pack's item il (the item enters the key, so
+// equal values of different items fall apart).
+__device__ __forceinline__ uint32_t pack_slot(int32_t w, int il, int shift, uint32_t mask) {
+    return hash_slot(w + il * 0x3C6EF35, shift, mask);
+}
+
+// Counts the items of the lanes in `m` (one task; lane l: ids[b .. e) are
+// its walked lists' ids, st_col[sb .. se) its staged list) in one walk: the
+// items' staged lists go into one open-addressing table in the wave's LDS
+// region, each entry with its item's lane as a tag (the table in the hash
+// table words, the tags as bytes in the filter words; at most kPackSlots
+// slots, load <= 1/2, so the items' staged entries must sum to at most half
+// of that); the walked lists are then flattened as in tiny_items and each
+// element probes the table with its list's item.  The region is left zero
+// (what bitmap kernels expect; hash staging clears what it uses).
+template <int UNROLL, int LDS_WORDS>
+__device__ __forceinline__ uint32_t packed_items(uint64_t m, int32_t b, int32_t e, int32_t sb, int32_t se,
+                                                 const int32_t *st_col_, const int32_t *ids_,
+                                                 const int32_t *wk_rptr_, const int32_t *wk_col_,
+                                                 int32_t *__restrict__ lds, int32_t *own, int lane) {
+    constexpr int FC = HashLds<LDS_WORDS>::kFilterCap;
+    constexpr int kPackSlots = HashLds<LDS_WORDS>::kTableCap < 4 * FC ? HashLds<LDS_WORDS>::kTableCap : 4 * FC;
+    int32_t *table = lds + FC;
+    uint8_t *tag = reinterpret_cast<uint8_t *>(lds);
+    const gptr<int32_t> st_col = as_global(st_col_), ids = as_global(ids_);
+    const gptr<int32_t> wk_rptr = as_global(wk_rptr_), wk_col = as_global(wk_col_);
+    const bool in = (m >> lane) & 1ull;
+    // ---- stage every item's list, tagged with the item's lane
+    const int32_t ns = in ? se - sb : 0;
+    const int32_t incls = wave_inclusive_scan(ns);
+    const int32_t pres = incls - ns;
+    const int32_t nsum = __builtin_amdgcn_readlane(incls, kWave - 1);
+    int lg = 6;
+    while ((1 << lg) < 2 * nsum && (1 << lg) < kPackSlots) ++lg;
+    const uint32_t tmask = (1u << lg) - 1u;
+    const int shift = 24 - lg;
+    for (int q = lane; q < (1 << lg); q += kWave) table[q] = -1;
+    wave_lds_sync();
+    const int32_t sbase = sb - pres;  // staged entry k of the item is st_col[sbase + k]
+    uint32_t carry0 = 0;
+    for (int32_t k0 = 0; k0 < nsum; k0 += kWave) {
+        const int32_t p = pres - k0;
+        if (ns > 0 && p >= 0 && p < kWave) own[p] = lane + 1;
+        wave_lds_sync();
+        const uint32_t o = static_cast<uint32_t>(own[lane]);
+        own[lane] = 0;
+        wave_lds_sync();
+        const uint32_t il1 = max(wave_max_scan_dpp(o), carry0);
+        carry0 = __builtin_amdgcn_readlane(il1, kWave - 1);
+        const int il = static_cast<int>(il1) - 1;
+        const int32_t k = k0 + lane;
+        const int32_t base_k = __shfl(sbase, il);
+        if (k < nsum) {
+            const int32_t v = st_col[base_k + k];
+            uint32_t h = pack_slot(v, il, shift, tmask);
+            while (atomicCAS(&table[h], -1, v) != -1) h = (h + 1) & tmask;
+            tag[h] = static_cast<uint8_t>(il);
+        }
+    }
+    wave_lds_sync();
+    // ---- the walked lists, flattened as in tiny_items
+    const int32_t nl = in ? e - b : 0;
+    const int32_t incl1 = wave_inclusive_scan(nl);
+    const int32_t pre1 = incl1 - nl;
+    const int32_t nlists = __builtin_amdgcn_readlane(incl1, kWave - 1);
+    const int32_t idbase = b - pre1;
+    uint32_t cnt = 0;
+    uint32_t carry1 = 0;
+    for (int32_t j0 = 0; j0 < nlists; j0 += kWave) {
+        const int32_t p = pre1 - j0;
+        if (nl > 0 && p >= 0 && p < kWave) own[p] = lane + 1;
+        wave_lds_sync();
+        const uint32_t o = static_cast<uint32_t>(own[lane]);
+        own[lane] = 0;
+        wave_lds_sync();
+        const uint32_t il1 = max(wave_max_scan_dpp(o), carry1);
+        carry1 = __builtin_amdgcn_readlane(il1, kWave - 1);
+        const int il = static_cast<int>(il1) - 1;  // the item of list slot j0 + lane
+        const int32_t j = j0 + lane;
+        const int32_t ib = __shfl(idbase, il);
+        int32_t pb = 0, len = 0;
+        if (j < nlists) {
+            const int32_t id = ids[ib + j];
+            pb = wk_rptr[id];
+            len = wk_rptr[id + 1] - pb;
+        }
+        const int32_t incl = wave_inclusive_scan(len);
+        const int32_t pre = incl - len;
+        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        const int32_t rel = pb - pre;
+        uint32_t carry = 0;
+        for (int32_t base = 0; base < total; base += UNROLL * kWave) {
+            const int32_t p2 = pre - base;
+            if (len > 0 && p2 >= 0 && p2 < UNROLL * kWave) own[p2] = lane + 1;
+            wave_lds_sync();
+            uint32_t o2[UNROLL];
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                o2[q] = static_cast<uint32_t>(own[q * kWave + lane]);
+                own[q * kWave + lane] = 0;
+            }
+            wave_lds_sync();
+            int32_t y[UNROLL], yi[UNROLL];
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                const uint32_t sl1 = max(wave_max_scan_dpp(o2[q]), carry);
+                carry = __builtin_amdgcn_readlane(sl1, kWave - 1);
+                const int sl = static_cast<int>(sl1) - 1;
+                const int32_t x = base + q * kWave + lane;
+                const bool inb = x < total;
+                const int32_t off = __shfl(rel, sl);
+                yi[q] = __shfl(il, sl);  // the element's item
+                const int32_t v = wk_col[inb ? off + x : 0];
+                y[q] = inb ? v : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q) {
+                bool go = y[q] >= 0;
+                uint32_t h = pack_slot(y[q], yi[q], shift, tmask);
+                uint32_t hit = 0;
+                while (__ballot(go) != 0) {
+                    const int32_t sv = table[h];
+                    const bool same = go && sv == y[q] && tag[h] == static_cast<uint8_t>(yi[q]);
+                    hit |= same ? 1u : 0u;
+                    go = go && sv != -1 && !same;
+                    h = (h + 1) & tmask;
+                }
+                cnt += hit;
+            }
+        }
+    }
+    // ---- leave the region zero
+    wave_lds_sync();
+    for (int q = lane; q < (1 << lg); q += kWave) table[q] = 0;
+    for (int q = lane; q < ((1 << lg) + 3) / 4; q += kWave) lds[q] = 0;
+    wave_lds_sync();
+    return cnt;
+}
+
 // Adds to cnt the hits of the UNROLL elements in w (-1 = none) against S.
 // Hash probes are predicated: a wave-uniform loop runs while any lane is
 // still searching, with no per-lane branches.

@@ -110,6 +110,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_tc_tasks(CountArgs a) {
                 else
                     cnt += tiny_items<UNROLL>(mt, b, e, sb, se, T.jk.col, T.ij.crow, T.ik.rptr, T.ik.col, own, lane);
             }
+            // items with small staged lists and few walked lists: packed into
+            // one LDS table, task by task, while their staged entries fit
+            constexpr int kPackSlots = HashLds<LDS_WORDS>::kTableCap < 4 * HashLds<LDS_WORDS>::kFilterCap
+                                           ? HashLds<LDS_WORDS>::kTableCap
+                                           : 4 * HashLds<LDS_WORDS>::kFilterCap;
+            uint64_t small = todo & __ballot(se - sb <= kPackS && e - b <= kPackLists);
+            todo &= ~small;
+            while (small) {
+                const int32_t t = __builtin_amdgcn_readlane(tl, __builtin_ctzll(small));
+                const uint64_t mt = small & __ballot(tl == t);
+                const int32_t ns = ((mt >> lane) & 1ull) ? se - sb : 0;
+                const uint64_t mp = mt & __ballot(wave_inclusive_scan(ns) <= kPackSlots / 2);
+                small &= ~mp;
+                if (t != cur) {
+                    flush();
+                    cur = t;
+                }
+                const auto &T = tasks[t];
+                if (ORIENT == kOrientRow)
+                    cnt += packed_items<UNROLL, LDS_WORDS>(mp, b, e, sb, se, T.ik.col, T.ij.col, T.jk.rptr, T.jk.col,
+                                                           lds, own, lane);
+                else
+                    cnt += packed_items<UNROLL, LDS_WORDS>(mp, b, e, sb, se, T.jk.col, T.ij.crow, T.ik.rptr,
+                                                           T.ik.col, lds, own, lane);
+            }
             while (todo) {
                 const int l = __builtin_ctzll(todo);
                 todo &= todo - 1;
