@@ -95,7 +95,11 @@ class DArray {
     hipStream_t stream_ = nullptr;
 };
 
-// Pinned host array (hipHostMalloc).
+// Pinned host array.  reset(n) allocates with hipHostMalloc; reset(n, s,
+// true) takes the block from the pinned cache (halloc) instead, and release
+// returns it there, ordered after the work then queued on s: for large
+// stores that are rebuilt call after call, whose hipHostMalloc and
+// hipHostFree would otherwise repeat.
 template <class T>
 class PinnedArray {
   public:
@@ -103,20 +107,31 @@ class PinnedArray {
     ~PinnedArray() { release(); }
     PinnedArray(const PinnedArray &) = delete;
     PinnedArray &operator=(const PinnedArray &) = delete;
-    void reset(size_t n) {
+    void reset(size_t n, hipStream_t s = nullptr, bool cached = false) {
         release();
         if (n) {
-            void *p = nullptr;
-            hipError_t e = hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault);
-            if (e != hipSuccess) fail(PGABB_ENOMEM, "hipHostMalloc(%zu bytes): %s", n * sizeof(T), hipGetErrorString(e));
-            ptr_ = static_cast<T *>(p);
+            if (cached) {
+                ptr_ = static_cast<T *>(halloc(n * sizeof(T)));
+            } else {
+                void *p = nullptr;
+                hipError_t e = hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault);
+                if (e != hipSuccess)
+                    fail(PGABB_ENOMEM, "hipHostMalloc(%zu bytes): %s", n * sizeof(T), hipGetErrorString(e));
+                ptr_ = static_cast<T *>(p);
+            }
         }
         n_ = n;
+        stream_ = s;
+        cached_ = cached;
     }
     void release() {
-        if (ptr_) (void)hipHostFree(ptr_);
+        if (ptr_) {
+            if (cached_) hfree(ptr_, stream_);
+            else (void)hipHostFree(ptr_);
+        }
         ptr_ = nullptr;
         n_ = 0;
+        cached_ = false;
     }
     T *get() const { return ptr_; }
     size_t size() const { return n_; }
@@ -125,6 +140,8 @@ class PinnedArray {
   private:
     T *ptr_ = nullptr;
     size_t n_ = 0;
+    hipStream_t stream_ = nullptr;
+    bool cached_ = false;
 };
 
 // Pinned host staging array from the host cache, for copies between host

@@ -14,14 +14,18 @@
 //    event has already completed, so reuse is ordered after every earlier use
 //    whatever stream takes the block;
 //  - pinned host blocks (for small copies between host tables and the
-//    device, which would otherwise be pageable and synchronous) work the
-//    same way, except that the host waits for the event before reuse;
-//  - when the free lists exceed a limit (a quarter of device memory, 4 GiB
-//    of pinned memory) the largest blocks go back to HIP; a failed
-//    allocation returns every cached block and tries once more.
+//    device, which would otherwise be pageable and synchronous, and for the
+//    host block store of a streamed graph) work the same way, except that
+//    the host waits for the event before reuse;
+//  - when the free lists exceed a limit (a quarter of device memory; for
+//    pinned memory an eighth of physical memory, within 4 - 64 GiB) the
+//    largest blocks go back to HIP; a failed allocation returns every
+//    cached block and tries once more.
 //
 // While a caller's allocator hook is installed, new device allocations go
 // through it instead; blocks the cache handed out still come back to it.
+#include <unistd.h>
+
 #include <algorithm>
 #include <map>
 #include <memory>
@@ -114,7 +118,11 @@ Cache &host_cache() {
     static std::once_flag once;
     std::call_once(once, [] {
         g_host_cache.host = true;
-        g_host_cache.limit = size_t(4) << 30;
+        // room for a streamed graph's block store between calls: an eighth
+        // of physical memory, at least 4 GiB and at most 64 GiB
+        const long pages = sysconf(_SC_PHYS_PAGES), psz = sysconf(_SC_PAGE_SIZE);
+        const size_t phys = pages > 0 && psz > 0 ? static_cast<size_t>(pages) * static_cast<size_t>(psz) : 0;
+        g_host_cache.limit = std::clamp(phys / 8, size_t(4) << 30, size_t(64) << 30);
     });
     return g_host_cache;
 }

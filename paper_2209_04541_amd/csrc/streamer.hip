@@ -53,7 +53,7 @@ uint64_t chunk_bytes(const BlockInfo &b, int orient) {
 void move_blocks_to_host(pgabb_graph *g) {
     if (g->blocks_on_host) return;
     hipStream_t s = g->stream;
-    g->host_arena.reset(static_cast<size_t>(g->arena_words));
+    g->host_arena.reset(static_cast<size_t>(g->arena_words), s, true);
     if (g->arena_words)
         PGABB_HIP(hipMemcpyAsync(g->host_arena.get(), g->arena.get(), sizeof(int32_t) * g->arena_words,
                                  hipMemcpyDeviceToHost, s));
