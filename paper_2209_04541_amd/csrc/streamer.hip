@@ -20,6 +20,15 @@
 // one of several compute streams once its copies are done; windows on
 // different streams overlap, and the copies of later windows overlap earlier
 // launches.
+//
+// A graph partitioned on the device reaches its first streamed count with
+// the blocks still in the device arena.  Outside the hybrid mode the count
+// moves them to the host store itself, block by block in the order the tasks
+// first use them, on a stream of its own; each block's copy back waits only
+// for that block's move, so the first windows start after a small part of
+// the store has crossed and the moves overlap the copies back (the other
+// direction of the link) and the launches.  The arena is released once the
+// count ends, leaving the same host store as a move before the count.
 #include <algorithm>
 #include <chrono>
 #include <list>
@@ -134,7 +143,10 @@ std::vector<int32_t> locality_order(const pgabb_graph *g, uint64_t cap, int orie
 }
 
 uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
-    move_blocks_to_host(g);
+    const bool hybrid = (opt.flags & PGABB_OPT_HYBRID) != 0;
+    // host threads read the store directly: it must be whole before they start
+    if (hybrid) move_blocks_to_host(g);
+    const bool moving = !g->blocks_on_host;  // moved below, overlapping the count
     hipStream_t s = g->stream;
     const int32_t T = static_cast<int32_t>(g->tasks.size());
     const int32_t nblk = static_cast<int32_t>(g->blocks.size());
@@ -208,7 +220,6 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     // A window is cut when its blocks would exceed the cap or when it would
     // copy more than about an eighth of all block bytes: the first launch
     // starts after a short copy, and later copies overlap earlier launches.
-    const bool hybrid = (opt.flags & PGABB_OPT_HYBRID) != 0;
     // in the hybrid mode windows hold at most 1/32 of the tasks, so the
     // device claims work in steps small enough for the two sides to meet
     // near the balance point
@@ -221,6 +232,24 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     std::vector<int32_t> order(T);
     for (int32_t t = 0; t < T; ++t) order[t] = t;
     if (total_bytes > cap) order = locality_order(g, cap, orient);
+
+    // ---- the move to the host store, queued in full before the first
+    // window: every block's chunk in order of first use (moved[b] marks its
+    // end), then the arena's words outside the chunks
+    hipStream_t move_s = nullptr;
+    hipEvent_t arena_ready = nullptr;
+    std::vector<hipEvent_t> moved(nblk, nullptr);
+    auto end_moves = [&]() noexcept {
+        if (move_s) (void)hipStreamSynchronize(move_s);
+        for (auto &e : moved) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+        if (arena_ready) (void)hipEventDestroy(arena_ready);
+        if (move_s) (void)hipStreamDestroy(move_s);
+        move_s = nullptr;
+        arena_ready = nullptr;
+    };
 
     uint64_t h2d = 0;
     int32_t next_task = 0;  // position in `order`: the device takes [0, next_task)
@@ -313,6 +342,39 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     };
 
     try {
+        if (moving) {
+            g->host_arena.reset(static_cast<size_t>(g->arena_words), s, true);
+            PGABB_HIP(hipStreamCreateWithFlags(&move_s, hipStreamNonBlocking));
+            PGABB_HIP(hipEventCreateWithFlags(&arena_ready, hipEventDisableTiming));
+            PGABB_HIP(hipEventRecord(arena_ready, s));  // the arena was written on the graph's stream
+            PGABB_HIP(hipStreamWaitEvent(move_s, arena_ready, 0));
+            int32_t *harena = g->host_arena.get();
+            const int32_t *darena = g->arena.get();
+            auto move_words = [&](int64_t lo, int64_t hi) {
+                if (hi > lo)
+                    PGABB_HIP(hipMemcpyAsync(harena + lo, darena + lo, sizeof(int32_t) * static_cast<size_t>(hi - lo),
+                                             hipMemcpyDeviceToHost, move_s));
+            };
+            auto move_block = [&](int32_t b) {
+                if (moved[b]) return;
+                move_words(g->blocks[b].chunk_off, g->blocks[b].chunk_off + g->blocks[b].chunk_len);
+                PGABB_HIP(hipEventCreateWithFlags(&moved[b], hipEventDisableTiming));
+                PGABB_HIP(hipEventRecord(moved[b], move_s));
+            };
+            for (int32_t q = 0; q < T; ++q)
+                for (int32_t b : {g->tasks[order[q]].bij, g->tasks[order[q]].bik, g->tasks[order[q]].bjk})
+                    move_block(b);
+            for (int32_t b = 0; b < nblk; ++b) move_block(b);
+            std::vector<std::pair<int64_t, int64_t>> chunks;
+            for (const BlockInfo &bi : g->blocks) chunks.emplace_back(bi.chunk_off, bi.chunk_off + bi.chunk_len);
+            std::sort(chunks.begin(), chunks.end());
+            int64_t at = 0;
+            for (const auto &c : chunks) {
+                move_words(at, c.first);
+                at = std::max(at, c.second);
+            }
+            move_words(at, g->arena_words);
+        }
         for (;;) {
             // in the hybrid mode at most one window per stream is in flight,
             // so the device claims tasks only as fast as it counts them
@@ -413,6 +475,7 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
             for (int32_t b : loads) {
                 const BlockInfo &bi = g->blocks[b];
                 const size_t bytes = static_cast<size_t>(bi.walk_hi(orient) - bi.walk_lo(orient)) * sizeof(int32_t);
+                if (moving) PGABB_HIP(hipStreamWaitEvent(copy_s, moved[b], 0));
                 PGABB_HIP(hipMemcpyAsync(pool.get() + where[b], g->host_arena.get() + bi.walk_lo(orient), bytes,
                                          hipMemcpyHostToDevice, copy_s));
                 h2d += bytes;
@@ -474,6 +537,12 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         for (auto &th : host) th.join();
         for (auto x : cs) PGABB_HIP(hipStreamSynchronize(x));
         PGABB_HIP(hipStreamSynchronize(copy_s));
+        if (moving) {
+            PGABB_HIP(hipStreamSynchronize(move_s));
+            end_moves();
+            g->arena.release();
+            g->blocks_on_host = true;
+        }
         double kms = 0;
         for (size_t q = 0; q < kstart.size(); ++q) {
             float t = 0;
@@ -496,6 +565,10 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
         stop_host();
         for (auto x : cs) (void)hipStreamSynchronize(x);
         (void)hipStreamSynchronize(copy_s);
+        if (moving && !g->blocks_on_host) {  // the blocks stay in the device arena
+            end_moves();
+            g->host_arena.release();
+        }
         for (auto e : copied) (void)hipEventDestroy(e);
         for (auto e : done) (void)hipEventDestroy(e);
         for (auto e : kstart) (void)hipEventDestroy(e);
