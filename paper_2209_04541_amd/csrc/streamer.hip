@@ -23,10 +23,11 @@
 //
 // A graph partitioned on the device reaches its first streamed count with
 // the blocks still in the device arena.  Outside the hybrid mode the count
-// moves them to the host store itself, block by block in the order the tasks
-// first use them, on a stream of its own; each block's copy back waits only
-// for that block's move, so the first windows start after a small part of
-// the store has crossed and the moves overlap the copies back (the other
+// moves them to the host store itself, on a stream of its own: first the
+// part of each block its walk reads, block by block in the order the tasks
+// first use them, then the rest of the arena.  Each block's copy back waits
+// only for that block's move, so the first windows start after a small part
+// of the store has crossed and the moves overlap the copies back (the other
 // direction of the link) and the launches.  The arena is released once the
 // count ends, leaving the same host store as a move before the count.
 #include <algorithm>
@@ -234,8 +235,8 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
     if (total_bytes > cap) order = locality_order(g, cap, orient);
 
     // ---- the move to the host store, queued in full before the first
-    // window: every block's chunk in order of first use (moved[b] marks its
-    // end), then the arena's words outside the chunks
+    // window: the walked part of every block's chunk in order of first use
+    // (moved[b] marks its end), then the arena's other words
     hipStream_t move_s = nullptr;
     hipEvent_t arena_ready = nullptr;
     std::vector<hipEvent_t> moved(nblk, nullptr);
@@ -355,9 +356,10 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                     PGABB_HIP(hipMemcpyAsync(harena + lo, darena + lo, sizeof(int32_t) * static_cast<size_t>(hi - lo),
                                              hipMemcpyDeviceToHost, move_s));
             };
+            // the part of the chunk this count's walk reads comes first
             auto move_block = [&](int32_t b) {
                 if (moved[b]) return;
-                move_words(g->blocks[b].chunk_off, g->blocks[b].chunk_off + g->blocks[b].chunk_len);
+                move_words(g->blocks[b].walk_lo(orient), g->blocks[b].walk_hi(orient));
                 PGABB_HIP(hipEventCreateWithFlags(&moved[b], hipEventDisableTiming));
                 PGABB_HIP(hipEventRecord(moved[b], move_s));
             };
@@ -365,11 +367,12 @@ uint64_t count_streamed(pgabb_graph *g, const pgabb_tc_options &opt) {
                 for (int32_t b : {g->tasks[order[q]].bij, g->tasks[order[q]].bik, g->tasks[order[q]].bjk})
                     move_block(b);
             for (int32_t b = 0; b < nblk; ++b) move_block(b);
-            std::vector<std::pair<int64_t, int64_t>> chunks;
-            for (const BlockInfo &bi : g->blocks) chunks.emplace_back(bi.chunk_off, bi.chunk_off + bi.chunk_len);
-            std::sort(chunks.begin(), chunks.end());
+            // then every word outside the walked parts
+            std::vector<std::pair<int64_t, int64_t>> walked;
+            for (const BlockInfo &bi : g->blocks) walked.emplace_back(bi.walk_lo(orient), bi.walk_hi(orient));
+            std::sort(walked.begin(), walked.end());
             int64_t at = 0;
-            for (const auto &c : chunks) {
+            for (const auto &c : walked) {
                 move_words(at, c.first);
                 at = std::max(at, c.second);
             }
