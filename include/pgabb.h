@@ -587,7 +587,11 @@ void pgabb_batch_destroy(pgabb_batch *b);
  * ones in.
  *   device_budget_bytes : bound on the device bytes held by admitted requests
  *   opts                : counting options (NULL = defaults); num_streams is
- *                         the number of builders (0 = 2, at most 8)
+ *                         the number of builders (0 = 2, at most 8); p is
+ *                         the grid each request is partitioned with (0 =
+ *                         by size: 8 for requests of at least 2^18 pairs,
+ *                         else 1; at most 64, EINVAL outside [0, 64]) and
+ *                         cut_mode its cuts (Section 4.3)
  */
 typedef struct pgabb_server pgabb_server;
 

@@ -87,6 +87,12 @@ def test_server_calls_reject_null():
     assert L.pgabb_server_times(None, 1, ctypes.byref(ts), ctypes.byref(td)) == P.EINVAL
     assert L.pgabb_server_create(0, None, None) == P.EINVAL
     assert L.pgabb_server_submit(None, 1, 0, None, None, None) == P.EINVAL
+    # the requests' grid is checked when the server is created
+    h = ctypes.c_void_p()
+    for bad in (-1, 65):
+        o = P.options(p=bad)
+        assert L.pgabb_server_create(1 << 30, ctypes.byref(o), ctypes.byref(h)) == P.EINVAL
+        assert not h.value
 
 
 def test_options_struct_names_the_grid():

@@ -1,6 +1,7 @@
 """GPU parity of the batched form (one persistent, graph-captured launch over
 many graphs) and of the continuous-batching server, against the CPU oracle.
 """
+import functools
 import json
 import math
 import os
@@ -124,6 +125,25 @@ def test_server_alone_equals_mix(borrow):
         assert srv.launches() >= 2
     assert alone == want[:8]
     assert mix == want
+
+
+@functools.lru_cache(maxsize=1)
+def _grid_requests():
+    reqs = _rmat_requests(12, seed0=700)
+    return reqs, [oracle.tc(*g) for g in reqs]
+
+
+@pytest.mark.parametrize("grid", [(1, P.CUT_NNZ), (3, P.CUT_UNIFORM), (8, P.CUT_NNZ)])
+def test_server_fixed_grid(grid):
+    """Requests partitioned with a grid the options fix (by default requests
+    of at least 2^18 pairs get 8 x 8 blocks and smaller ones one block):
+    every result still equals the oracle's count."""
+    p, cut = grid
+    reqs, want = _grid_requests()
+    say("server grid", p, "cut", cut, "requests", len(reqs))
+    with P.Server(8 << 30, p=p, cut_mode=cut) as srv:
+        assert _wait(srv, [srv.submit(*g) for g in reqs]) == want
+        srv.drain()
 
 
 def test_server_small_budget_and_rejection():
