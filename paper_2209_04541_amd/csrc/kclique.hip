@@ -13,14 +13,16 @@
 // A_ik[a] and A_il[a] (one list when k = l) in an open-addressing hash table
 // in LDS.  For each b its lanes look the entries of A_jk[b] and A_jl[b] up in
 // the table and mark the ones found (C and D) by setting the stored key's top
-// bit; then, for the marked keys of stripe k (C), they walk A_kl[c]
-// flattened over the lanes and count the entries whose key is marked (in D),
-// and finally clear the marks.  Blocks hold column ids local to their stripe,
-// so when k < l the ids of stripe l enter the table shifted by the width of
-// stripe k: keys of A_ik[a] lie below that width and keys of A_il[a] above
-// it, and an entry of A_kl[c] (stripe l, shifted too) can only match a key
-// of A_il[a].  Items whose staged rows hold more than kStageCap entries go to
-// a kernel with one thread per (item, b) and plain merges.
+// bit and the slot's bit in a bitmap of C or of D; then the lists A_kl[c] of
+// the marked keys of stripe k (C), found from C's bitmap and gathered up to
+// 64 at a time, are walked flattened over the lanes, counting the entries
+// whose key is marked (in D); the bitmaps lead the clearing of the marks.
+// A b with no marks costs its look-ups only.  Blocks hold column ids local
+// to their stripe, so when k < l the ids of stripe l enter the table shifted
+// by the width of stripe k: keys of A_ik[a] lie below that width and keys of
+// A_il[a] above it, and an entry of A_kl[c] (stripe l, shifted too) can only
+// match a key of A_il[a].  Items whose staged rows hold more than kStageCap
+// entries go to a kernel with one thread per (item, b) and plain merges.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +51,19 @@ constexpr int kQuadUnroll = 2;   // walk chunks in flight
 // rows of high-degree vertices then spread over several waves.
 constexpr int kQuadSpan = 8;
 constexpr int kQuadParts = kSplitV / kQuadSpan;
+// Work counters: the items are cut into chunks of `grab` items, chunk c
+// belongs to counter c mod kQuadQueues, and a wave takes chunks from the
+// counter of its workgroup's XCD (workgroups are dealt round-robin to the 8
+// XCDs), moving on to the next counter when that one runs dry.  At p = 8
+// most items end after a few loads (a row of A_ij with no entries in stripe
+// k or l), and one counter taking one item per grab serialised the launch
+// on the grabs' round trips; at p = 1 the items are heavy and large chunks
+// unbalance the waves.  So the chunk is sized per launch for about
+// kQuadGrabsPerWave grabs per wave, within [kQuadGrabMin, kQuadGrabMax].
+constexpr int kQuadQueues = 8;
+constexpr int64_t kQuadGrabsPerWave = 256;
+constexpr int64_t kQuadGrabMin = 4;
+constexpr int64_t kQuadGrabMax = 64;
 // A marked key has its top bit set.  Vertex ids are below 2^31 - 1, so a
 // marked key is never -1, the empty slot.
 constexpr int32_t kMarkBit = INT32_MIN;
@@ -80,10 +95,12 @@ __device__ __forceinline__ int32_t quad_of(gptr<int64_t> pre, int32_t nq, int64_
 }
 
 // Marks the entries of the sorted list x[0, n) found in the table, each
-// looked up as its id plus `add` (ids above top cannot be there).  Every
-// lane of the wave calls this.
-__device__ __forceinline__ void quad_mark(int32_t *H, int shift, uint32_t tmask, gptr<int32_t> x, int32_t n,
-                                          int32_t top, int32_t add, int lane) {
+// looked up as its id plus `add` (ids above top cannot be there), sets the
+// marked slots' bits in `bits`, and returns how many it marked (the same on
+// every lane).  Every lane of the wave calls this.
+__device__ __forceinline__ int32_t quad_mark(int32_t *H, uint32_t *bits, int shift, uint32_t tmask, gptr<int32_t> x,
+                                             int32_t n, int32_t top, int32_t add, int lane) {
+    int32_t marked = 0;
     for (int32_t x0 = 0; x0 < n; x0 += kWave) {
         const int32_t i = x0 + lane;
         const int32_t u = i < n ? x[i] : -1;
@@ -92,12 +109,18 @@ __device__ __forceinline__ void quad_mark(int32_t *H, int shift, uint32_t tmask,
         uint32_t h = hash_slot(v, shift, tmask);
         while (__ballot(go) != 0) {
             const int32_t sv = H[h];
-            if (go && sv == v) H[h] = v | kMarkBit;
+            const bool hit = go && sv == v;
+            if (hit) {
+                H[h] = v | kMarkBit;
+                atomicOr(&bits[h >> 5], 1u << (h & 31));
+            }
+            marked += __popcll(__ballot(hit));
             go = go && sv != -1 && (sv & kKeyBits) != v;
             h = (h + 1) & tmask;
         }
         if (__ballot(u > top) != 0) break;  // the rest of the list is above top too
     }
+    return marked;
 }
 
 // Staged items: one wave per item from a work counter.  Counts go to the
@@ -107,122 +130,181 @@ __global__ __launch_bounds__(kCliqueWaves *kWave) void k_quad_items(const QuadDe
                                                                      const int64_t *__restrict__ item_pre,
                                                                      int32_t nq,
                                                                      unsigned long long *__restrict__ next,
+                                                                     int64_t grab,
                                                                      unsigned long long *__restrict__ counts) {
     __shared__ int32_t s_table[kCliqueWaves][1 << kTableLg];
     __shared__ int32_t s_own[kCliqueWaves][kQuadUnroll * kWave];
+    __shared__ int32_t s_gather[kCliqueWaves][2][kWave];  // walked lists: start, length
+    // slots marked in C and in D, one bit each (2^kTableLg / 32 words)
+    __shared__ uint32_t s_bits[kCliqueWaves][2][(1 << kTableLg) / 32];
     int32_t *H = s_table[threadIdx.x / kWave];
     int32_t *own = s_own[threadIdx.x / kWave];
+    int32_t *gpb = s_gather[threadIdx.x / kWave][0];
+    int32_t *glen = s_gather[threadIdx.x / kWave][1];
+    uint32_t *bits_c = s_bits[threadIdx.x / kWave][0];
+    uint32_t *bits_d = s_bits[threadIdx.x / kWave][1];
     const int lane = lane_id();
 #pragma unroll
     for (int q = 0; q < kQuadUnroll; ++q) own[q * kWave + lane] = 0;
+    for (int q = lane; q < (1 << kTableLg) / 32; q += kWave) bits_c[q] = bits_d[q] = 0u;
     wave_lds_sync();
     const gptr<int64_t> ip = as_global(item_pre);
     const int64_t nitems = ip[nq];
     unsigned long long acc = 0;  // this lane's share of the current list's count
     int32_t acc_slot = -1;
-    for (;;) {
-        unsigned long long q0 = 0;
-        if (lane == 0) q0 = atomicAdd(next, 1ull);
-        q0 = shfl_t(q0, 0);
-        if (q0 >= static_cast<unsigned long long>(nitems)) break;
-        const int64_t q = static_cast<int64_t>(q0);
-        const int32_t t = __builtin_amdgcn_readfirstlane(quad_of(ip, nq, q));
-        const QuadDesc &Q = quads[t];
-        const int64_t r = (q - ip[t]) / kQuadParts;  // row item, and its part
-        const int32_t part = static_cast<int32_t>((q - ip[t]) - r * kQuadParts);
-        const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * r;
-        const int32_t a = it[0];
-        const int32_t eb = it[1] + part * kQuadSpan, ee = min(eb + kQuadSpan, it[2]);
-        if (eb >= ee) continue;
-        const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
-        const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
-        const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
-        if (dk == 0 || dl == 0 || !quad_staged(dk, dl, Q.same)) continue;  // none, or the long kernel's
-        if (Q.slot != acc_slot) {  // counts gather per 4-list (its slot among all the count's lists)
-            const unsigned long long w = wave_sum(acc);
-            if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
-            acc = 0;
-            acc_slot = Q.slot;
+    const int64_t nchunks = (nitems + grab - 1) / grab;
+    int32_t qi = static_cast<int32_t>(blockIdx.x % kQuadQueues);
+    for (int32_t dry = 0; dry < kQuadQueues;) {
+        unsigned long long k = 0;
+        if (lane == 0) k = atomicAdd(&next[qi], 1ull);
+        k = shfl_t(k, 0);
+        const int64_t c = static_cast<int64_t>(k) * kQuadQueues + qi;
+        if (c >= nchunks) {  // this counter is dry: the next one
+            qi = (qi + 1) % kQuadQueues;
+            ++dry;
+            continue;
         }
-        const gptr<int32_t> ikc = as_global(Q.ik.col), ilc = as_global(Q.il.col);
-        // table of 2^lg >= 4 x the staged entries slots (64 .. 2^kTableLg)
-        const int32_t nst = Q.same ? dk : dk + dl;
-        int lg = 6;
-        while ((1 << lg) < 4 * nst && lg < kTableLg) ++lg;
-        const int32_t T = 1 << lg;
-        const uint32_t tmask = static_cast<uint32_t>(T - 1);
-        const int shift = 24 - lg;
-        for (int32_t s0 = lane; s0 < T; s0 += kWave) H[s0] = -1;
-        wave_lds_sync();
-        for (int32_t x = lane; x < nst; x += kWave) {
-            const int32_t v = x < dk ? ikc[k0 + x] : ilc[l0 + x - dk] + Q.lshift;
-            uint32_t h = hash_slot(v, shift, tmask);
-            while (atomicCAS(&H[h], -1, v) != -1) h = (h + 1) & tmask;
-        }
-        wave_lds_sync();
-        const int32_t topk = ikc[k0 + dk - 1], topl = ilc[l0 + dl - 1];
-        const int32_t lshift = Q.lshift;
-        const gptr<int32_t> ijc = as_global(Q.ij.col);
-        const gptr<int32_t> jkr = as_global(Q.jk.rptr), jkc = as_global(Q.jk.col);
-        const gptr<int32_t> jlr = as_global(Q.jl.rptr), jlc = as_global(Q.jl.col);
-        const gptr<int32_t> klr = as_global(Q.kl.rptr), klc = as_global(Q.kl.col);
-        uint32_t cnt = 0;
-        for (int32_t e = eb; e < ee; ++e) {
-            const int32_t b = ijc[e];
-            const int32_t bk0 = jkr[b], dbk = jkr[b + 1] - bk0;
-            const int32_t bl0 = jlr[b], dbl = jlr[b + 1] - bl0;
-            if (dbk == 0 || dbl == 0) continue;
-            quad_mark(H, shift, tmask, jkc + bk0, dbk, topk, 0, lane);  // C (and D when k = l)
-            if (!Q.same) quad_mark(H, shift, tmask, jlc + bl0, dbl, topl, Q.lshift, lane);  // D
+        dry = 0;
+        const int64_t g0 = c * grab;
+        const int64_t gend = min(g0 + grab, nitems);
+        int32_t t = __builtin_amdgcn_readfirstlane(quad_of(ip, nq, g0));
+        for (int64_t q = g0; q < gend; ++q) {
+            while (ip[t + 1] <= q) ++t;  // the next non-empty 4-list (ip[nq] = nitems > q)
+            t = __builtin_amdgcn_readfirstlane(t);
+            const QuadDesc &Q = quads[t];
+            const int64_t r = (q - ip[t]) / kQuadParts;  // row item, and its part
+            const int32_t part = static_cast<int32_t>((q - ip[t]) - r * kQuadParts);
+            const gptr<int32_t> it = as_global(Q.ij.items) + kItemWords * r;
+            const int32_t a = it[0];
+            const int32_t eb = it[1] + part * kQuadSpan, ee = min(eb + kQuadSpan, it[2]);
+            if (eb >= ee) continue;
+            const gptr<int32_t> ikr = as_global(Q.ik.rptr), ilr = as_global(Q.il.rptr);
+            const int32_t k0 = ikr[a], dk = ikr[a + 1] - k0;
+            const int32_t l0 = ilr[a], dl = ilr[a + 1] - l0;
+            if (dk == 0 || dl == 0 || !quad_staged(dk, dl, Q.same)) continue;  // none, or the long kernel's
+            if (Q.slot != acc_slot) {  // counts gather per 4-list (its slot among all the count's lists)
+                const unsigned long long w = wave_sum(acc);
+                if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
+                acc = 0;
+                acc_slot = Q.slot;
+            }
+            const gptr<int32_t> ikc = as_global(Q.ik.col), ilc = as_global(Q.il.col);
+            // table of 2^lg >= 4 x the staged entries slots (64 .. 2^kTableLg)
+            const int32_t nst = Q.same ? dk : dk + dl;
+            int lg = 6;
+            while ((1 << lg) < 4 * nst && lg < kTableLg) ++lg;
+            const int32_t T = 1 << lg;
+            const uint32_t tmask = static_cast<uint32_t>(T - 1);
+            const int shift = 24 - lg;
+            for (int32_t s0 = lane; s0 < T; s0 += kWave) H[s0] = -1;
             wave_lds_sync();
-            // walk A_kl[c] for the marked keys c of stripe k, 64 slots at a time
-            for (int32_t s0 = 0; s0 < T; s0 += kWave) {
-                const int32_t sv = H[s0 + lane];
-                const bool in = sv < -1 && (sv & kKeyBits) <= topk;
-                if (__ballot(in) == 0) continue;
-                int32_t pb = 0, len = 0;
-                if (in) {
-                    const int32_t c = sv & kKeyBits;
-                    pb = klr[c];
-                    len = klr[c + 1] - pb;
-                }
-                const int32_t incl = wave_inclusive_scan(len);
-                const int32_t pre = incl - len;
-                const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-                if (total == 0) continue;
-                uint32_t carry = 0;
-                int32_t w[kQuadUnroll];
-                walk_load<kQuadUnroll>(w, 0, total, pre, len, pb, carry, own, klc, lane);
-                for (int32_t base = 0; base < total; base += kQuadUnroll * kWave) {
-                    int32_t wn[kQuadUnroll];
-                    walk_load<kQuadUnroll>(wn, base + kQuadUnroll * kWave, total, pre, len, pb, carry, own, klc,
-                                           lane);
+            for (int32_t x = lane; x < nst; x += kWave) {
+                const int32_t v = x < dk ? ikc[k0 + x] : ilc[l0 + x - dk] + Q.lshift;
+                uint32_t h = hash_slot(v, shift, tmask);
+                while (atomicCAS(&H[h], -1, v) != -1) h = (h + 1) & tmask;
+            }
+            wave_lds_sync();
+            const int32_t topk = ikc[k0 + dk - 1], topl = ilc[l0 + dl - 1];
+            const int32_t lshift = Q.lshift;
+            const gptr<int32_t> ijc = as_global(Q.ij.col);
+            const gptr<int32_t> jkr = as_global(Q.jk.rptr), jkc = as_global(Q.jk.col);
+            const gptr<int32_t> jlr = as_global(Q.jl.rptr), jlc = as_global(Q.jl.col);
+            const gptr<int32_t> klr = as_global(Q.kl.rptr), klc = as_global(Q.kl.col);
+            uint32_t cnt = 0;
+            for (int32_t e = eb; e < ee; ++e) {
+                const int32_t b = ijc[e];
+                const int32_t bk0 = jkr[b], dbk = jkr[b + 1] - bk0;
+                const int32_t bl0 = jlr[b], dbl = jlr[b + 1] - bl0;
+                if (dbk == 0 || dbl == 0) continue;
+                const int32_t nc = quad_mark(H, bits_c, shift, tmask, jkc + bk0, dbk, topk, 0, lane);  // C (and D when k = l)
+                const int32_t nd =
+                    Q.same ? nc : quad_mark(H, bits_d, shift, tmask, jlc + bl0, dbl, topl, Q.lshift, lane);  // D
+                if (nc + nd == 0) continue;  // nothing marked: the table is as staged
+                wave_lds_sync();
+                // walk A_kl[c] for the marked keys c of stripe k: the marked slots
+                // are gathered, 64 slots of the table at a time, into lists of at
+                // most one per lane, and each full set of 64 lists (and the last)
+                // is walked as one flattened sequence; only when a pair c < d can
+                // be there (C and D non-empty; two marks when they are one set)
+                const bool pairs = nc > 0 && nd > 0 && (!Q.same || nc >= 2);
+                auto walk_gathered = [&](int32_t ng) {
+                    wave_lds_sync();  // the gathered lists are written
+                    const int32_t pb = lane < ng ? gpb[lane] : 0;
+                    const int32_t len = lane < ng ? glen[lane] : 0;
+                    wave_lds_sync();  // read before the next lists are gathered
+                    const int32_t incl = wave_inclusive_scan(len);
+                    const int32_t pre = incl - len;
+                    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                    if (total == 0) return;
+                    uint32_t carry = 0;
+                    int32_t w[kQuadUnroll];
+                    walk_load<kQuadUnroll>(w, 0, total, pre, len, pb, carry, own, klc, lane);
+                    for (int32_t base = 0; base < total; base += kQuadUnroll * kWave) {
+                        int32_t wn[kQuadUnroll];
+                        walk_load<kQuadUnroll>(wn, base + kQuadUnroll * kWave, total, pre, len, pb, carry, own, klc,
+                                               lane);
 #pragma unroll
-                    for (int u = 0; u < kQuadUnroll; ++u) {
-                        bool go = w[u] >= 0 && w[u] <= topl;
-                        const int32_t y = w[u] + lshift;  // its key in the table
-                        uint32_t h = hash_slot(y, shift, tmask);
-                        uint32_t hit = 0;
-                        while (__ballot(go) != 0) {
-                            const int32_t hv = H[h];
-                            hit |= (go && hv == (y | kMarkBit)) ? 1u : 0u;
-                            go = go && hv != -1 && (hv & kKeyBits) != y;
-                            h = (h + 1) & tmask;
+                        for (int u = 0; u < kQuadUnroll; ++u) {
+                            bool go = w[u] >= 0 && w[u] <= topl;
+                            const int32_t y = w[u] + lshift;  // its key in the table
+                            uint32_t h = hash_slot(y, shift, tmask);
+                            uint32_t hit = 0;
+                            while (__ballot(go) != 0) {
+                                const int32_t hv = H[h];
+                                hit |= (go && hv == (y | kMarkBit)) ? 1u : 0u;
+                                go = go && hv != -1 && (hv & kKeyBits) != y;
+                                h = (h + 1) & tmask;
+                            }
+                            cnt += hit;
+                            w[u] = wn[u];
                         }
-                        cnt += hit;
-                        w[u] = wn[u];
                     }
+                };
+                // gather: lane q takes word q of C's bitmap (the table has at most
+                // 2^kTableLg = 64 words of slots) and places its marked slots' lists
+                // after those of the lanes below it; 64 lists at most per walk
+                const int32_t nw = T >> 5;
+                int32_t ng = 0;  // lists gathered so far (the same on every lane)
+                uint32_t word = pairs && lane < nw ? bits_c[lane] : 0u;
+                for (;;) {
+                    const int32_t mine = __popc(word);
+                    const int32_t incl = wave_inclusive_scan(mine);
+                    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                    if (total == 0) break;
+                    int32_t at = ng + incl - mine;
+                    while (word != 0u && at < kWave) {
+                        const int32_t slot = (lane << 5) + __builtin_ctz(word);
+                        word &= word - 1u;
+                        const int32_t c = H[slot] & kKeyBits;
+                        const int32_t c0 = klr[c];
+                        gpb[at] = c0;
+                        glen[at] = klr[c + 1] - c0;
+                        ++at;
+                    }
+                    if (ng + total <= kWave) {
+                        ng += total;
+                        break;
+                    }
+                    walk_gathered(kWave);  // full: walk these, then place the rest
+                    ng = 0;
                 }
+                if (ng > 0) walk_gathered(ng);
+                wave_lds_sync();  // the walk's reads are done: clear the marks
+                if (lane < nw) {
+                    uint32_t mk = bits_c[lane] | bits_d[lane];
+                    while (mk != 0u) {
+                        const int32_t slot = (lane << 5) + __builtin_ctz(mk);
+                        mk &= mk - 1u;
+                        H[slot] &= kKeyBits;
+                    }
+                    bits_c[lane] = 0u;
+                    bits_d[lane] = 0u;
+                }
+                wave_lds_sync();
             }
-            wave_lds_sync();  // the walk's reads are done: clear the marks
-            for (int32_t s0 = lane; s0 < T; s0 += kWave) {
-                const int32_t sv = H[s0];
-                if (sv < -1) H[s0] = sv & kKeyBits;
-            }
-            wave_lds_sync();
+            acc += cnt;
+            wave_lds_sync();  // before the next item is staged
         }
-        acc += cnt;
-        wave_lds_sync();  // before the next item is staged
     }
     const unsigned long long w = wave_sum(acc);
     if (lane == 0 && w) atomicAdd(&counts[acc_slot], w);
@@ -343,7 +425,8 @@ BlockRef quad_ref(const BlockInfo &bi, const int32_t *base) {
 }
 
 // Counts the 4-lists lists[first, last) (their blocks at the given device
-// bases), adding to dcnt[slot]; dcnt[NQ] is the work counter.
+// bases), adding to dcnt[slot]; dcnt[NQ .. NQ + kQuadQueues) are the work
+// counters.
 void quad_launch(pgabb_graph *g, const std::vector<std::array<int32_t, 4>> &lists, int32_t first, int32_t last,
                  const std::vector<const int32_t *> &base, unsigned long long *dcnt, int32_t NQ, double &kernel_ms,
                  int64_t &launches) {
@@ -377,7 +460,7 @@ void quad_launch(pgabb_graph *g, const std::vector<std::array<int32_t, 4>> &list
     DArray<int64_t> dpre(static_cast<size_t>(W) + 1, s);
     PGABB_HIP(hipMemcpyAsync(dq.get(), hq.get(), hq.bytes(), hipMemcpyHostToDevice, s));
     PGABB_HIP(hipMemcpyAsync(dpre.get(), hpre.get(), hpre.bytes(), hipMemcpyHostToDevice, s));
-    k_zero_u64q<<<1, 64, 0, s>>>(dcnt + NQ, 1);  // the work counter
+    k_zero_u64q<<<1, 64, 0, s>>>(dcnt + NQ, kQuadQueues);  // the work counters
     // some row too long to stage (with p > 1, two rows of a 4-list may
     // share the table)
     const bool long_rows = (p == 1 ? max_row : 2 * max_row) > kStageCap;
@@ -385,7 +468,9 @@ void quad_launch(pgabb_graph *g, const std::vector<std::array<int32_t, 4>> &list
     tm.start(s);
     const unsigned grid =
         static_cast<unsigned>(std::min<int64_t>(256 * 4, (nitems + kCliqueWaves - 1) / kCliqueWaves));
-    k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), W, dcnt + NQ, dcnt);
+    int64_t grab = kQuadGrabMin;
+    while (grab < kQuadGrabMax && nitems / (grab * 2) >= kQuadGrabsPerWave * grid * kCliqueWaves) grab *= 2;
+    k_quad_items<<<grid, kCliqueWaves * kWave, 0, s>>>(dq.get(), dpre.get(), W, dcnt + NQ, grab, dcnt);
     if (long_rows)
         k_quad_long<<<std::min<unsigned>(grid_for(nitems * kQuadSpan, kQB), 256u * 16u), kQB, 0, s>>>(
             dq.get(), dpre.get(), W, dcnt);
@@ -435,8 +520,9 @@ uint64_t four_cliques(pgabb_graph *g, uint64_t device_cap_bytes) {
     uint64_t result = 0;
     if (NQ > 0) {
         const int32_t nblk = static_cast<int32_t>(g->blocks.size());
-        DArray<unsigned long long> dcnt(static_cast<size_t>(NQ) + 1, s);  // counts, then the work counter
-        k_zero_u64q<<<std::min<unsigned>(grid_for(NQ + 1, 256), 1024u), 256, 0, s>>>(dcnt.get(), NQ + 1);
+        DArray<unsigned long long> dcnt(static_cast<size_t>(NQ) + kQuadQueues, s);  // counts, then the work counters
+        k_zero_u64q<<<std::min<unsigned>(grid_for(NQ + kQuadQueues, 256), 1024u), 256, 0, s>>>(dcnt.get(),
+                                                                                           NQ + kQuadQueues);
         PGABB_HIP(hipGetLastError());
         double kernel_ms = 0;
         int64_t launches = 0;
