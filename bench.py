@@ -644,7 +644,7 @@ def bench_batch(args):
 def bench_served(args):
     """A Poisson request trace against the continuous-batching server and
     against plain sequential launches (one request at a time, build then
-    count), on the same trace.  Requests arrive for `duration` seconds; an
+    count, with the grid the server would give it), on the same trace.  Requests arrive for `duration` seconds; an
     arrival that finds `max_outstanding` requests already waiting or running
     is shed (counted, not served), so an overloaded run measures capacity
     instead of an ever-growing queue.  Two traces: the configured rate, and
@@ -744,7 +744,8 @@ def bench_served(args):
             i = queue.pop(0)
             n, s, d, _, _ = pool[reqs[i]]
             with P.Graph(n, s, d) as g:
-                g.partition(1)
+                # the grid the server gives a request of this size
+                g.partition(8 if len(s) >= (1 << 18) else 1)
                 c = g.count()
             lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
             gg = gold.get(str(reqs[i]))
@@ -763,7 +764,8 @@ def bench_served(args):
                     "edge factor ~ U{8..32}, seed (5,r mod %d); %d GiB device budget, %d builders; arrivals "
                     "finding %d requests outstanding are shed" % (args.rate, args.duration, pool_size,
                                                                  args.budget_gb, args.builders, K),
-        "rate": args.rate, "duration_s": args.duration, "pool": pool_size, "max_outstanding": K})
+        "rate": args.rate, "duration_s": args.duration, "pool": pool_size, "max_outstanding": K,
+        "request_grid": "8x8 blocks from 2^18 input pairs, else one block (server and sequential alike)"})
     # roofline of the server's counting launches over the run: algorithmic
     # bytes (4 per walked entry, 16 per edge, as for one count) over their
     # summed device time
