@@ -508,8 +508,8 @@ def bench_ooc(args):
     import paper_2209_04541_amd as P
     from paper_2209_04541_amd import gen
     n, s, d = gen.rmat(24, 16, gen.seed(3, 0))
-    cap = args.cap_mb * (1 << 20) if args.cap_mb else args.cap_gb * (1 << 30)
-    cap_label = "%d MiB" % args.cap_mb if args.cap_mb else "%d GiB" % args.cap_gb
+    cap = args.cap_mb * (1 << 20) if args.cap_mb else int(args.cap_gb * 1e9)
+    cap_label = "%d MiB" % args.cap_mb if args.cap_mb else "%g GB" % args.cap_gb
     opts = P.options(kernel=args.kernel, device_cap_bytes=int(cap), stream_blocks=True)
 
     def cpu_sample():
@@ -924,7 +924,7 @@ def main():
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0)
-    ap.add_argument("--cap-gb", type=int, default=8)
+    ap.add_argument("--cap-gb", type=float, default=8.0, help="device cap in GB (10^9 bytes)")
     ap.add_argument("--cap-mb", type=int, default=0, help="device cap in MiB (overrides --cap-gb)")
     ap.add_argument("--host-edges", action="store_true",
                     help="hand the edge list over in pinned host memory (its copy is then in the step)")
