@@ -766,6 +766,11 @@ def bench_served(args):
                                                                  args.budget_gb, args.builders, K),
         "rate": args.rate, "duration_s": args.duration, "pool": pool_size, "max_outstanding": K,
         "request_grid": "8x8 blocks from 2^18 input pairs, else one block (server and sequential alike)"})
+    # a step of this line is one served request of the trace: ms_per_step is
+    # the trace's span over the requests served, with no warmup
+    out["steps"] = main["served"]
+    out["warmup"] = 0
+    out["step"] = "one served request"
     # roofline of the server's counting launches over the run: algorithmic
     # bytes (4 per walked entry, 16 per edge, as for one count) over their
     # summed device time
